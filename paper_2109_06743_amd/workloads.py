@@ -1,0 +1,170 @@
+"""Seeded synthetic workloads (initial conditions and run parameters).
+
+This module holds only the problem set-ups: analytic initial distributions
+sampled at cell centres, initial fields, grid extents, time steps.  It
+contains none of the solver's arithmetic (no sweeps, quadratures, fitting or
+field updates), so both the HIP path and the CPU reference can start from
+the same arrays.
+
+Set-ups (paper sections cited by name):
+* landau    - linear Landau damping (Sec. 3.1): f0 = (1 + a cos kx) e^{-v^2/2}/sqrt(2 pi)
+* twostream - two drifting Maxwellians at +-2.4, v_t 0.5, k 0.2 (a beam
+              variant of the two-stream set-up of Sec. 3.1)
+* gem       - Harris sheet with the GEM perturbation (Sec. 3.3)
+* tail      - Harris sheet plus background populations, guide field,
+              seeded random B_x noise (magnetotail set-up, Sec. 4.1)
+Units: electrostatic runs in omega_p^-1, lambda_D, v_t, m_e (Sec. 3.1);
+electromagnetic runs in Omega_i^-1, d_i, v_A, m_i, q_i, mu0 = k_B = 1 (Sec. 2.1).
+"""
+import math
+
+import numpy as np
+
+
+def _centres(lo, hi, n):
+    h = (hi - lo) / n
+    return lo + (np.arange(n) + 0.5) * h
+
+
+# ------------------------------------------------------------ 1X1V ------
+def landau(nx=64, nv=64, vmax=6.0, alpha=0.01, k=0.5, dt=0.1, steps=100, fit=False):
+    L = 2 * math.pi / k
+    cfg = dict(kind="1x1v", nx=nx, x_lo=-L / 2, x_hi=L / 2, nv=nv, v_lo=-vmax, v_hi=vmax,
+               q=-1.0, m=1.0, fit=fit, dt=dt, steps=steps, name=f"landau {nx}x{nv}")
+    x = _centres(cfg["x_lo"], cfg["x_hi"], nx)
+    v = _centres(-vmax, vmax, nv)
+    f = (1.0 + alpha * np.cos(k * x))[:, None] * (np.exp(-0.5 * v * v) / math.sqrt(2 * math.pi))[None, :]
+    return cfg, f
+
+
+def twostream(nx=256, nv=256, vmax=8.0, alpha=1e-3, k=0.2, vd=2.4, vt=0.5, dt=0.1, steps=500, fit=False):
+    L = 2 * math.pi / k
+    cfg = dict(kind="1x1v", nx=nx, x_lo=0.0, x_hi=L, nv=nv, v_lo=-vmax, v_hi=vmax,
+               q=-1.0, m=1.0, fit=fit, dt=dt, steps=steps, name=f"twostream {nx}x{nv}")
+    x = _centres(0.0, L, nx)
+    v = _centres(-vmax, vmax, nv)
+    g = lambda w: np.exp(-0.5 * (w / vt) ** 2) / (math.sqrt(2 * math.pi) * vt)
+    f = (1.0 + alpha * np.cos(k * x))[:, None] * (0.5 * (g(v - vd) + g(v + vd)))[None, :]
+    return cfg, f
+
+
+# ------------------------------------------------------------ 2X3V ------
+def _maxwellian_block(n, uz, T, m, v):
+    """Analytic isotropic Maxwellian n (m/2piT)^{3/2} exp(-m |v-u|^2/(2T)), u = (0,0,uz),
+    for arrays n, uz of shape [...]; returns [..., nvx, nvy, nvz]."""
+    vx, vy, vz = v
+    pre = n * (m / (2 * math.pi * T)) ** 1.5
+    ex = np.exp(-0.5 * m * vx * vx / T)[:, None, None] * np.exp(-0.5 * m * vy * vy / T)[None, :, None]
+    ez = np.exp(-0.5 * m * (vz[None, :] - np.asarray(uz)[..., None]) ** 2 / T)
+    return pre[..., None, None, None] * ex * ez[..., None, None, :]
+
+
+def _species(q, m, vmax, nv):
+    return dict(q=q, m=m, v_lo=[-vmax] * 3, v_hi=[vmax] * 3, nv=[nv] * 3)
+
+
+class Yee0:
+    """Initial Yee-grid fields (same placement as the solver's)."""
+
+    def __init__(self, nx, ny):
+        self.Ex = np.zeros((ny, nx)); self.Ey = np.zeros((ny + 1, nx)); self.Ez = np.zeros((ny, nx))
+        self.Bx = np.zeros((ny + 1, nx)); self.By = np.zeros((ny, nx)); self.Bz = np.zeros((ny + 1, nx))
+
+
+def gem(nx=256, ny=128, nv=16, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5.0, psi0=0.1,
+        ve_max=12.5, vi_max=5.0, dt=0.003, steps=200, fit=True, dtype=np.float32):
+    """GEM reconnection set-up (Sec. 3.3) on an nx x ny x nv^3 grid."""
+    Lx, Ly = 8 * math.pi, 4 * math.pi
+    Te = 0.5 / (1.0 + Ti_Te)
+    Ti = Ti_Te * Te
+    me = 1.0 / mass_ratio
+    sp = [_species(-1.0, me, ve_max, nv), _species(1.0, 1.0, vi_max, nv)]
+    cfg = dict(kind="2x3v", nx=nx, ny=ny, x_lo=-Lx / 2, x_hi=Lx / 2, y_lo=-Ly / 2, y_hi=Ly / 2,
+               c=c, species=sp, fit=fit, dt=dt, steps=steps,
+               name=f"gem {nx}x{ny}x{nv}^3 mi/me={mass_ratio:g}")
+    x = _centres(-Lx / 2, Lx / 2, nx)
+    y = _centres(-Ly / 2, Ly / 2, ny)
+    X, Y = np.meshgrid(x, y)          # [ny, nx]
+    n = 1.0 / np.cosh(Y / lam) ** 2 + nb
+    jz = (psi0 * ((2 * math.pi / Lx) ** 2 + (math.pi / Ly) ** 2)
+          * np.cos(2 * math.pi * X / Lx) * np.cos(math.pi * Y / Ly)
+          - (1.0 / lam) / np.cosh(Y / lam) ** 2)
+    uzi = jz * Ti / (n * (Ti + Te))
+    uze = -uzi * Te / Ti
+    f = []
+    for s, (uz, T) in zip(sp, ((uze, Te), (uzi, Ti))):
+        v = [_centres(s["v_lo"][d], s["v_hi"][d], s["nv"][d]) for d in range(3)]
+        f.append(_maxwellian_block(n, uz, T, s["m"], v).astype(dtype))
+    F = Yee0(nx, ny)
+    dx, dy = Lx / nx, Ly / ny
+    xc = -Lx / 2 + (np.arange(nx) + 0.5) * dx      # integer i
+    xf = -Lx / 2 + (np.arange(nx) + 1.0) * dx      # i + 1/2
+    yc = -Ly / 2 + (np.arange(ny) + 0.5) * dy      # integer j
+    yf = -Ly / 2 + np.arange(ny + 1) * dy          # j - 1/2 (walls included)
+    XF, YF = np.meshgrid(xc, yf)
+    F.Bx = np.tanh(YF / lam) - psi0 * (math.pi / Ly) * np.cos(2 * math.pi * XF / Lx) * np.sin(math.pi * YF / Ly)
+    XB, YB = np.meshgrid(xf, yc)
+    F.By = psi0 * (2 * math.pi / Lx) * np.sin(2 * math.pi * XB / Lx) * np.cos(math.pi * YB / Ly)
+    return cfg, f, F
+
+
+def tail(nx=1024, ny=512, nv=12, mass_ratio=100.0, c=30.0, lam=0.6, Ti_Te=3.0, Bg=0.1, noise=1e-4,
+         ve_max=20.0, vi_max=5.0, dt=0.0012, steps=20, fit=True, seed=0, dtype=np.float32):
+    """Magnetotail-like set-up (Sec. 4.1): Harris sheet carrying the current,
+    static background at n0/3 and T0/3, guide field -Bg, seeded noise on B_x."""
+    Lx, Ly = 120.0, 40.0
+    Te = 0.5 / (1.0 + Ti_Te)
+    Ti = Ti_Te * Te
+    me = 1.0 / mass_ratio
+    nbg = 1.0 / 3.0
+    sp = [_species(-1.0, me, ve_max, nv), _species(1.0, 1.0, vi_max, nv)]
+    cfg = dict(kind="2x3v", nx=nx, ny=ny, x_lo=-Lx / 2, x_hi=Lx / 2, y_lo=-Ly / 2, y_hi=Ly / 2,
+               c=c, species=sp, fit=fit, dt=dt, steps=steps,
+               name=f"tail {nx}x{ny}x{nv}^3 mi/me={mass_ratio:g}")
+    x = _centres(-Lx / 2, Lx / 2, nx)
+    y = _centres(-Ly / 2, Ly / 2, ny)
+    X, Y = np.meshgrid(x, y)
+    ns = 1.0 / np.cosh(Y / lam) ** 2
+    uzi = np.full_like(ns, -Ti / (lam * (Ti + Te)))
+    uze = -uzi * Te / Ti
+    f = []
+    for s, (uz, T) in zip(sp, ((uze, Te), (uzi, Ti))):
+        v = [_centres(s["v_lo"][d], s["v_hi"][d], s["nv"][d]) for d in range(3)]
+        blk = _maxwellian_block(ns, uz, T, s["m"], v)
+        blk += _maxwellian_block(np.full_like(ns, nbg), np.zeros_like(ns), T / 3.0, s["m"], v)
+        f.append(blk.astype(dtype))
+    F = Yee0(nx, ny)
+    dy = Ly / ny
+    yf = -Ly / 2 + np.arange(ny + 1) * dy
+    rng = np.random.default_rng(seed)
+    F.Bx = np.tanh(yf / lam)[:, None] + noise * rng.uniform(-1.0, 1.0, size=(ny + 1, nx))
+    F.Bz[:] = -Bg
+    return cfg, f, F
+
+
+def random_block(shape, seed, kind="smooth"):
+    """Seeded non-negative test data for sweep/moment parity: 'smooth'
+    (Maxwellian-like with a seeded modulation), 'rough' (uniform random) or
+    'step' (piecewise constant with jumps)."""
+    rng = np.random.default_rng(seed)
+    if kind == "rough":
+        return rng.uniform(0.0, 1.0, size=shape)
+    if kind == "step":
+        a = (rng.uniform(size=shape) > 0.5).astype(np.float64)
+        return a * rng.uniform(0.5, 1.0, size=shape)
+    out = np.ones(shape)
+    for ax, n in enumerate(shape):
+        c = (np.arange(n) + 0.5) / n - 0.5
+        w = rng.uniform(0.15, 0.35)
+        sh = [1] * len(shape)
+        sh[ax] = n
+        out = out * np.exp(-0.5 * (c / w) ** 2).reshape(sh)
+    return out * (1.0 + 0.3 * rng.uniform(-1, 1, size=shape))
+
+
+CONFIGS = {
+    "landau": dict(builder="landau", kwargs=dict()),
+    "twostream": dict(builder="twostream", kwargs=dict()),
+    "gem": dict(builder="gem", kwargs=dict()),
+    "tail": dict(builder="tail", kwargs=dict()),
+}

@@ -1,0 +1,197 @@
+"""Pins of the oracle's field solvers and ten-moment fluid step.
+
+Fields:
+* spectral Poisson is exact on a single Fourier mode;
+* the Yee half step is leapfrog with step dt/2, so a vacuum eigenmode evolves
+  as cos(n theta) with cos(theta) = 1 - (c kappa dt/2)^2 / 2,
+  kappa^2 = sum_d (2/h_d sin(k_d h_d / 2))^2 (the discrete dispersion relation),
+  for modes along x, along y (between the conducting walls) and oblique;
+* with j = 0 the discrete divergence of E is constant (Gauss's law residual).
+Fluid:
+* a uniform state with no fields is steady;
+* total density is conserved to round-off (periodic x, reflecting y);
+* x-momentum is conserved with no fields (reflecting y walls exert no x-force);
+* a uniform drifting, anisotropic plasma in a uniform B gyrates: u and the
+  temperature tensor rotate at the cyclotron frequency qB/m (clockwise for
+  q > 0 about +z); RK3 matches the exact rotation to O((Omega dt)^4);
+* with a uniform E the momentum grows linearly and P quadratically (exact);
+* cold advection of a density wave converges at high order.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fields, fluid
+from oracle.moments import PAIRS
+
+
+def test_poisson_single_mode():
+    N, L = 64, 4 * math.pi
+    dx = L / N
+    x = -L / 2 + (np.arange(N) + 0.5) * dx
+    a, k = 0.01, 0.5
+    E = fields.efield_1x1v(1.0 + a * np.cos(k * x), dx, q_e=-1.0)
+    np.testing.assert_allclose(E, -(a / k) * np.sin(k * x), atol=1e-15)
+
+
+def _kappa(k, h):
+    return 2.0 / h * math.sin(0.5 * k * h)
+
+
+@pytest.mark.parametrize("mode", ["x", "y", "oblique"])
+def test_yee_vacuum_dispersion(mode):
+    nx, ny = 32, 16
+    dx, dy = 0.3, 0.25
+    c, dt = 2.0, 0.04
+    F = fields.Yee(nx, ny)
+    xi = (np.arange(nx) + 0.5) * dx        # integer-i positions (from x_lo)
+    yj = (np.arange(ny) + 0.5) * dy        # integer-j positions (from the wall)
+    kx = 2 * math.pi * 2 / (nx * dx)
+    ky = math.pi * 3 / (ny * dy)
+    if mode == "x":                        # Ey(x), Bz(x): even at the walls
+        F.Ey[:] = np.cos(kx * xi)[None, :]
+        Om = c * _kappa(kx, dx)
+        get = lambda G: G.Ey
+        shape = np.ones((ny + 1, 1)) * np.cos(kx * xi)[None, :]
+    elif mode == "y":                      # Ex(y) odd at the walls, Bz(y)
+        F.Ex[:] = np.sin(ky * yj)[:, None]
+        Om = c * _kappa(ky, dy)
+        get = lambda G: G.Ex
+        shape = np.sin(ky * yj)[:, None] * np.ones((1, nx))
+    else:                                  # Ez odd at the walls, Bx, By
+        F.Ez[:] = np.sin(ky * yj)[:, None] * np.cos(kx * xi)[None, :]
+        Om = c * math.hypot(_kappa(kx, dx), _kappa(ky, dy))
+        get = lambda G: G.Ez
+        shape = F.Ez.copy()
+    theta = math.acos(1.0 - 0.5 * (Om * 0.5 * dt) ** 2)
+    jc = np.zeros((ny, nx, 3))
+    for n in range(1, 161):
+        F = fields.maxwell_half_step(F, jc, dt, c, dx, dy)
+        if n % 40 == 0:
+            np.testing.assert_allclose(get(F), shape * math.cos(n * theta), atol=1e-11)
+
+
+def test_gauss_residual_constant_without_current():
+    rng = np.random.default_rng(9)
+    nx, ny, dx, dy, c = 12, 10, 0.2, 0.3, 3.0
+    F = fields.Yee(nx, ny)
+    for k in ("Ex", "Ey", "Ez", "Bx", "Bz"):
+        setattr(F, k, rng.uniform(-1, 1, size=getattr(F, k).shape))
+    F.By = rng.uniform(-1, 1, size=F.By.shape)
+
+    def div(G):
+        return (G.Ex - np.roll(G.Ex, 1, axis=1)) / dx + (G.Ey[1:] - G.Ey[:-1]) / dy
+
+    d0 = div(F)
+    for _ in range(20):
+        F = fields.maxwell_half_step(F, np.zeros((ny, nx, 3)), 0.01, c, dx, dy)
+    np.testing.assert_allclose(div(F), d0, atol=1e-12)
+
+
+# ------------------------------------------------------------------ fluid --
+def _uniform_state(ny, nx, n, u, T, m):
+    U = np.zeros((ny, nx, 10))
+    U[..., 0] = n
+    U[..., 1:4] = n * np.asarray(u)
+    P = n * np.asarray(T) + m * n * np.outer(u, u)
+    for k, (a, b) in enumerate(PAIRS):
+        U[..., 4 + k] = P[a, b]
+    return U
+
+
+def test_uniform_state_steady():
+    U = _uniform_state(6, 8, 1.3, [0.2, 0.0, -0.1], np.diag([0.5, 0.4, 0.6]), 0.7)
+    Q = np.ones((6, 8, 10)) * np.linspace(0.1, 1.0, 10)
+    Q[..., [1, 4, 6, 8]] = 0.0                # y-odd components vanish (mirror symmetry)
+    Z = np.zeros((6, 8, 3))
+    U1 = fluid.rk3_3v(U, Q, Q, (Z, Z), (Z, Z), (Z, Z), 1.0, 0.7, 0.3, 0.4, 0.01)
+    np.testing.assert_allclose(U1, U, rtol=1e-14, atol=1e-15)
+
+
+def test_density_and_x_momentum_conservation():
+    rng = np.random.default_rng(10)
+    ny, nx, m = 8, 12, 0.5
+    U = _uniform_state(ny, nx, 1.0, [0, 0, 0], np.eye(3) * 0.5, m)
+    U[..., 0] *= 1 + 0.2 * rng.uniform(-1, 1, size=(ny, nx))
+    U[..., 1:4] = 0.1 * rng.uniform(-1, 1, size=(ny, nx, 3))
+    for k, (a, b) in enumerate(PAIRS):
+        U[..., 4 + k] = U[..., 0] * (0.5 if a == b else 0.05) + m * U[..., 1 + a] * U[..., 1 + b] / U[..., 0]
+    Q = 0.05 * rng.uniform(-1, 1, size=(ny, nx, 10))
+    Z = np.zeros((ny, nx, 3))
+    U1 = fluid.rk3_3v(U, Q, Q, (Z, Z), (Z, Z), (Z, Z), -1.0, m, 0.3, 0.3, 0.01)
+    assert U1[..., 0].sum() == pytest.approx(U[..., 0].sum(), rel=1e-14)
+    assert U1[..., 1].sum() == pytest.approx(U[..., 1].sum(), abs=1e-13)
+
+
+def _rot_z(angle):
+    c, s = math.cos(angle), math.sin(angle)
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])
+
+
+@pytest.mark.parametrize("q", [1.0, -1.0])
+def test_gyration_in_uniform_B(q):
+    m, n, B = 0.5, 1.1, 0.8
+    u0 = np.array([0.3, 0.1, 0.05])
+    T0 = np.array([[0.6, 0.1, 0.0], [0.1, 0.3, 0.02], [0.0, 0.02, 0.4]])
+    # the y-walls disturb the drifting state near them; over t = 1 the disturbance
+    # travels a few cells, so the middle of a 40-cell column is checked
+    U = _uniform_state(40, 2, n, u0, T0, m)
+    Q = np.zeros((40, 2, 10))
+    E = np.zeros((40, 2, 3))
+    Bv = np.zeros((40, 2, 3))
+    Bv[..., 2] = B
+    Om = q * B / m
+    dt, steps = 0.01, 100
+    for _ in range(steps):
+        U = fluid.rk3_3v(U, Q, Q, (E, Bv), (E, Bv), (E, Bv), q, m, 1.0, 1.0, dt)
+    R = _rot_z(-Om * dt * steps)               # v' = (q/m) v x B: clockwise for q B > 0
+    u1 = R @ u0
+    T1 = R @ T0 @ R.T
+    expect = _uniform_state(1, 1, n, u1, T1, m)[0, 0]
+    tol = steps * (abs(Om) * dt) ** 4
+    for j in range(15, 25):
+        np.testing.assert_allclose(U[j, 0], expect, atol=tol)
+
+
+def test_uniform_E_polynomial_growth():
+    m, n, q, Ex = 0.25, 0.9, -1.0, 0.3
+    U = _uniform_state(2, 2, n, [0.1, 0, 0], np.eye(3) * 0.2, m)
+    Ev = np.zeros((2, 2, 3))
+    Ev[..., 0] = Ex
+    Z = np.zeros((2, 2, 3))
+    Q = np.zeros((2, 2, 10))
+    t = 0.37
+    U1 = fluid.rk3_3v(U, Q, Q, (Ev, Z), (Ev, Z), (Ev, Z), q, m, 1.0, 1.0, t)
+    nux0, Pxx0 = U[0, 0, 1], U[0, 0, 4]
+    a = (q / m) * n * Ex
+    assert U1[0, 0, 1] == pytest.approx(nux0 + a * t, rel=1e-14)
+    assert U1[0, 0, 4] == pytest.approx(Pxx0 + 2 * q * Ex * (nux0 * t + 0.5 * a * t * t), rel=1e-14)
+
+
+def test_cold_advection_convergence_1v():
+    """n = 1 + 0.2 sin(2 pi (x - u t)), cold (T = 0), Qcal = m n u^3 supplied at
+    the stage times: the exact solution translates at speed u."""
+    m, u, dt_over_h = 1.0, 0.7, 0.3
+    errs = []
+    for N in (64, 128, 256):
+        h = 1.0 / N
+        x_lo = np.arange(N) * h
+
+        def avg_n(t):
+            lo, hi = x_lo - u * t, x_lo + h - u * t
+            return 1.0 + 0.2 * (np.cos(2 * np.pi * lo) - np.cos(2 * np.pi * hi)) / (2 * np.pi * h)
+
+        dt = dt_over_h * h
+        steps = int(round(0.5 / (u * dt)))
+        nn = avg_n(0.0)
+        U = np.stack([nn, nn * u, m * nn * u * u], axis=1)
+        E = np.zeros(N)
+        for k in range(steps):
+            Qt, Qt1 = m * avg_n(k * dt) * u ** 3, m * avg_n((k + 1) * dt) * u ** 3
+            U = fluid.rk3_1v(U, Qt, Qt1, E, E, -1.0, m, h, dt)
+        errs.append(np.abs(U[:, 0] - avg_n(steps * dt)).mean())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    # CWENO's nonlinear weights reach their linear values only once the cell
+    # differences are small against eps = 1e-6; from 64 cells on, ratios > 5
+    assert r1 > 5.0 and r2 > 5.0, errs
