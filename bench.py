@@ -1,0 +1,199 @@
+"""Throughput of the full moment-fitting Vlasov step on one MI355X.
+
+A step is one vl_step (Algorithm 1: Maxwell half step, X(dt/2), V(dt),
+X(dt/2), moments, ten-moment fluid RK3, moment fitting, Maxwell half step)
+over all phase-space cells of both species, with inputs resident in HBM.
+
+Default workload: GEM-like 2X3V reconnection (Sec. 3.3 geometry) on
+256 x 128 spatial cells x 16^3 velocity cells x 2 species (m_i/m_e = 25),
+FP32 f with FP64 moments, fitting and fields.  The same workload is also run
+with FP64 f to report the FP32 speed-up.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "phase-space cell-updates/s per full step (FP32 vs FP64) + % of HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    from paper_2109_06743_amd import workloads as W
+    if name == "gem":
+        cfg, f, F = W.gem(nx=256, ny=128, nv=16, dt=0.003, fit=True, dtype=np.float32)
+        label = "GEM 2X3V 256x128 x 16^3 x 2 species, mi/me=25, moment fitting"
+    elif name == "tail":
+        cfg, f, F = W.tail(nx=1024, ny=512, nv=12, dt=0.0012, fit=True, dtype=np.float32)
+        label = "magnetotail 2X3V 1024x512 x 12^3 x 2 species, mi/me=100, Bg=0.1, moment fitting"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return cfg, f, F, label
+
+
+def run_gpu(cfg, f, F, dtype, steps, warmup, timing_steps):
+    import torch
+    from paper_2109_06743_amd import vl
+    ctx = vl.Context(cfg, dtype)
+    st = vl.StepState(ctx, f, vl.yee_pack(F))
+    torch.cuda.synchronize()
+    ncells = sum(x.numel() for x in st.f)
+    me0 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    e0 = 0.0
+    for s in range(len(st.f)):
+        ctx.mass_energy(s, st.f[s], st.mom_post[s], me0)
+        e0 += me0[1].item()
+    for _ in range(warmup):
+        ctx.step(st, cfg["dt"])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(steps):
+        ctx.step(st, cfg["dt"])
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = a.elapsed_time(b) / steps
+    ctx.sync()
+    # per-kernel timing with HIP events on the launch stream
+    ctx.timing_enable(True)
+    for _ in range(timing_steps):
+        ctx.step(st, cfg["dt"])
+    ctx.sync()
+    tim = ctx.timing_read()
+    ctx.timing_enable(False)
+    e1 = 0.0
+    mass = []
+    for s in range(len(st.f)):
+        ctx.mass_energy(s, st.f[s], st.mom_post[s], me0)
+        e1 += me0[1].item()
+        mass.append(me0[0].item())
+    cnt = st.counters.cpu().numpy().tolist()
+    res = dict(ms=ms, wall=wall, ncells=ncells, timing=tim, kinetic_energy=(e0, e1), mass=mass,
+               counters=cnt, elem=4 if dtype == "f32" else 8)
+    del st, ctx
+    torch.cuda.empty_cache()
+    return res
+
+
+def roofline(res, cells_per_species, nspecies):
+    """Dominant f-pass kernel: algorithmic bytes per launch / mean launch time."""
+    elem = res["elem"]
+    # bytes of f each category moves per launch: read + write of one species' f
+    # (moments: read only); halo re-reads are not algorithmic traffic
+    per_launch = {"pfc_x": 2 * elem, "pfc_y": 2 * elem, "pfc_v": 2 * elem, "fit": 2 * elem, "moments": elem}
+    best = None
+    for k, nbytes in per_launch.items():
+        tot, n = res["timing"][k]
+        if n == 0:
+            continue
+        if best is None or tot > best[1]:
+            best = (k, tot, n, nbytes)
+    k, tot, n, nbytes = best
+    avg_s = tot / n * 1e-3
+    traffic = nbytes * cells_per_species
+    achieved = traffic / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": k,
+            "avg_launch_ms": round(tot / n, 4), "algorithmic_bytes_per_launch": traffic}
+
+
+def cpu_baseline(seconds_cap=30.0):
+    """The FP64 numpy oracle's full step on a sample of the same workload: the
+    GEM set-up with the same 16^3 velocity grids and species on a 16 x 8
+    spatial slab (per-cell work identical to the full grid)."""
+    from oracle import fields as OF, moments as OM, step as OS
+    from paper_2109_06743_amd import workloads as W
+    cfg, f, F0 = W.gem(nx=16, ny=8, nv=16, dt=0.003, fit=True, dtype=np.float64)
+    F = OF.Yee(cfg["nx"], cfg["ny"])
+    for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        setattr(F, k, getattr(F0, k).copy())
+    moms, Us = [], []
+    for k, sp in enumerate(cfg["species"]):
+        v, dv = OS._grids(cfg, sp)
+        mm = OM.raw_moments_3v(f[k], v, dv, sp["m"])
+        moms.append(mm)
+        Us.append(mm[..., :10].copy())
+    st = dict(f=f, U=Us, mom_post=moms, F=F)
+    ncells = sum(x.size for x in f)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        st = OS.step_2x3v(st, cfg, cfg["dt"])
+        n += 1
+        if time.perf_counter() - t0 > seconds_cap / 2 or n >= 10:
+            break
+    dt = (time.perf_counter() - t0) / n
+    return {"value": ncells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"GEM 16x8 x 16^3 x 2 species (fit on), {n} steps of the numpy FP64 oracle, "
+                      f"{dt:.2f} s/step, single-threaded numpy"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gem", choices=["gem", "tail"])
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this build runs on one GPU only: the method's data-parallel path is measured on one MI355X; "
+              "--gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2109_06743_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    cfg, f, F, label = build_workload(args.workload)
+    log(f"workload {label}: built in {time.perf_counter() - t0:.1f} s")
+    cells_per_species = f[0].size
+    r32 = run_gpu(cfg, f, F, "f32", args.steps, args.warmup, 3)
+    log(f"fp32: {r32['ms']:.3f} ms/step  timing {r32['timing']}")
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", max(args.steps // 2, 3), 2, 3)
+        log(f"fp64: {r64['ms']:.3f} ms/step")
+    value = r32["ncells"] / (r32["ms"] * 1e-3)
+    roof = roofline(r32, cells_per_species, len(f))
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r32["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": label, "cells": r32["ncells"], "species": len(f), "dt": cfg["dt"],
+                   "moments_fields_fluid": "f64"},
+        "roofline": roof,
+    }
+    step_bytes = 6 * 2 * r32["elem"] * r32["ncells"]          # six read+write passes over f per step
+    out["effective_hbm_frac_step"] = round(step_bytes / (r32["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    if r64 is not None:
+        v64 = r64["ncells"] / (r64["ms"] * 1e-3)
+        out["fp64"] = {"value": v64, "ms_per_step": round(r64["ms"], 4), "speedup_fp32_over_fp64": round(value / v64, 3)}
+    e0, e1 = r32["kinetic_energy"]
+    out["kinetic_energy_rel_change"] = (e1 - e0) / e0
+    out["kernel_ms_per_step"] = {k: round(v[0] / 3, 4) for k, v in r32["timing"].items()}
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

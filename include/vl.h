@@ -1,0 +1,217 @@
+/*
+ * vl.h - C ABI of the MI355X (gfx950) moment-fitting Vlasov hot path.
+ *
+ * Method: arXiv 2109.06743 (Allmann-Rahn, Lautenbach, Grauer), "An Energy
+ * Conserving Vlasov Solver That Tolerates Coarse Velocity Space
+ * Resolutions".  The library advances the distribution function f of each
+ * species by dimensionally split PFC advection (Eq. 1; Sec. 2.1), computes
+ * its velocity moments (Sec. 2.1, definitions after Eq. 1), fits the
+ * ten-moment Maxwellian part of f to the fluid solver's moments (Sec. 2.2,
+ * Algorithm 1) and runs the full time step of Algorithm 1 with the Yee
+ * FDTD (2X3V) or spectral Poisson (1X1V) field solver and the ten-moment
+ * CWENO/SSP-RK3 fluid solver.
+ *
+ * Conventions shared by every entry point
+ * - Every large buffer is caller-owned DEVICE memory (HIP global memory on
+ *   the current device).  The library never frees it.
+ * - f layouts (C order, fastest index last):
+ *     1X1V  f[nx][nv]
+ *     2X3V  f[ny][nx][nvx][nvy][nvz]
+ *   f is FP32 or FP64 as fixed by vl_config.f_dtype.  f >= 0 is required.
+ * - Velocity cell centres: v_j = v_lo + (j + 1/2) (v_hi - v_lo) / n.
+ *   Spatial cell centres likewise; x is periodic, y (2X3V) is bounded by
+ *   conducting walls for the fields and reflecting walls for particles,
+ *   which needs each species' v_y grid symmetric about 0.
+ * - Moment vectors per spatial cell, FP64 (raw moments, midpoint rule):
+ *     3V: [n, M1x, M1y, M1z, P(xx,xy,xz,yy,yz,zz), Q(xxx,xxy,xxz,xyy,xyz,
+ *          xzz,yyy,yyz,yzz,zzz)]  (20 doubles), with P = m sum v v f dV,
+ *          Q = m sum v v v f dV;
+ *     1V: [n, M1, P, Q]  (4 doubles).
+ * - Fluid state per spatial cell, FP64: 3V [n, nu(3), P(6)] (10 doubles),
+ *   1V [n, nu, P] (3 doubles).
+ * - Every call validates its arguments on the host before any launch and
+ *   returns a status; nothing is thrown across the ABI.  Launches are
+ *   asynchronous on the given stream (NULL = the default stream).  A device
+ *   fault surfaces as VL_EHIP on a later call or on vl_sync.
+ * - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef VL_H
+#define VL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* vl_stream; /* a hipStream_t */
+
+typedef enum {
+    VL_OK = 0,
+    VL_EINVAL = 1,   /* bad argument: NULL, size, non-finite or non-positive step, ... */
+    VL_EALIAS = 2,   /* an output aliases an input where that is not allowed */
+    VL_ENOTSUP = 3,  /* valid request the library does not implement */
+    VL_EDEVICE = 4,  /* no usable HIP device */
+    VL_EHIP = 5,     /* a HIP runtime call failed (message in vl_last_error) */
+    VL_ENUMERIC = 6  /* non-finite values found by a guard */
+} vl_status;
+
+enum { VL_F32 = 0, VL_F64 = 1 };
+enum { VL_BC_REFLECT = 0 };
+enum { VL_CLOSURE_KINETIC = 0 };
+enum { VL_MAX_SPECIES = 2 };
+
+typedef struct {
+    double q, m;          /* charge and mass (normalised units of Sec. 2.1 / Sec. 3.1) */
+    double v_lo[3];       /* velocity box, per axis (1V uses index 0) */
+    double v_hi[3];
+    int32_t nv[3];        /* velocity cells per axis (1V: nv[1] = nv[2] = 1) */
+} vl_species;
+
+typedef struct {
+    int32_t dim_x;        /* 1 or 2 */
+    int32_t dim_v;        /* 1 (with dim_x = 1) or 3 (with dim_x = 2) */
+    int32_t nx, ny;       /* spatial cells; ny = 1 when dim_x = 1 */
+    double x_lo, x_hi;    /* periodic x extent */
+    double y_lo, y_hi;    /* y extent between walls (2X3V) */
+    int32_t bc_y;         /* VL_BC_REFLECT */
+    int32_t nspecies;     /* 1 .. VL_MAX_SPECIES */
+    vl_species sp[VL_MAX_SPECIES];
+    int32_t f_dtype;      /* VL_F32 or VL_F64 */
+    double c;             /* speed of light (2X3V); eps0 = 1/c^2, mu0 = 1 */
+    int32_t fit;          /* 0: standard PFC step, 1: moment fitting (Algorithm 1) */
+    int32_t closure;      /* VL_CLOSURE_KINETIC: third moment from f */
+} vl_config;
+
+typedef struct vl_ctx vl_ctx;
+
+/* Create a context for one problem geometry.  Host-only: validates and copies
+ * *cfg; device scratch (a few hundred bytes) is allocated on first use on the
+ * device current at that time.  Errors: VL_EINVAL (bad geometry, velocity
+ * grid not symmetric in v_y for 2X3V), VL_ENOTSUP (unsupported combination). */
+vl_status vl_create(const vl_config* cfg, vl_ctx** out);
+vl_status vl_destroy(vl_ctx* ctx);
+
+/* Free streaming X(tau) of species s (Eq. 1, v . grad f; split PFC sweeps,
+ * Sec. 2.1): x-sweep by v_x tau/dx cells (periodic), then in 2X3V a y-sweep
+ * by v_y tau/dy cells between reflecting walls.  The PFC limiter bound is
+ * the maximum of f_in.  f_in is not modified.  In 2X3V f_work (same size as
+ * f) receives the intermediate x-swept array; in 1X1V it may be NULL.
+ * f_out must not alias f_in or f_work (VL_EALIAS). */
+vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, void* f_work,
+                          double tau, vl_stream stream);
+
+/* Acceleration V(tau) of species s (Eq. 1, (q/m)(E + v x B) . grad_v f) with
+ * zero-flux velocity boundaries (Sec. 2.1).  E, B are cell-centred FP64
+ * fields [cells][3] (cells = ny*nx); B may be NULL (treated as 0).  1V uses
+ * E[cells] (one double per cell) and ignores B.  3V applies the sweeps
+ * vx(tau/2) vy(tau/2) vz(tau) vy(tau/2) vx(tau/2), each a uniform shift by the
+ * acceleration at the pencil's transverse velocities.  Limiter bound: max of
+ * f_in.  f_out must not alias f_in. */
+vl_status vl_pfc_advect_v(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out,
+                          const double* E, const double* B, double tau, vl_stream stream);
+
+/* Raw velocity moments of species s (Sec. 2.1) per spatial cell into mom
+ * (FP64, [cells][20] in 3V, [cells][4] in 1V; layout in the header comment). */
+vl_status vl_moments(vl_ctx* ctx, int32_t s, const void* f, double* mom, vl_stream stream);
+
+/* Moment fitting of species s (Algorithm 1, "Moment Fitting"; Sec. 2.2):
+ * per cell, with n_V, u_V, T_V from mom_pre (raw moments of f_in) and u_F,
+ * T_F from the fluid state U, f_out = f_in - M[n_V,u_V,T_V] + M[n_V,u_F,T_F],
+ * negatives set to 0, then rescaled to density n_V.  M is the ten-moment
+ * Maxwellian normalised by its discrete sum.  U is rescaled by n_V/n_F in
+ * place.  Cells with n_V <= 1e-12, n_F <= 1e-12 or a temperature tensor that
+ * is not positive definite are copied unchanged and counted as skipped.
+ * mom_post (may be NULL) receives the raw moments of f_out; counters (may
+ * be NULL; int64[2] device) accumulates {clipped values, skipped cells}.
+ * f_out may equal f_in (in place). */
+vl_status vl_moment_fit(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, const double* mom_pre,
+                        double* U, double* mom_post, int64_t* counters, vl_stream stream);
+
+/* Fields.  1X1V: E[nx] at cell centres from Gauss's law with the uniform
+ * neutralising background (Sec. 3.1), spectral, E_0 = 0.  The density is
+ * taken from mom (species 0 moments, [nx][4]). */
+vl_status vl_poisson(vl_ctx* ctx, const double* mom, double* E, vl_stream stream);
+
+/* 2X3V Yee fields, FP64, concatenated: Ex[ny][nx] (i+1/2, j), Ey[ny+1][nx]
+ * (i, j-1/2), Ez[ny][nx] (i, j), Bx[ny+1][nx] (i, j-1/2), By[ny][nx]
+ * (i+1/2, j), Bz[ny+1][nx] (i+1/2, j-1/2); rows 0 and ny of the [ny+1]
+ * arrays lie on the walls.  One Maxwell half step (Algorithm 1, first and
+ * last line; the reading is B -= dt/4 curl E, E += dt/2 c^2 (curl B - j),
+ * B -= dt/4 curl E) with the current j = sum_s q_s M1_s taken from the
+ * species' moment arrays mom[s] ([cells][20]). */
+size_t vl_yee_size(const vl_ctx* ctx);   /* doubles in the Yee array */
+vl_status vl_maxwell_half_step(vl_ctx* ctx, double* yee, const double* const* mom, double dt,
+                               vl_stream stream);
+/* Cell-centred E, B ([cells][3] each) averaged from the Yee array. */
+vl_status vl_cell_fields(vl_ctx* ctx, const double* yee, double* E, double* B, vl_stream stream);
+
+/* One SSP-RK3 step of the ten-moment fluid (Eqs. 2-4) for species s with the
+ * third moment supplied from f (Algorithm 1): Qcal at t and t+1 are taken
+ * from mom_t and mom_t1 (raw moment arrays), t+1/2 is their mean.  Fields at
+ * the stage times t, t+1, t+1/2: 3V E_*, B_* [cells][3]; 1V E_* [cells]
+ * (B_* ignored).  U is updated in place.  work: vl_fluid_work_size doubles. */
+size_t vl_fluid_work_size(const vl_ctx* ctx);
+vl_status vl_fluid_step(vl_ctx* ctx, int32_t s, double* U, const double* mom_t, const double* mom_t1,
+                        const double* E_t, const double* B_t, const double* E_t1, const double* B_t1,
+                        const double* E_th, const double* B_th, double dt, double* work,
+                        vl_stream stream);
+
+/* Full time step (Algorithm 1).  All pointers are device buffers.
+ *   f[s]        in: f^t, out: f^{t+1}
+ *   f_tmp[s]    scratch of the same size as f[s]
+ *   mom_post[s] in: raw moments of f^t; out: of f^{t+1} (after fitting)
+ *   mom_pre[s]  out: raw moments of f^{t+1} before fitting
+ *   U[s]        fluid state (used when fit = 1), in/out
+ *   fields      2X3V: the Yee array (in/out); 1X1V: E at t+1/2 (out, [nx])
+ *   work        vl_step_work_size doubles of scratch
+ *   counters    int64[2] {clipped, skipped} accumulated, or NULL
+ * Sequence (2X3V): Maxwell half step with j^t; X(dt/2); V(dt) with the
+ * cell-centred fields at t+1/2; X(dt/2); raw moments; fluid RK3 with Qcal at
+ * t, t+1, t+1/2; moment fitting; Maxwell half step with j^{t+1}.  1X1V: X(dt/2);
+ * Poisson; V(dt); X(dt/2); moments; fluid; fitting.  fit = 0 skips fluid and
+ * fitting (standard PFC step, mom_post = mom_pre).
+ * f_max_valid: host flag; 0 tells the step to compute max f[s] itself, the
+ * step sets it to 1 (the maximum of f^{t+1} is kept in the context for the
+ * next step).  Set it to 0 whenever f changes outside vl_step. */
+typedef struct {
+    void* f[VL_MAX_SPECIES];
+    void* f_tmp[VL_MAX_SPECIES];
+    double* mom_post[VL_MAX_SPECIES];
+    double* mom_pre[VL_MAX_SPECIES];
+    double* U[VL_MAX_SPECIES];
+    double* fields;
+    double* work;
+    int64_t* counters;
+    int32_t f_max_valid;
+} vl_state;
+
+size_t vl_step_work_size(const vl_ctx* ctx);
+vl_status vl_step(vl_ctx* ctx, vl_state* st, double dt, vl_stream stream);
+
+/* Diagnostics: total mass of species s (sum f dV dX, FP64) and the
+ * kinetic+thermal energy sum tr(P)/2 dX (3V) or P/2 dX (1V) from a raw
+ * moment array, written to out[0..1] (device doubles). */
+vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mom, double* out,
+                         vl_stream stream);
+
+/* Kernel timing (tracing aid).  When enabled, every launch group issued by
+ * the entry points of ctx is bracketed by HIP events recorded on the stream
+ * it runs on.  vl_timing_read waits for the recorded events, returns the
+ * summed milliseconds and launch-group counts per category (arrays of
+ * VL_T_COUNT entries) since the previous read, and clears them. */
+enum { VL_T_MAX = 0, VL_T_PFC_X, VL_T_PFC_Y, VL_T_PFC_V, VL_T_MOMENTS, VL_T_FLUID, VL_T_FIT, VL_T_FIELDS,
+       VL_T_COPY, VL_T_COUNT };
+vl_status vl_timing_enable(vl_ctx* ctx, int32_t on);
+vl_status vl_timing_read(vl_ctx* ctx, double* ms, int64_t* count);
+
+vl_status vl_sync(vl_ctx* ctx, vl_stream stream);       /* wait for the stream, report device errors */
+const char* vl_status_str(vl_status st);
+const char* vl_last_error(const vl_ctx* ctx);          /* message of the last failure on ctx */
+const char* vl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VL_H */

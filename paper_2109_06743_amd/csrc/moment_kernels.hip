@@ -1,0 +1,508 @@
+// Velocity moments and moment fitting for gfx950.
+//
+// Moments (Sec. 2.1 of arXiv 2109.06743, definitions after Eq. 1), midpoint
+// rule on the velocity cell centres, accumulated in FP64 whatever the storage
+// type of f.  3V sums are separable: each thread forms the four row sums
+// sum_z f v_z^k (k = 0..3) of one (v_x, v_y) row, then the row's share of the
+// 20 raw moments needs 20 FP64 operations per row instead of per cell.
+//
+// Moment fitting (Algorithm 1, "Moment Fitting"; Sec. 2.2): per cell
+//   f' = f - M[n_V, u_V, T_V] + M[n_V, u_F, T_F],  f'' = max(f', 0),
+//   f_new = f'' n_V / (sum f'' dV),
+// M the ten-moment Maxwellian n g / (sum g dV), g = exp(-(m/2) w^T T^-1 w),
+// w = v - u.  Exponentials and f in the storage type; quadratic-form
+// coefficients, normalisation sums, the rescale factor and all moments FP64.
+#include "vl_internal.h"
+
+namespace vl {
+
+struct VGrid {
+    int nvx, nvy, nvz;
+    double lo[3], dv[3];
+    double m;
+};
+
+__device__ __forceinline__ double vc(const VGrid& G, int d, int i) { return G.lo[d] + (i + 0.5) * G.dv[d]; }
+
+// 20 raw moments (already multiplied by dV, and by m for P and Q) of a block
+// held in shared memory with rows of length nvz at stride pz.  Result in
+// mom[] of every thread.  red: shared scratch of 20 * (blockDim/64) doubles.
+template <class T>
+__device__ void block_moments3(const T* blk, int pz, const VGrid& G, double (&mom)[20], double* red) {
+    double acc[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+    const int rows = G.nvx * G.nvy;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        const int ix = r / G.nvy, iy = r % G.nvy;
+        const T* row = blk + r * pz;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int iz = 0; iz < G.nvz; ++iz) {
+            const double f = (double)row[iz];
+            const double z = vc(G, 2, iz);
+            const double fz = f * z;
+            s0 += f;
+            s1 += fz;
+            s2 += fz * z;
+            s3 += fz * z * z;
+        }
+        const double X = vc(G, 0, ix), Y = vc(G, 1, iy);
+        const double X2 = X * X, Y2 = Y * Y, XY = X * Y;
+        acc[0] += s0;
+        acc[1] += X * s0;
+        acc[2] += Y * s0;
+        acc[3] += s1;
+        acc[4] += X2 * s0;      // xx
+        acc[5] += XY * s0;      // xy
+        acc[6] += X * s1;       // xz
+        acc[7] += Y2 * s0;      // yy
+        acc[8] += Y * s1;       // yz
+        acc[9] += s2;           // zz
+        acc[10] += X2 * X * s0; // xxx
+        acc[11] += X2 * Y * s0; // xxy
+        acc[12] += X2 * s1;     // xxz
+        acc[13] += X * Y2 * s0; // xyy
+        acc[14] += XY * s1;     // xyz
+        acc[15] += X * s2;      // xzz
+        acc[16] += Y2 * Y * s0; // yyy
+        acc[17] += Y2 * s1;     // yyz
+        acc[18] += Y * s2;      // yzz
+        acc[19] += s3;          // zzz
+    }
+    block_sum<20>(acc, red);
+    const double dV = G.dv[0] * G.dv[1] * G.dv[2];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) mom[k] = acc[k] * (k < 4 ? dV : G.m * dV);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) moments3_kernel(const T* __restrict__ f, double* __restrict__ mom, VGrid G) {
+    extern __shared__ unsigned char smem_raw[];
+    T* blk = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[20 * 4];
+    const long long cell = blockIdx.x;
+    const int nv = G.nvx * G.nvy * G.nvz;
+    const int pz = G.nvz | 1;
+    const T* src = f + cell * nv;
+    for (int e = threadIdx.x; e < nv; e += blockDim.x) blk[(e / G.nvz) * pz + e % G.nvz] = src[e];
+    __syncthreads();
+    double m[20];
+    block_moments3(blk, pz, G, m, red);
+    if (threadIdx.x < 20) {
+        double v = 0;
+#pragma unroll
+        for (int k = 0; k < 20; ++k) v = (threadIdx.x == k) ? m[k] : v;
+        mom[cell * 20 + threadIdx.x] = v;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) moments1_kernel(const T* __restrict__ f, double* __restrict__ mom, int nv,
+                                                       double vlo, double dv, double mass) {
+    __shared__ double red[4 * 4];
+    const long long cell = blockIdx.x;
+    const T* src = f + cell * nv;
+    double acc[4] = {0, 0, 0, 0};
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+        const double v = vlo + (j + 0.5) * dv;
+        const double x = (double)src[j];
+        const double xv = x * v;
+        acc[0] += x;
+        acc[1] += xv;
+        acc[2] += xv * v;
+        acc[3] += xv * v * v;
+    }
+    block_sum<4>(acc, red);
+    if (threadIdx.x == 0) {
+        mom[cell * 4 + 0] = acc[0] * dv;
+        mom[cell * 4 + 1] = acc[1] * dv;
+        mom[cell * 4 + 2] = mass * acc[2] * dv;
+        mom[cell * 4 + 3] = mass * acc[3] * dv;
+    }
+}
+
+// ------------------------------------------------------------------ fit ----
+// Symmetric 3x3 stored as (xx, xy, xz, yy, yz, zz).  Returns false unless the
+// matrix is positive definite (Cholesky pivots > 0); inv receives its inverse.
+__device__ __forceinline__ bool spd_inverse(const double (&a)[6], double (&inv)[6]) {
+    const double l11sq = a[0];
+    if (!(l11sq > 0.0)) return false;
+    const double l11 = sqrt(l11sq);
+    const double l21 = a[1] / l11, l31 = a[2] / l11;
+    const double l22sq = a[3] - l21 * l21;
+    if (!(l22sq > 0.0)) return false;
+    const double l22 = sqrt(l22sq);
+    const double l32 = (a[4] - l31 * l21) / l22;
+    const double l33sq = a[5] - l31 * l31 - l32 * l32;
+    if (!(l33sq > 0.0)) return false;
+    // inverse via cofactors (the matrix is SPD, so det > 0)
+    const double c00 = a[3] * a[5] - a[4] * a[4];
+    const double c01 = a[2] * a[4] - a[1] * a[5];
+    const double c02 = a[1] * a[4] - a[2] * a[3];
+    const double c11 = a[0] * a[5] - a[2] * a[2];
+    const double c12 = a[1] * a[2] - a[0] * a[4];
+    const double c22 = a[0] * a[3] - a[1] * a[1];
+    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    const double id = 1.0 / det;
+    inv[0] = c00 * id; inv[1] = c01 * id; inv[2] = c02 * id;
+    inv[3] = c11 * id; inv[4] = c12 * id; inv[5] = c22 * id;
+    return true;
+}
+
+// Mean velocity and temperature tensor from (n, nu, P) with T = (P - m n u u)/n.
+__device__ __forceinline__ void u_and_T(const double* nuP, double n, double m, double (&u)[3], double (&T)[6]) {
+    u[0] = nuP[0] / n; u[1] = nuP[1] / n; u[2] = nuP[2] / n;
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) T[k] = (nuP[3 + k] - m * n * u[ia[k]] * u[ib[k]]) / n;
+}
+
+template <class T>
+__device__ __forceinline__ T expo(T x);
+template <> __device__ __forceinline__ float expo<float>(float x) { return __expf(x); }
+template <> __device__ __forceinline__ double expo<double>(double x) { return exp(x); }
+
+// Exponent -(m/2) w^T Tinv w with coefficients A = (m/2) Tinv (off-diagonals doubled).
+template <class T>
+struct Quad {
+    T axx, axy, axz, ayy, ayz, azz;
+    T ux, uy, uz;
+    __device__ __forceinline__ void set(const double (&inv)[6], const double (&u)[3], double m) {
+        const double h = 0.5 * m;
+        axx = (T)(h * inv[0]); axy = (T)(2.0 * h * inv[1]); axz = (T)(2.0 * h * inv[2]);
+        ayy = (T)(h * inv[3]); ayz = (T)(2.0 * h * inv[4]); azz = (T)(h * inv[5]);
+        ux = (T)u[0]; uy = (T)u[1]; uz = (T)u[2];
+    }
+    __device__ __forceinline__ T g(T vx, T vy, T vz) const {
+        const T wx = vx - ux, wy = vy - uy, wz = vz - uz;
+        const T q = wx * (axx * wx + axy * wy + axz * wz) + wy * (ayy * wy + ayz * wz) + azz * wz * wz;
+        return expo<T>(-q);
+    }
+};
+
+// Per-cell fit.  One block per spatial cell; the block's f values sit in
+// registers (EPT per thread, element e = tid + k * blockDim), the clipped f''
+// is staged in shared memory for the separable moment sums.
+template <class T, int EPT>
+__global__ void __launch_bounds__(256)
+fit3_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* __restrict__ U,
+            double* __restrict__ mom_post, unsigned long long* __restrict__ counters, VGrid G,
+            typename Bits<T>::U* __restrict__ max_out) {
+    extern __shared__ unsigned char smem_raw[];
+    T* blk = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[21 * 4];
+    const long long cell = blockIdx.x;
+    const int nv = G.nvx * G.nvy * G.nvz;
+    const int pz = G.nvz | 1;
+    const double dV = G.dv[0] * G.dv[1] * G.dv[2];
+    const T* src = fin + cell * nv;
+    T* dst = fout + cell * nv;
+
+    T fv[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = threadIdx.x + k * blockDim.x;
+        fv[k] = (e < nv) ? src[e] : T(0);
+    }
+
+    // cell parameters (every thread computes the same values)
+    double mp[10], Uc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) { mp[k] = mom_pre[cell * 20 + k]; Uc[k] = U[cell * 10 + k]; }
+    const double nV = mp[0], nF = Uc[0];
+    double uV[3], TV[6], uF[3], TF[6], iV[6], iF[6];
+    bool ok = nV > 1e-12 && nF > 1e-12;
+    if (ok) {
+        u_and_T(mp + 1, nV, G.m, uV, TV);
+        u_and_T(Uc + 1, nF, G.m, uF, TF);
+        ok = spd_inverse(TV, iV) && spd_inverse(TF, iF);
+    }
+
+    T outv[EPT];
+    unsigned long long nclip = 0;
+    if (ok) {
+        Quad<T> qv, qf;
+        qv.set(iV, uV, G.m);
+        qf.set(iF, uF, G.m);
+        T gv[EPT], gf[EPT];
+        double sums[2] = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * blockDim.x;
+            gv[k] = T(0);
+            gf[k] = T(0);
+            if (e < nv) {
+                const int iz = e % G.nvz, r = e / G.nvz;
+                const T vx = (T)vc(G, 0, r / G.nvy), vy = (T)vc(G, 1, r % G.nvy), vz = (T)vc(G, 2, iz);
+                gv[k] = qv.g(vx, vy, vz);
+                gf[k] = qf.g(vx, vy, vz);
+                sums[0] += (double)gv[k];
+                sums[1] += (double)gf[k];
+            }
+        }
+        block_sum<2>(sums, red);
+        const T A = (T)(nV / (sums[0] * dV));
+        const T Bc = (T)(nV / (sums[1] * dV));
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * blockDim.x;
+            const T x = fv[k] - A * gv[k] + Bc * gf[k];
+            if (e < nv && x < T(0)) ++nclip;
+            outv[k] = fmax(x, T(0));
+            if (e < nv) blk[(e / G.nvz) * pz + e % G.nvz] = outv[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int e = threadIdx.x + k * blockDim.x;
+            outv[k] = fv[k];
+            if (e < nv) blk[(e / G.nvz) * pz + e % G.nvz] = fv[k];
+        }
+    }
+    __syncthreads();
+    double mm[20];
+    block_moments3(blk, pz, G, mm, red);
+    const double scale = ok ? nV / mm[0] : 1.0;
+    const T sc = (T)scale;
+    T mx = T(0);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = threadIdx.x + k * blockDim.x;
+        if (e < nv) {
+            const T o = ok ? outv[k] * sc : outv[k];
+            dst[e] = o;
+            mx = fmax(mx, o);
+        }
+    }
+    if (threadIdx.x < 20 && mom_post) {
+        double v = 0;
+#pragma unroll
+        for (int k = 0; k < 20; ++k) v = (threadIdx.x == k) ? mm[k] : v;
+        mom_post[cell * 20 + threadIdx.x] = v * scale;
+    }
+    if (ok && threadIdx.x < 10) {
+        const double r = nV / nF;
+        double v = 0;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) v = (threadIdx.x == k) ? Uc[k] : v;
+        U[cell * 10 + threadIdx.x] = v * r;
+    }
+    if (counters) {
+        double c[1] = {(double)nclip};
+        block_sum<1>(c, red);
+        if (threadIdx.x == 0) {
+            if (c[0] > 0) atomicAdd(&counters[0], (unsigned long long)c[0]);
+            if (!ok) atomicAdd(&counters[1], 1ull);
+        }
+    }
+    if (max_out) block_max_to(mx, max_out);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+fit1_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* __restrict__ U,
+            double* __restrict__ mom_post, unsigned long long* __restrict__ counters, int nv, double vlo,
+            double dv, double mass, typename Bits<T>::U* __restrict__ max_out) {
+    extern __shared__ unsigned char smem_raw[];
+    T* g = reinterpret_cast<T*>(smem_raw);
+    __shared__ double red[5 * 4];
+    const long long cell = blockIdx.x;
+    const T* src = fin + cell * nv;
+    T* dst = fout + cell * nv;
+    const double nV = mom_pre[cell * 4 + 0];
+    const double Un = U[cell * 3 + 0], Unu = U[cell * 3 + 1], UP = U[cell * 3 + 2];
+    bool ok = nV > 1e-12 && Un > 1e-12;
+    double uV = 0, TV = 0, uF = 0, TF = 0;
+    if (ok) {
+        uV = mom_pre[cell * 4 + 1] / nV;
+        TV = (mom_pre[cell * 4 + 2] - mass * nV * uV * uV) / nV;
+        uF = Unu / Un;
+        TF = (UP - mass * Un * uF * uF) / Un;
+        ok = TV > 0.0 && TF > 0.0;
+    }
+    const T aV = (T)(0.5 * mass / TV), aF = (T)(0.5 * mass / TF);
+    double s[2] = {0.0, 0.0};
+    if (ok) {
+        for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+            const double v = vlo + (j + 0.5) * dv;
+            const T wv = (T)(v - uV), wf = (T)(v - uF);
+            s[0] += (double)expo<T>(-aV * wv * wv);
+            s[1] += (double)expo<T>(-aF * wf * wf);
+        }
+    }
+    block_sum<2>(s, red);
+    const T A = ok ? (T)(nV / (s[0] * dv)) : T(0);
+    const T Bc = ok ? (T)(nV / (s[1] * dv)) : T(0);
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+        T x = src[j];
+        if (ok) {
+            const double v = vlo + (j + 0.5) * dv;
+            const T wv = (T)(v - uV), wf = (T)(v - uF);
+            x = x - A * expo<T>(-aV * wv * wv) + Bc * expo<T>(-aF * wf * wf);
+            if (x < T(0)) acc[4] += 1.0;
+            x = fmax(x, T(0));
+        }
+        g[j] = x;
+        const double v = vlo + (j + 0.5) * dv;
+        const double xd = (double)x, xv = xd * v;
+        acc[0] += xd;
+        acc[1] += xv;
+        acc[2] += xv * v;
+        acc[3] += xv * v * v;
+    }
+    block_sum<5>(acc, red);
+    const double scale = ok ? nV / (acc[0] * dv) : 1.0;
+    const T sc = (T)scale;
+    T mx = T(0);
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+        const T o = ok ? g[j] * sc : g[j];
+        dst[j] = o;
+        mx = fmax(mx, o);
+    }
+    if (threadIdx.x == 0) {
+        if (mom_post) {
+            mom_post[cell * 4 + 0] = acc[0] * dv * scale;
+            mom_post[cell * 4 + 1] = acc[1] * dv * scale;
+            mom_post[cell * 4 + 2] = mass * acc[2] * dv * scale;
+            mom_post[cell * 4 + 3] = mass * acc[3] * dv * scale;
+        }
+        if (ok) {
+            const double r = nV / Un;
+            U[cell * 3 + 0] = Un * r;
+            U[cell * 3 + 1] = Unu * r;
+            U[cell * 3 + 2] = UP * r;
+        }
+        if (counters) {
+            if (acc[4] > 0) atomicAdd(&counters[0], (unsigned long long)acc[4]);
+            if (!ok) atomicAdd(&counters[1], 1ull);
+        }
+    }
+    if (max_out) block_max_to(mx, max_out);
+}
+
+// ------------------------------------------------------------ launchers ----
+static int threads_for(int work) {
+    int t = ((work + 63) / 64) * 64;
+    return t > 256 ? 256 : (t < 64 ? 64 : t);
+}
+
+template <class T>
+hipError_t launch_moments3(const T* f, double* mom, long long cells, const VGridArgs& a, hipStream_t st) {
+    VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m};
+    const size_t shm = sizeof(T) * (size_t)a.nv[0] * a.nv[1] * (a.nv[2] | 1);
+    hipLaunchKernelGGL((moments3_kernel<T>), dim3((unsigned)cells), dim3(threads_for(a.nv[0] * a.nv[1])), shm, st, f,
+                       mom, G);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, double vlo, double dv, double m,
+                           hipStream_t st) {
+    hipLaunchKernelGGL((moments1_kernel<T>), dim3((unsigned)cells), dim3(threads_for(nv)), 0, st, f, mom, nv, vlo, dv,
+                       m);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
+                       long long cells, const VGridArgs& a, void* max_out, hipStream_t st) {
+    VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m};
+    const int nv = a.nv[0] * a.nv[1] * a.nv[2];
+    const size_t shm = sizeof(T) * (size_t)a.nv[0] * a.nv[1] * (a.nv[2] | 1);
+    const int threads = 256;
+    const int ept = (nv + threads - 1) / threads;
+    auto* cnt = (unsigned long long*)counters;
+    auto* mo = (typename Bits<T>::U*)max_out;
+    if (ept <= 4)
+        hipLaunchKernelGGL((fit3_kernel<T, 4>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, mom_pre, U,
+                           mom_post, cnt, G, mo);
+    else if (ept <= 8)
+        hipLaunchKernelGGL((fit3_kernel<T, 8>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, mom_pre, U,
+                           mom_post, cnt, G, mo);
+    else if (ept <= 16)
+        hipLaunchKernelGGL((fit3_kernel<T, 16>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, mom_pre, U,
+                           mom_post, cnt, G, mo);
+    else if (ept <= 32)
+        hipLaunchKernelGGL((fit3_kernel<T, 32>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, mom_pre, U,
+                           mom_post, cnt, G, mo);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
+                       long long cells, int nv, double vlo, double dv, double m, void* max_out, hipStream_t st) {
+    hipLaunchKernelGGL((fit1_kernel<T>), dim3((unsigned)cells), dim3(threads_for(nv)), sizeof(T) * (size_t)nv, st,
+                       fin, fout, mom_pre, U, mom_post, (unsigned long long*)counters, nv, vlo, dv, m,
+                       (typename Bits<T>::U*)max_out);
+    return hipGetLastError();
+}
+
+#define VL_INST(T)                                                                                              \
+    template hipError_t launch_moments3<T>(const T*, double*, long long, const VGridArgs&, hipStream_t);         \
+    template hipError_t launch_moments1<T>(const T*, double*, long long, int, double, double, double,            \
+                                           hipStream_t);                                                        \
+    template hipError_t launch_fit3<T>(const T*, T*, const double*, double*, double*, void*, long long,         \
+                                       const VGridArgs&, void*, hipStream_t);                                   \
+    template hipError_t launch_fit1<T>(const T*, T*, const double*, double*, double*, void*, long long, int,    \
+                                       double, double, double, void*, hipStream_t);
+VL_INST(float)
+VL_INST(double)
+#undef VL_INST
+
+}  // namespace vl
+
+namespace vl {
+
+// ------------------------------------------------------------ diagnostics --
+// Deterministic two-level sums: block partials in a fixed order, then one
+// block adds the partials in index order.
+template <class T>
+__global__ void __launch_bounds__(256)
+partial_sum_kernel(const T* __restrict__ f, long long n, double* __restrict__ part) {
+    __shared__ double red[4];
+    double acc[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        acc[0] += (double)f[i];
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+__global__ void __launch_bounds__(256)
+energy_partial_kernel(const double* __restrict__ mom, long long cells, int kmom, int dimv, double* __restrict__ part) {
+    __shared__ double red[4];
+    double acc[1] = {0.0};
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (long long)gridDim.x * blockDim.x)
+        acc[0] += dimv == 3 ? 0.5 * (mom[c * kmom + 4] + mom[c * kmom + 7] + mom[c * kmom + 9]) : 0.5 * mom[c * kmom + 2];
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+__global__ void finish_sum_kernel(const double* __restrict__ part, int np, double scale, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < np; ++i) s += part[i];
+        *out = s * scale;
+    }
+}
+
+template <class T>
+hipError_t launch_mass_energy(const T* f, const double* mom, long long cells, long long nv, int kmom, int dimv,
+                              double dV, double dX, double* out, double* part, hipStream_t st) {
+    // out[0] = mass, out[1] = energy; part: 1024 doubles of scratch
+    const int np = 1024;
+    hipLaunchKernelGGL((partial_sum_kernel<T>), dim3(np), dim3(256), 0, st, f, cells * nv, part);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(64), 0, st, part, np, dV * dX, out);
+    hipLaunchKernelGGL(energy_partial_kernel, dim3(np), dim3(256), 0, st, mom, cells, kmom, dimv, part);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(64), 0, st, part, np, dX, out + 1);
+    return hipGetLastError();
+}
+
+template hipError_t launch_mass_energy<float>(const float*, const double*, long long, long long, int, int, double,
+                                              double, double*, double*, hipStream_t);
+template hipError_t launch_mass_energy<double>(const double*, const double*, long long, long long, int, int, double,
+                                               double, double*, double*, hipStream_t);
+
+}  // namespace vl

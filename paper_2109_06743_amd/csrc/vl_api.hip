@@ -1,0 +1,644 @@
+// C ABI of the moment-fitting Vlasov hot path (include/vl.h): host-side
+// validation, dispatch on the storage type of f, and the orchestration of the
+// full time step (Algorithm 1 of arXiv 2109.06743) as a sequence of kernel
+// launches on one stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "vl_internal.h"
+
+struct vl_timer {
+    hipEvent_t start, stop;
+    int cat;
+};
+
+struct vl_ctx {
+    vl_config cfg;
+    int device = -1;
+    // kernel timing (vl_timing_enable / vl_timing_read)
+    bool timing = false;
+    std::vector<vl_timer> pending;
+    std::vector<hipEvent_t> pool;
+    double t_ms[VL_T_COUNT] = {0};
+    int64_t t_cnt[VL_T_COUNT] = {0};
+    // device scratch: kSlots maxima per species, then the DFT coefficients,
+    // then the diagnostics partials
+    unsigned long long* slots = nullptr;
+    double* dft = nullptr;
+    double* part = nullptr;
+    long long cells = 0;
+    long long nv[VL_MAX_SPECIES] = {0, 0};
+    char err[512] = {0};
+};
+
+namespace {
+
+constexpr int kSlots = 4;   // A: input of the step, B: after first X, C: after V, S: standalone
+constexpr int kPartials = 1024;
+
+vl_status fail(vl_ctx* c, vl_status st, const char* fmt, ...) {
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return st;
+}
+
+#define VL_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(ctx, VL_EHIP, "%s: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+hipEvent_t take_event(vl_ctx* c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets the launches issued during its lifetime with events on `st` when
+// timing is enabled on the context.
+struct Timed {
+    vl_ctx* c;
+    hipStream_t st;
+    vl_timer t{};
+    bool on;
+    Timed(vl_ctx* c_, int cat, hipStream_t st_) : c(c_), st(st_), on(c_->timing) {
+        if (!on) return;
+        t.cat = cat;
+        t.start = take_event(c);
+        t.stop = take_event(c);
+        on = t.start && t.stop;
+        if (on) (void)hipEventRecord(t.start, st);
+    }
+    ~Timed() {
+        if (!on) return;
+        (void)hipEventRecord(t.stop, st);
+        c->pending.push_back(t);
+    }
+};
+
+double dx_of(const vl_config& c) { return (c.x_hi - c.x_lo) / c.nx; }
+double dy_of(const vl_config& c) { return c.dim_x == 2 ? (c.y_hi - c.y_lo) / c.ny : 1.0; }
+double dv_of(const vl_species& s, int d) { return (s.v_hi[d] - s.v_lo[d]) / s.nv[d]; }
+
+unsigned long long* slot(vl_ctx* c, int which, int s) { return c->slots + which * VL_MAX_SPECIES + s; }
+
+vl_status ensure_device(vl_ctx* ctx) {
+    int dev = -1;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(ctx, VL_EDEVICE, "no HIP device");
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ctx, VL_EDEVICE, "hipGetDevice failed");
+    if (ctx->slots && ctx->device == dev) return VL_OK;
+    if (ctx->slots && ctx->device != dev)
+        return fail(ctx, VL_EDEVICE, "context was first used on device %d, current device is %d", ctx->device, dev);
+    const size_t bytes = sizeof(unsigned long long) * kSlots * VL_MAX_SPECIES +
+                         sizeof(double) * (2 * (size_t)ctx->cfg.nx + 2 + kPartials);
+    void* p = nullptr;
+    VL_HIP(hipMalloc(&p, bytes));
+    VL_HIP(hipMemset(p, 0, bytes));
+    ctx->slots = (unsigned long long*)p;
+    ctx->dft = (double*)(ctx->slots + kSlots * VL_MAX_SPECIES);
+    ctx->part = ctx->dft + 2 * (size_t)ctx->cfg.nx + 2;
+    ctx->device = dev;
+    return VL_OK;
+}
+
+vl_status check_species(vl_ctx* ctx, int32_t s) {
+    if (!ctx) return VL_EINVAL;
+    if (s < 0 || s >= ctx->cfg.nspecies) return fail(ctx, VL_EINVAL, "species index %d out of range", s);
+    return VL_OK;
+}
+
+size_t yee_doubles(const vl_config& c) {
+    return c.dim_x == 2 ? (size_t)c.nx * (3 * (size_t)c.ny + 3 * ((size_t)c.ny + 1)) : 0;
+}
+
+size_t fluid_doubles(const vl_config& c) {
+    const size_t cells = (size_t)c.nx * c.ny;
+    if (c.dim_v == 3) return 30 * cells + 10 * (size_t)c.nx * (c.ny + 1);
+    return 9 * (size_t)c.nx;
+}
+
+size_t step_doubles(const vl_config& c) {
+    const size_t cells = (size_t)c.nx * c.ny;
+    if (c.dim_v == 3) return yee_doubles(c) + 18 * cells + fluid_doubles(c);
+    return 4 * (size_t)c.nx + 3 * (size_t)c.nx + fluid_doubles(c);
+}
+
+// ------------------------------------------------------------ typed paths --
+template <class T>
+vl_status advect_x_typed(vl_ctx* ctx, int s, const T* fin, T* fout, T* fwork, double tau, const void* finf,
+                         void* max_x, void* max_y, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const vl_species& sp = c.sp[s];
+    if (c.dim_x == 1) {
+        Timed tm(ctx, VL_T_PFC_X, st);
+        VL_HIP((vl::launch_pfc_x<T>(fin, fout, 1, c.nx, sp.nv[0], 1, sp.v_lo[0], dv_of(sp, 0), tau / dx_of(c), finf,
+                                    max_x, st)));
+        return VL_OK;
+    }
+    const int inner = sp.nv[1] * sp.nv[2];
+    {
+        Timed tm(ctx, VL_T_PFC_X, st);
+        VL_HIP((vl::launch_pfc_x<T>(fin, fwork, c.ny, c.nx, ctx->nv[s], inner, sp.v_lo[0], dv_of(sp, 0), tau / dx_of(c),
+                                finf, nullptr, st)));
+    }
+    Timed tm(ctx, VL_T_PFC_Y, st);
+    VL_HIP((vl::launch_pfc_y<T>(fwork, fout, c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2], sp.v_lo[1], dv_of(sp, 1),
+                                tau / dy_of(c), finf, max_y, st)));
+    return VL_OK;
+}
+
+template <class T>
+vl_status advect_v_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double* E, const double* B, double tau,
+                         const void* finf, void* max_out, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const vl_species& sp = c.sp[s];
+    Timed tm(ctx, VL_T_PFC_V, st);
+    if (c.dim_v == 1) {
+        VL_HIP((vl::launch_pfc_v1<T>(fin, fout, c.nx, sp.nv[0], E, sp.q / sp.m * tau / dv_of(sp, 0), finf, max_out,
+                                     st)));
+        return VL_OK;
+    }
+    vl::V3Params P;
+    P.nvx = sp.nv[0];
+    P.nvy = sp.nv[1];
+    P.nvz = sp.nv[2];
+    for (int d = 0; d < 3; ++d) {
+        P.lo[d] = sp.v_lo[d];
+        P.dv[d] = dv_of(sp, d);
+    }
+    P.qm = sp.q / sp.m;
+    P.tau = tau;
+    VL_HIP((vl::launch_pfc_v3<T>(fin, fout, ctx->cells, E, B, P, finf, max_out, st)));
+    return VL_OK;
+}
+
+vl::VGridArgs grid_args(const vl_species& sp) {
+    vl::VGridArgs a;
+    for (int d = 0; d < 3; ++d) {
+        a.nv[d] = sp.nv[d];
+        a.lo[d] = sp.v_lo[d];
+        a.dv[d] = dv_of(sp, d);
+    }
+    a.m = sp.m;
+    return a;
+}
+
+template <class T>
+vl_status moments_typed(vl_ctx* ctx, int s, const T* f, double* mom, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const vl_species& sp = c.sp[s];
+    Timed tm(ctx, VL_T_MOMENTS, st);
+    if (c.dim_v == 1)
+        VL_HIP((vl::launch_moments1<T>(f, mom, ctx->cells, sp.nv[0], sp.v_lo[0], dv_of(sp, 0), sp.m, st)));
+    else
+        VL_HIP((vl::launch_moments3<T>(f, mom, ctx->cells, grid_args(sp), st)));
+    return VL_OK;
+}
+
+template <class T>
+vl_status fit_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post,
+                    int64_t* counters, void* max_out, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const vl_species& sp = c.sp[s];
+    Timed tm(ctx, VL_T_FIT, st);
+    if (c.dim_v == 1)
+        VL_HIP((vl::launch_fit1<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, sp.nv[0], sp.v_lo[0],
+                                   dv_of(sp, 0), sp.m, max_out, st)));
+    else
+        VL_HIP((vl::launch_fit3<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, grid_args(sp), max_out,
+                                   st)));
+    return VL_OK;
+}
+
+template <class T>
+vl_status array_max_typed(vl_ctx* ctx, int s, const T* f, void* out, hipStream_t st) {
+    Timed tm(ctx, VL_T_MAX, st);
+    VL_HIP((vl::launch_array_max<T>(f, ctx->cells * ctx->nv[s], out, st)));
+    return VL_OK;
+}
+
+vl_status fluid_step_impl(vl_ctx* ctx, int s, double* U, const double* mom_t, const double* mom_t1, const double* E_t,
+                          const double* B_t, const double* E_t1, const double* B_t1, const double* E_th,
+                          const double* B_th, double dt, double* work, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const vl_species& sp = c.sp[s];
+    Timed tm(ctx, VL_T_FLUID, st);
+    if (c.dim_v == 3)
+        VL_HIP(vl::launch_fluid_rk3_3v(U, mom_t, mom_t1, E_t, B_t, E_t1, B_t1, E_th, B_th, dt, c.nx, c.ny, sp.q, sp.m,
+                                       dx_of(c), dy_of(c), work, st));
+    else
+        VL_HIP(vl::launch_fluid_rk3_1v(U, mom_t, mom_t1, E_t, E_t1, E_th, dt, c.nx, sp.q, sp.m, dx_of(c), work, st));
+    return VL_OK;
+}
+
+#define DISPATCH(ctx, call_f32, call_f64) ((ctx)->cfg.f_dtype == VL_F32 ? (call_f32) : (call_f64))
+
+template <class T>
+vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const int ns = c.nspecies;
+    const double q[2] = {c.sp[0].q, ns > 1 ? c.sp[1].q : 0.0};
+    vl_status r;
+    for (int s = 0; s < ns; ++s)
+        if (!S->f_max_valid)
+            if ((r = array_max_typed<T>(ctx, s, (const T*)S->f[s], slot(ctx, 0, s), st)) != VL_OK) return r;
+
+    if (c.dim_x == 2) {
+        const long long cells = ctx->cells;
+        const size_t ny1 = yee_doubles(c);
+        double* yee_t = S->work;
+        double* E_t = yee_t + ny1;
+        double* B_t = E_t + 3 * cells;
+        double* E_h = B_t + 3 * cells;
+        double* B_h = E_h + 3 * cells;
+        double* E_1 = B_h + 3 * cells;
+        double* B_1 = E_1 + 3 * cells;
+        double* fwork = B_1 + 3 * cells;
+        {
+            Timed tm(ctx, VL_T_FIELDS, st);
+            if (c.fit) {
+                VL_HIP(hipMemcpyAsync(yee_t, S->fields, ny1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+                VL_HIP(vl::launch_cell_fields(yee_t, c.nx, c.ny, E_t, B_t, st));
+            }
+            const double* mom_t[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
+            VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t, q, ns, dt, c.c, dx_of(c), dy_of(c), st));
+            VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, st));
+            if (c.fit) {
+                VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 3 * cells, st));
+                VL_HIP(vl::launch_axpby(B_h, B_t, 2.0, -1.0, B_1, 3 * cells, st));
+            }
+        }
+        for (int s = 0; s < ns; ++s) {
+            T* f = (T*)S->f[s];
+            T* tmp = (T*)S->f_tmp[s];
+            VL_HIP(vl::launch_fill_u64(slot(ctx, 1, s), 1, 0ull, st));
+            VL_HIP(vl::launch_fill_u64(slot(ctx, 2, s), 1, 0ull, st));
+            if ((r = advect_x_typed<T>(ctx, s, f, f, tmp, 0.5 * dt, slot(ctx, 0, s), nullptr, slot(ctx, 1, s), st)) !=
+                VL_OK)
+                return r;
+            VL_HIP(vl::launch_fill_u64(slot(ctx, 0, s), 1, 0ull, st));
+            if ((r = advect_v_typed<T>(ctx, s, f, f, E_h, B_h, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) != VL_OK)
+                return r;
+            if ((r = advect_x_typed<T>(ctx, s, f, f, tmp, 0.5 * dt, slot(ctx, 2, s), nullptr,
+                                       c.fit ? nullptr : slot(ctx, 0, s), st)) != VL_OK)
+                return r;
+            if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
+            if (c.fit) {
+                if ((r = fluid_step_impl(ctx, s, S->U[s], S->mom_post[s], S->mom_pre[s], E_t, B_t, E_1, B_1, E_h, B_h,
+                                         dt, fwork, st)) != VL_OK)
+                    return r;
+                if ((r = fit_typed<T>(ctx, s, f, f, S->mom_pre[s], S->U[s], S->mom_post[s], S->counters,
+                                      slot(ctx, 0, s), st)) != VL_OK)
+                    return r;
+            } else {
+                Timed tm(ctx, VL_T_COPY, st);
+                VL_HIP(hipMemcpyAsync(S->mom_post[s], S->mom_pre[s], cells * 20 * sizeof(double),
+                                      hipMemcpyDeviceToDevice, st));
+            }
+        }
+        const double* mom_t1[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
+        Timed tm(ctx, VL_T_FIELDS, st);
+        VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t1, q, ns, dt, c.c, dx_of(c), dy_of(c), st));
+    } else {
+        const int nx = c.nx;
+        double* mom_half = S->work;
+        double* E_t = mom_half + 4 * nx;
+        double* E_t1 = E_t + nx;
+        double* E_th = E_t1 + nx;
+        double* fwork = E_th + nx;
+        const int s = 0;
+        T* f = (T*)S->f[s];
+        T* tmp = (T*)S->f_tmp[s];
+        const double L = c.x_hi - c.x_lo;
+        VL_HIP(vl::launch_fill_u64(slot(ctx, 1, s), 1, 0ull, st));
+        VL_HIP(vl::launch_fill_u64(slot(ctx, 2, s), 1, 0ull, st));
+        if ((r = advect_x_typed<T>(ctx, s, f, tmp, nullptr, 0.5 * dt, slot(ctx, 0, s), slot(ctx, 1, s), nullptr, st)) !=
+            VL_OK)
+            return r;
+        VL_HIP(vl::launch_fill_u64(slot(ctx, 0, s), 1, 0ull, st));
+        if ((r = moments_typed<T>(ctx, s, tmp, mom_half, st)) != VL_OK) return r;
+        {
+            Timed tm(ctx, VL_T_FIELDS, st);
+            VL_HIP(vl::launch_poisson(mom_half, nx, L, c.sp[0].q, ctx->dft, S->fields, st));
+        }
+        if ((r = advect_v_typed<T>(ctx, s, tmp, tmp, S->fields, nullptr, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) !=
+            VL_OK)
+            return r;
+        if ((r = advect_x_typed<T>(ctx, s, tmp, f, nullptr, 0.5 * dt, slot(ctx, 2, s),
+                                   c.fit ? nullptr : slot(ctx, 0, s), nullptr, st)) != VL_OK)
+            return r;
+        if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
+        if (c.fit) {
+            {
+                Timed tm(ctx, VL_T_FIELDS, st);
+                VL_HIP(vl::launch_poisson(S->mom_post[s], nx, L, c.sp[0].q, ctx->dft, E_t, st));
+                VL_HIP(vl::launch_poisson(S->mom_pre[s], nx, L, c.sp[0].q, ctx->dft, E_t1, st));
+                VL_HIP(vl::launch_axpby(E_t, E_t1, 0.5, 0.5, E_th, nx, st));
+            }
+            if ((r = fluid_step_impl(ctx, s, S->U[s], S->mom_post[s], S->mom_pre[s], E_t, nullptr, E_t1, nullptr, E_th,
+                                     nullptr, dt, fwork, st)) != VL_OK)
+                return r;
+            if ((r = fit_typed<T>(ctx, s, f, f, S->mom_pre[s], S->U[s], S->mom_post[s], S->counters, slot(ctx, 0, s),
+                                  st)) != VL_OK)
+                return r;
+        } else {
+            Timed tm(ctx, VL_T_COPY, st);
+            VL_HIP(hipMemcpyAsync(S->mom_post[s], S->mom_pre[s], (size_t)nx * 4 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+        }
+    }
+    S->f_max_valid = 1;
+    return VL_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI ==
+extern "C" {
+
+const char* vl_version(void) { return "vl 0.1 gfx950"; }
+
+const char* vl_status_str(vl_status st) {
+    switch (st) {
+        case VL_OK: return "ok";
+        case VL_EINVAL: return "invalid argument";
+        case VL_EALIAS: return "output aliases an input";
+        case VL_ENOTSUP: return "not supported";
+        case VL_EDEVICE: return "no usable device";
+        case VL_EHIP: return "HIP runtime error";
+        case VL_ENUMERIC: return "non-finite values";
+    }
+    return "unknown status";
+}
+
+const char* vl_last_error(const vl_ctx* ctx) { return ctx ? ctx->err : "null context"; }
+
+vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
+    if (!cfg || !out) return VL_EINVAL;
+    *out = nullptr;
+    const vl_config& c = *cfg;
+    if (!((c.dim_x == 1 && c.dim_v == 1) || (c.dim_x == 2 && c.dim_v == 3))) return VL_ENOTSUP;
+    if (c.nx < 1 || c.nx > (1 << 24) || c.ny < 1 || c.ny > (1 << 24)) return VL_EINVAL;
+    if (c.dim_x == 1 && c.ny != 1) return VL_EINVAL;
+    if (c.dim_x == 2 && c.ny < 2) return VL_EINVAL;   // the wall ghosts mirror two interior rows
+    if (!(std::isfinite(c.x_lo) && std::isfinite(c.x_hi) && c.x_hi > c.x_lo)) return VL_EINVAL;
+    if (c.dim_x == 2 && !(std::isfinite(c.y_lo) && std::isfinite(c.y_hi) && c.y_hi > c.y_lo)) return VL_EINVAL;
+    if (c.dim_x == 2 && c.bc_y != VL_BC_REFLECT) return VL_ENOTSUP;
+    if (c.nspecies < 1 || c.nspecies > VL_MAX_SPECIES) return VL_EINVAL;
+    if (c.dim_x == 1 && c.nspecies != 1) return VL_ENOTSUP;
+    if (c.f_dtype != VL_F32 && c.f_dtype != VL_F64) return VL_EINVAL;
+    if (c.dim_x == 2 && !finite_pos(c.c)) return VL_EINVAL;
+    if (c.fit != 0 && c.fit != 1) return VL_EINVAL;
+    if (c.closure != VL_CLOSURE_KINETIC) return VL_ENOTSUP;
+    const size_t elem = c.f_dtype == VL_F32 ? 4 : 8;
+    for (int s = 0; s < c.nspecies; ++s) {
+        const vl_species& sp = c.sp[s];
+        if (!finite_pos(sp.m) || !std::isfinite(sp.q)) return VL_EINVAL;
+        const int nd = c.dim_v;
+        for (int d = 0; d < 3; ++d) {
+            if (d < nd) {
+                if (sp.nv[d] < 2 || !(std::isfinite(sp.v_lo[d]) && std::isfinite(sp.v_hi[d]) && sp.v_hi[d] > sp.v_lo[d]))
+                    return VL_EINVAL;
+            } else if (sp.nv[d] != 1) {
+                return VL_EINVAL;
+            }
+        }
+        if (nd == 1 && sp.nv[0] > 4096) return VL_ENOTSUP;
+        if (nd == 3) {
+            for (int d = 0; d < 3; ++d)
+                if (sp.nv[d] > 32) return VL_ENOTSUP;
+            if ((long long)sp.nv[0] * sp.nv[1] * sp.nv[2] > 8192) return VL_ENOTSUP;
+            if (vl::v3_shared_bytes(sp.nv[0], sp.nv[1], sp.nv[2], elem) > 64 * 1024) return VL_ENOTSUP;
+            // reflecting walls pair v_y with -v_y: the v_y grid must be symmetric about 0
+            if (std::fabs(sp.v_lo[1] + sp.v_hi[1]) > 1e-12 * std::fabs(sp.v_hi[1])) return VL_EINVAL;
+        }
+    }
+    vl_ctx* ctx = new (std::nothrow) vl_ctx;
+    if (!ctx) return VL_EINVAL;
+    ctx->cfg = c;
+    ctx->cells = (long long)c.nx * c.ny;
+    for (int s = 0; s < c.nspecies; ++s) ctx->nv[s] = (long long)c.sp[s].nv[0] * c.sp[s].nv[1] * c.sp[s].nv[2];
+    *out = ctx;
+    return VL_OK;
+}
+
+vl_status vl_destroy(vl_ctx* ctx) {
+    if (!ctx) return VL_EINVAL;
+    for (const vl_timer& t : ctx->pending) {
+        (void)hipEventSynchronize(t.stop);
+        ctx->pool.push_back(t.start);
+        ctx->pool.push_back(t.stop);
+    }
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->slots) (void)hipFree(ctx->slots);
+    delete ctx;
+    return VL_OK;
+}
+
+vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, void* f_work, double tau,
+                          vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (!f_in || !f_out) return fail(ctx, VL_EINVAL, "null f");
+    if (ctx->cfg.dim_x == 2 && !f_work) return fail(ctx, VL_EINVAL, "2X3V needs f_work");
+    if (!finite_pos(tau)) return fail(ctx, VL_EINVAL, "tau must be finite and > 0");
+    if (f_out == f_in || (f_work && (f_work == f_in || f_work == f_out)))
+        return fail(ctx, VL_EALIAS, "f_out/f_work alias");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    void* S = slot(ctx, 3, s);
+    if (ctx->cfg.f_dtype == VL_F32) {
+        if ((r = array_max_typed<float>(ctx, s, (const float*)f_in, S, st)) != VL_OK) return r;
+        return advect_x_typed<float>(ctx, s, (const float*)f_in, (float*)f_out, (float*)f_work, tau, S, nullptr,
+                                     nullptr, st);
+    }
+    if ((r = array_max_typed<double>(ctx, s, (const double*)f_in, S, st)) != VL_OK) return r;
+    return advect_x_typed<double>(ctx, s, (const double*)f_in, (double*)f_out, (double*)f_work, tau, S, nullptr,
+                                  nullptr, st);
+}
+
+vl_status vl_pfc_advect_v(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, const double* E, const double* B,
+                          double tau, vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (!f_in || !f_out || !E) return fail(ctx, VL_EINVAL, "null argument");
+    if (!finite_pos(tau)) return fail(ctx, VL_EINVAL, "tau must be finite and > 0");
+    if (f_out == f_in) return fail(ctx, VL_EALIAS, "f_out aliases f_in");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    void* S = slot(ctx, 3, s);
+    if (ctx->cfg.f_dtype == VL_F32) {
+        if ((r = array_max_typed<float>(ctx, s, (const float*)f_in, S, st)) != VL_OK) return r;
+        return advect_v_typed<float>(ctx, s, (const float*)f_in, (float*)f_out, E, B, tau, S, nullptr, st);
+    }
+    if ((r = array_max_typed<double>(ctx, s, (const double*)f_in, S, st)) != VL_OK) return r;
+    return advect_v_typed<double>(ctx, s, (const double*)f_in, (double*)f_out, E, B, tau, S, nullptr, st);
+}
+
+vl_status vl_moments(vl_ctx* ctx, int32_t s, const void* f, double* mom, vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (!f || !mom) return fail(ctx, VL_EINVAL, "null argument");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(ctx, moments_typed<float>(ctx, s, (const float*)f, mom, st),
+                    moments_typed<double>(ctx, s, (const double*)f, mom, st));
+}
+
+vl_status vl_moment_fit(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, const double* mom_pre, double* U,
+                        double* mom_post, int64_t* counters, vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (!f_in || !f_out || !mom_pre || !U) return fail(ctx, VL_EINVAL, "null argument");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(ctx,
+                    fit_typed<float>(ctx, s, (const float*)f_in, (float*)f_out, mom_pre, U, mom_post, counters,
+                                     nullptr, st),
+                    fit_typed<double>(ctx, s, (const double*)f_in, (double*)f_out, mom_pre, U, mom_post, counters,
+                                      nullptr, st));
+}
+
+vl_status vl_poisson(vl_ctx* ctx, const double* mom, double* E, vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    if (ctx->cfg.dim_x != 1) return fail(ctx, VL_ENOTSUP, "Poisson solver is the 1X1V field solver");
+    if (!mom || !E) return fail(ctx, VL_EINVAL, "null argument");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    VL_HIP(vl::launch_poisson(mom, ctx->cfg.nx, ctx->cfg.x_hi - ctx->cfg.x_lo, ctx->cfg.sp[0].q, ctx->dft, E,
+                              (hipStream_t)stream));
+    return VL_OK;
+}
+
+size_t vl_yee_size(const vl_ctx* ctx) { return ctx ? yee_doubles(ctx->cfg) : 0; }
+size_t vl_fluid_work_size(const vl_ctx* ctx) { return ctx ? fluid_doubles(ctx->cfg) : 0; }
+size_t vl_step_work_size(const vl_ctx* ctx) { return ctx ? step_doubles(ctx->cfg) : 0; }
+
+vl_status vl_maxwell_half_step(vl_ctx* ctx, double* yee, const double* const* mom, double dt, vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    const vl_config& c = ctx->cfg;
+    if (c.dim_x != 2) return fail(ctx, VL_ENOTSUP, "Maxwell solver is the 2X3V field solver");
+    if (!yee || !mom) return fail(ctx, VL_EINVAL, "null argument");
+    for (int s = 0; s < c.nspecies; ++s)
+        if (!mom[s]) return fail(ctx, VL_EINVAL, "null moment array");
+    if (!finite_pos(dt)) return fail(ctx, VL_EINVAL, "dt must be finite and > 0");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    const double q[2] = {c.sp[0].q, c.nspecies > 1 ? c.sp[1].q : 0.0};
+    VL_HIP(vl::launch_maxwell_half(yee, c.nx, c.ny, mom, q, c.nspecies, dt, c.c, dx_of(c), dy_of(c),
+                                   (hipStream_t)stream));
+    return VL_OK;
+}
+
+vl_status vl_cell_fields(vl_ctx* ctx, const double* yee, double* E, double* B, vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    if (ctx->cfg.dim_x != 2) return fail(ctx, VL_ENOTSUP, "Yee fields exist in 2X3V only");
+    if (!yee || !E || !B) return fail(ctx, VL_EINVAL, "null argument");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    VL_HIP(vl::launch_cell_fields(yee, ctx->cfg.nx, ctx->cfg.ny, E, B, (hipStream_t)stream));
+    return VL_OK;
+}
+
+vl_status vl_fluid_step(vl_ctx* ctx, int32_t s, double* U, const double* mom_t, const double* mom_t1,
+                        const double* E_t, const double* B_t, const double* E_t1, const double* B_t1,
+                        const double* E_th, const double* B_th, double dt, double* work, vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (!U || !mom_t || !mom_t1 || !E_t || !E_t1 || !E_th || !work) return fail(ctx, VL_EINVAL, "null argument");
+    if (ctx->cfg.dim_v == 3 && (!B_t || !B_t1 || !B_th)) return fail(ctx, VL_EINVAL, "3V fluid needs B");
+    if (!finite_pos(dt)) return fail(ctx, VL_EINVAL, "dt must be finite and > 0");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    return fluid_step_impl(ctx, s, U, mom_t, mom_t1, E_t, B_t, E_t1, B_t1, E_th, B_th, dt, work, (hipStream_t)stream);
+}
+
+vl_status vl_step(vl_ctx* ctx, vl_state* S, double dt, vl_stream stream) {
+    if (!ctx || !S) return VL_EINVAL;
+    const vl_config& c = ctx->cfg;
+    if (!finite_pos(dt)) return fail(ctx, VL_EINVAL, "dt must be finite and > 0");
+    if (!S->fields || !S->work) return fail(ctx, VL_EINVAL, "null fields/work");
+    for (int s = 0; s < c.nspecies; ++s) {
+        if (!S->f[s] || !S->f_tmp[s] || !S->mom_post[s] || !S->mom_pre[s])
+            return fail(ctx, VL_EINVAL, "null buffer for species %d", s);
+        if (c.fit && !S->U[s]) return fail(ctx, VL_EINVAL, "fit needs U[%d]", s);
+        if (S->f[s] == S->f_tmp[s]) return fail(ctx, VL_EALIAS, "f and f_tmp alias");
+        if (S->mom_pre[s] == S->mom_post[s]) return fail(ctx, VL_EALIAS, "mom_pre and mom_post alias");
+    }
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(ctx, step_typed<float>(ctx, S, dt, st), step_typed<double>(ctx, S, dt, st));
+}
+
+vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mom, double* out, vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (!f || !mom || !out) return fail(ctx, VL_EINVAL, "null argument");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    const vl_config& c = ctx->cfg;
+    const vl_species& sp = c.sp[s];
+    double dV = 1.0;
+    for (int d = 0; d < c.dim_v; ++d) dV *= dv_of(sp, d);
+    const double dX = dx_of(c) * dy_of(c);
+    const int kmom = c.dim_v == 3 ? 20 : 4;
+    hipStream_t st = (hipStream_t)stream;
+    if (c.f_dtype == VL_F32)
+        VL_HIP(vl::launch_mass_energy<float>((const float*)f, mom, ctx->cells, ctx->nv[s], kmom, c.dim_v, dV, dX, out,
+                                             ctx->part, st));
+    else
+        VL_HIP(vl::launch_mass_energy<double>((const double*)f, mom, ctx->cells, ctx->nv[s], kmom, c.dim_v, dV, dX,
+                                              out, ctx->part, st));
+    return VL_OK;
+}
+
+vl_status vl_timing_enable(vl_ctx* ctx, int32_t on) {
+    if (!ctx) return VL_EINVAL;
+    ctx->timing = on != 0;
+    return VL_OK;
+}
+
+vl_status vl_timing_read(vl_ctx* ctx, double* ms, int64_t* count) {
+    if (!ctx || !ms || !count) return VL_EINVAL;
+    for (const vl_timer& t : ctx->pending) {
+        VL_HIP(hipEventSynchronize(t.stop));
+        float e = 0.f;
+        VL_HIP(hipEventElapsedTime(&e, t.start, t.stop));
+        ctx->t_ms[t.cat] += e;
+        ctx->t_cnt[t.cat] += 1;
+        ctx->pool.push_back(t.start);
+        ctx->pool.push_back(t.stop);
+    }
+    ctx->pending.clear();
+    for (int k = 0; k < VL_T_COUNT; ++k) {
+        ms[k] = ctx->t_ms[k];
+        count[k] = ctx->t_cnt[k];
+        ctx->t_ms[k] = 0.0;
+        ctx->t_cnt[k] = 0;
+    }
+    return VL_OK;
+}
+
+vl_status vl_sync(vl_ctx* ctx, vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    VL_HIP(hipStreamSynchronize((hipStream_t)stream));
+    VL_HIP(hipGetLastError());
+    return VL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal interface between the C ABI (vl_api.hip) and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/vl.h"
+#include "vl_common.h"
+
+namespace vl {
+
+struct VGridArgs {
+    int nv[3];
+    double lo[3], dv[3];
+    double m;
+};
+
+struct V3Params;  // pfc_kernels.hip
+
+template <class T>
+hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, int inner, double vx_lo, double dvx,
+                        double tau_dx, const void* finf, void* max_out, hipStream_t st);
+template <class T>
+hipError_t launch_pfc_y(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vy_lo, double dvy,
+                        double tau_dy, const void* finf, void* max_out, hipStream_t st);
+template <class T>
+hipError_t launch_pfc_v1(const T* fin, T* fout, int nx, int nv, const double* E, double qm_tau_dv, const void* finf,
+                         void* max_out, hipStream_t st);
+struct V3Params {
+    int nvx, nvy, nvz;
+    double lo[3], dv[3];
+    double qm, tau;
+};
+template <class T>
+hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E, const double* B, const V3Params& P,
+                         const void* finf, void* max_out, hipStream_t st);
+size_t v3_shared_bytes(int nvx, int nvy, int nvz, size_t elem);
+template <class T>
+hipError_t launch_array_max(const T* f, long long n, void* out, hipStream_t st);
+hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st);
+
+template <class T>
+hipError_t launch_moments3(const T* f, double* mom, long long cells, const VGridArgs& a, hipStream_t st);
+template <class T>
+hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, double vlo, double dv, double m,
+                           hipStream_t st);
+template <class T>
+hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
+                       long long cells, const VGridArgs& a, void* max_out, hipStream_t st);
+template <class T>
+hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
+                       long long cells, int nv, double vlo, double dv, double m, void* max_out, hipStream_t st);
+
+hipError_t launch_poisson(const double* mom, int N, double L, double q, double* ab, double* E, hipStream_t st);
+hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
+                               double dt, double c, double dx, double dy, hipStream_t st);
+hipError_t launch_cell_fields(const double* yee, int nx, int ny, double* E, double* B, hipStream_t st);
+hipError_t launch_axpby(const double* x, const double* y, double a, double b, double* out, long long n,
+                        hipStream_t st);
+
+hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom_t1, const double* E_t,
+                               const double* B_t, const double* E_t1, const double* B_t1, const double* E_th,
+                               const double* B_th, double dt, int nx, int ny, double q, double m, double dx,
+                               double dy, double* work, hipStream_t st);
+hipError_t launch_fluid_rk3_1v(double* U, const double* mom_t, const double* mom_t1, const double* E_t,
+                               const double* E_t1, const double* E_th, double dt, int nx, double q, double m,
+                               double dx, double* work, hipStream_t st);
+
+template <class T>
+hipError_t launch_mass_energy(const T* f, const double* mom, long long cells, long long nv, int kmom, int dimv,
+                              double dV, double dX, double* out, double* part, hipStream_t st);
+
+}  // namespace vl

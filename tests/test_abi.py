@@ -1,0 +1,97 @@
+"""The C-ABI library loads, exports every function include/vl.h declares, and
+rejects bad arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2109_06743_amd import build as B
+from paper_2109_06743_amd import vl, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB):
+        B.build()
+    return vl.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15, names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(vl.EXPORTS) <= set(names)
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.vl_status_str(code)
+    assert b"gfx950" in lib.vl_version()
+
+
+def _create(cfg, dtype="f32"):
+    c = vl.make_config(cfg, dtype)
+    h = ctypes.c_void_p()
+    st = vl.load().vl_create(ctypes.byref(c), ctypes.byref(h))
+    return st, h
+
+
+def test_create_validates_on_host(lib):
+    cfg, _ = workloads.landau(nx=16, nv=16)
+    st, h = _create(cfg)
+    assert st == 0 and h.value
+    assert lib.vl_yee_size(h) == 0
+    assert lib.vl_step_work_size(h) > 0
+    assert lib.vl_destroy(h) == 0
+    bad = dict(cfg, nx=0)
+    assert _create(bad)[0] == 1
+    bad = dict(cfg, v_hi=cfg["v_lo"])
+    assert _create(bad)[0] == 1
+    bad = dict(cfg, m=-1.0)
+    assert _create(bad)[0] == 1
+
+
+def test_create_2x3v_checks(lib):
+    cfg, _, _ = workloads.gem(nx=4, ny=2, nv=4, dtype="float64")
+    st, h = _create(cfg, "f64")
+    assert st == 0
+    assert lib.vl_yee_size(h) == 4 * (3 * 2 + 3 * 3)
+    lib.vl_destroy(h)
+    sp = [dict(s) for s in cfg["species"]]
+    sp[0]["v_lo"] = [-1.0, -2.0, -1.0]          # v_y grid not symmetric: reflecting walls impossible
+    assert _create(dict(cfg, species=sp))[0] == 1
+    sp = [dict(s) for s in cfg["species"]]
+    sp[1]["nv"] = [40, 4, 4]                    # longer pencils than the velocity kernel supports
+    assert _create(dict(cfg, species=sp))[0] == 3
+
+
+def test_entry_points_reject_bad_arguments_before_device_use(lib):
+    cfg, _ = workloads.landau(nx=16, nv=16)
+    st, h = _create(cfg)
+    p = ctypes.c_void_p(0x1000)                 # never dereferenced: validation fails first
+    q = ctypes.c_void_p(0x2000)
+    assert lib.vl_pfc_advect_x(h, 0, None, p, None, 0.1, None) == 1
+    assert lib.vl_pfc_advect_x(h, 0, p, q, None, -0.1, None) == 1
+    assert lib.vl_pfc_advect_x(h, 0, p, q, None, float("nan"), None) == 1
+    assert lib.vl_pfc_advect_x(h, 0, p, p, None, 0.1, None) == 2
+    assert lib.vl_pfc_advect_x(h, 1, p, q, None, 0.1, None) == 1
+    assert lib.vl_pfc_advect_v(h, 0, p, p, q, None, 0.1, None) == 2
+    assert lib.vl_pfc_advect_v(h, 0, p, q, None, None, 0.1, None) == 1
+    assert lib.vl_moments(h, 0, None, p, None) == 1
+    assert lib.vl_moment_fit(h, 0, p, p, None, q, None, None, None) == 1
+    assert lib.vl_maxwell_half_step(h, p, ctypes.c_void_p(0x3000), 0.1, None) == 3
+    s = vl.State()
+    assert lib.vl_step(h, ctypes.byref(s), 0.1, None) == 1
+    assert lib.vl_step(h, None, 0.1, None) == 1
+    assert b"" != lib.vl_last_error(h)
+    lib.vl_destroy(h)
