@@ -20,6 +20,7 @@ struct VGrid {
     int nvx, nvy, nvz;
     double lo[3], dv[3];
     double m;
+    float inv_nvz;
 };
 
 __device__ __forceinline__ double vc(const VGrid& G, int d, int i) { return G.lo[d] + (i + 0.5) * G.dv[d]; }
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(256) moments3_kernel(const T* __restrict__ f, 
     const int nv = G.nvx * G.nvy * G.nvz;
     const int pz = G.nvz | 1;
     const T* src = f + cell * nv;
-    for (int e = threadIdx.x; e < nv; e += blockDim.x) blk[(e / G.nvz) * pz + e % G.nvz] = src[e];
+    for (int e = threadIdx.x; e < nv; e += blockDim.x) blk[e + row_of(e, G.inv_nvz) * (pz - G.nvz)] = src[e];
     __syncthreads();
     double m[20];
     block_moments3(blk, pz, G, m, red);
@@ -298,6 +299,234 @@ fit3_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* _
     if (max_out) block_max_to(mx, max_out);
 }
 
+// ------------------------------------------------------- cubic blocks -------
+// Velocity blocks with N cells per axis: thread t < N*N owns the v_x pencil at
+// (v_y, v_z) = (t / N, t % N); element (ix, t) sits at t + N*N*ix, so the loads
+// of a wave are contiguous and the only coordinate that varies along a thread's
+// elements is v_x, which is uniform across the block (table in the arguments).
+struct XTable {
+    double v[32], v2[32], v3[32];
+};
+
+// The 20 raw moments as weighted sums of the pencil sums S_k = sum_x f v_x^k
+// with the thread's transverse velocities (v_y, v_z).
+__device__ __forceinline__ void pencil_moments(const double (&S)[4], double vy, double vz, double (&a)[20]) {
+    const double vy2 = vy * vy, vz2 = vz * vz, vyz = vy * vz;
+    a[0] = S[0];        a[1] = S[1];        a[2] = vy * S[0];   a[3] = vz * S[0];
+    a[4] = S[2];        a[5] = vy * S[1];   a[6] = vz * S[1];
+    a[7] = vy2 * S[0];  a[8] = vyz * S[0];  a[9] = vz2 * S[0];
+    a[10] = S[3];       a[11] = vy * S[2];  a[12] = vz * S[2];  a[13] = vy2 * S[1];
+    a[14] = vyz * S[1]; a[15] = vz2 * S[1]; a[16] = vy2 * vy * S[0];
+    a[17] = vy2 * vz * S[0]; a[18] = vy * vz2 * S[0]; a[19] = vz2 * vz * S[0];
+}
+
+__device__ __forceinline__ void store20(double* dst, const double (&a)[20], double scale_lo, double scale_hi) {
+    if (threadIdx.x < 20) {
+        double v = 0;
+#pragma unroll
+        for (int k = 0; k < 20; ++k) v = (threadIdx.x == k) ? a[k] * (k < 4 ? scale_lo : scale_hi) : v;
+        dst[threadIdx.x] = v;
+    }
+}
+
+// One wave per cell (four cells per 256-thread block): lane l owns the v_x
+// pencils at transverse positions t = l + 64 j (t = iy * N + iz), so the 20
+// sums are reduced inside one wave, with no block barrier.
+template <class T, int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
+moments3_cube_kernel(const T* __restrict__ f, double* __restrict__ mom, long long cells, VGrid G, XTable X) {
+    constexpr int NT = (N * N + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const long long cell = (long long)xcd_work_index(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (cell >= cells) return;
+    const T* src = f + cell * (N * N * N);
+    T fv[NT][N];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int t = lane + 64 * j;
+#pragma unroll
+        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? src[t + k * N * N] : T(0);
+    }
+    double acc[20];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int t = lane + 64 * j;
+        double S[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double g = (double)fv[j][k];
+            S[0] += g;
+            S[1] = fma(g, X.v[k], S[1]);
+            S[2] = fma(g, X.v2[k], S[2]);
+            S[3] = fma(g, X.v3[k], S[3]);
+        }
+        double a[20];
+        pencil_moments(S, vc(G, 1, t / N), vc(G, 2, t % N), a);
+#pragma unroll
+        for (int q = 0; q < 20; ++q) acc[q] += a[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 20; ++q) acc[q] = wave_sum(acc[q]);
+    const double dV = G.dv[0] * G.dv[1] * G.dv[2];
+    if (lane < 20) {
+        double v = 0;
+#pragma unroll
+        for (int q = 0; q < 20; ++q) v = (lane == q) ? acc[q] * (q < 4 ? dV : G.m * dV) : v;
+        mom[cell * 20 + lane] = v;
+    }
+}
+
+// Moment fitting of one cubic cell per block (see fit3_kernel for the steps).
+// Per element: two exponentials of a quadratic in v_x whose other terms are
+// per-thread constants, the exchange and clip, and FP64 pencil sums.
+template <class T>
+struct QuadX {       // -(m/2) w^T T^-1 w = -(axx wx^2 + bt wx + ct) for fixed (wy, wz)
+    T axx, bt, ct, ux;
+    __device__ __forceinline__ void set(const double (&inv)[6], const double (&u)[3], double m, double vy,
+                                        double vz) {
+        const double h = 0.5 * m, wy = vy - u[1], wz = vz - u[2];
+        axx = (T)(h * inv[0]);
+        bt = (T)(2.0 * h * (inv[1] * wy + inv[2] * wz));
+        ct = (T)(h * (inv[3] * wy * wy + 2.0 * inv[4] * wy * wz + inv[5] * wz * wz));
+        ux = (T)u[0];
+    }
+    __device__ __forceinline__ T g(T vx) const {
+        const T wx = vx - ux;
+        return expo<T>(-fma(fma(axx, wx, bt), wx, ct));
+    }
+};
+
+// One block per cell; thread t owns the v_x pencils at transverse positions
+// t + nthr * j (j < NT), nthr = blockDim.x.  FP32 storage uses two pencils per
+// thread (128 threads for 16^3), FP64 one (256 threads): enough values per
+// thread to amortise the reductions, few enough to stay in registers.
+template <class T, int N, int NT>
+__global__ void __launch_bounds__(256)
+fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* __restrict__ U,
+                 double* __restrict__ mom_post, unsigned long long* __restrict__ counters, VGrid G, XTable X,
+                 typename Bits<T>::U* __restrict__ max_out) {
+    __shared__ double red[21 * 4];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
+    const double dV = G.dv[0] * G.dv[1] * G.dv[2];
+    const T* src = fin + cell * (N * N * N);
+    T* dst = fout + cell * (N * N * N);
+    T fv[NT][N];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int t = tid + nthr * j;
+#pragma unroll
+        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? src[t + k * N * N] : T(0);
+    }
+    double mp[10], Uc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) { mp[k] = mom_pre[cell * 20 + k]; Uc[k] = U[cell * 10 + k]; }
+    const double nV = mp[0], nF = Uc[0];
+    double uV[3], TV[6], uF[3], TF[6], iV[6], iF[6];
+    bool ok = nV > 1e-12 && nF > 1e-12;
+    if (ok) {
+        u_and_T(mp + 1, nV, G.m, uV, TV);
+        u_and_T(Uc + 1, nF, G.m, uF, TF);
+        ok = spd_inverse(TV, iV) && spd_inverse(TF, iF);
+    }
+    double nclip = 0.0;
+    if (ok) {
+        QuadX<T> qv[NT], qf[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int t = tid + nthr * j;
+            qv[j].set(iV, uV, G.m, vc(G, 1, t / N), vc(G, 2, t % N));
+            qf[j].set(iF, uF, G.m, vc(G, 1, t / N), vc(G, 2, t % N));
+        }
+        // normalisation sums of the two Maxwellians (FP64)
+        double s[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            if (tid + nthr * j < N * N) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const T vx = (T)X.v[k];
+                    s[0] += (double)qv[j].g(vx);
+                    s[1] += (double)qf[j].g(vx);
+                }
+            }
+        }
+        block_sum<2>(s, red);
+        const T A = (T)(nV / (s[0] * dV));
+        const T Bc = (T)(nV / (s[1] * dV));
+        // exchange the Maxwellians and clip (exponentials recomputed)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const bool act = tid + nthr * j < N * N;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const T vx = (T)X.v[k];
+                const T x = fv[j][k] - A * qv[j].g(vx) + Bc * qf[j].g(vx);
+                nclip += (act && x < T(0)) ? 1.0 : 0.0;
+                fv[j][k] = act ? fmax(x, T(0)) : T(0);
+            }
+        }
+    }
+    // raw moments of the clipped f'' (FP64 pencil sums)
+    double acc[21];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) acc[q] = 0.0;
+    acc[20] = nclip;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int t = tid + nthr * j;
+        double S[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double g = (double)fv[j][k];
+            S[0] += g;
+            S[1] = fma(g, X.v[k], S[1]);
+            S[2] = fma(g, X.v2[k], S[2]);
+            S[3] = fma(g, X.v3[k], S[3]);
+        }
+        double a[20];
+        pencil_moments(S, vc(G, 1, t / N), vc(G, 2, t % N), a);
+#pragma unroll
+        for (int q = 0; q < 20; ++q) acc[q] += a[q];
+    }
+    block_sum<21>(acc, red);
+    const double scale = ok ? nV / (acc[0] * dV) : 1.0;
+    const T sc = (T)scale;
+    T mx = T(0);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int t = tid + nthr * j;
+        if (t < N * N) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const T o = ok ? fv[j][k] * sc : fv[j][k];
+                dst[t + k * N * N] = o;
+                mx = fmax(mx, o);
+            }
+        }
+    }
+    if (mom_post && tid < 20) {
+        double v = 0;
+#pragma unroll
+        for (int q = 0; q < 20; ++q) v = (tid == q) ? acc[q] * (q < 4 ? dV : G.m * dV) * scale : v;
+        mom_post[cell * 20 + tid] = v;
+    }
+    if (ok && tid < 10) {
+        const double r = nV / nF;
+        double v = 0;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) v = (tid == k) ? Uc[k] : v;
+        U[cell * 10 + tid] = v * r;
+    }
+    if (counters && tid == 0) {
+        if (acc[20] > 0) atomicAdd(&counters[0], (unsigned long long)acc[20]);
+        if (!ok) atomicAdd(&counters[1], 1ull);
+    }
+    if (max_out) block_max_to(mx, max_out);
+}
+
 template <class T>
 __global__ void __launch_bounds__(256)
 fit1_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* __restrict__ U,
@@ -387,9 +616,34 @@ static int threads_for(int work) {
     return t > 256 ? 256 : (t < 64 ? 64 : t);
 }
 
+static XTable xtable(const VGridArgs& a) {
+    XTable X{};
+    for (int k = 0; k < a.nv[0] && k < 32; ++k) {
+        const double v = a.lo[0] + (k + 0.5) * a.dv[0];
+        X.v[k] = v;
+        X.v2[k] = v * v;
+        X.v3[k] = v * v * v;
+    }
+    return X;
+}
+
+static int cube_edge(const VGridArgs& a) {
+    const bool cube = a.nv[0] == a.nv[1] && a.nv[1] == a.nv[2];
+    return (cube && (a.nv[0] == 8 || a.nv[0] == 12 || a.nv[0] == 16)) ? a.nv[0] : 0;
+}
+
 template <class T>
 hipError_t launch_moments3(const T* f, double* mom, long long cells, const VGridArgs& a, hipStream_t st) {
-    VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m};
+    VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m, 1.0f / (float)a.nv[2]};
+    const int N = cube_edge(a);
+    if (N) {
+        const XTable X = xtable(a);
+        const dim3 grid((unsigned)((cells + 3) / 4)), blk(256);
+        if (N == 16) hipLaunchKernelGGL((moments3_cube_kernel<T, 16>), grid, blk, 0, st, f, mom, cells, G, X);
+        if (N == 12) hipLaunchKernelGGL((moments3_cube_kernel<T, 12>), grid, blk, 0, st, f, mom, cells, G, X);
+        if (N == 8) hipLaunchKernelGGL((moments3_cube_kernel<T, 8>), grid, blk, 0, st, f, mom, cells, G, X);
+        return hipGetLastError();
+    }
     const size_t shm = sizeof(T) * (size_t)a.nv[0] * a.nv[1] * (a.nv[2] | 1);
     hipLaunchKernelGGL((moments3_kernel<T>), dim3((unsigned)cells), dim3(threads_for(a.nv[0] * a.nv[1])), shm, st, f,
                        mom, G);
@@ -407,13 +661,30 @@ hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, dou
 template <class T>
 hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
                        long long cells, const VGridArgs& a, void* max_out, hipStream_t st) {
-    VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m};
+    VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m, 1.0f / (float)a.nv[2]};
     const int nv = a.nv[0] * a.nv[1] * a.nv[2];
     const size_t shm = sizeof(T) * (size_t)a.nv[0] * a.nv[1] * (a.nv[2] | 1);
     const int threads = 256;
     const int ept = (nv + threads - 1) / threads;
     auto* cnt = (unsigned long long*)counters;
     auto* mo = (typename Bits<T>::U*)max_out;
+    const int N = cube_edge(a);
+    if (N) {
+        const XTable X = xtable(a);
+        const dim3 grid((unsigned)cells);
+        constexpr int NT = sizeof(T) == 4 ? 2 : 1;
+        auto thr = [](int n) { return 64 * ((n * n + 64 * NT - 1) / (64 * NT)); };
+        if (N == 16)
+            hipLaunchKernelGGL((fit3_cube_kernel<T, 16, NT>), grid, dim3(thr(16)), 0, st, fin, fout, mom_pre, U, mom_post,
+                               cnt, G, X, mo);
+        if (N == 12)
+            hipLaunchKernelGGL((fit3_cube_kernel<T, 12, NT>), grid, dim3(thr(12)), 0, st, fin, fout, mom_pre, U, mom_post,
+                               cnt, G, X, mo);
+        if (N == 8)
+            hipLaunchKernelGGL((fit3_cube_kernel<T, 8, NT>), grid, dim3(thr(8)), 0, st, fin, fout, mom_pre, U, mom_post,
+                               cnt, G, X, mo);
+        return hipGetLastError();
+    }
     if (ept <= 4)
         hipLaunchKernelGGL((fit3_kernel<T, 4>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, mom_pre, U,
                            mom_post, cnt, G, mo);

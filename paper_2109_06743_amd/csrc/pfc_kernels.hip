@@ -20,46 +20,86 @@ namespace vl {
 // load and store of a wave is one contiguous 256-byte (FP32) segment.  The
 // thread keeps a window of CX+3 inputs in registers, ordered upwind to
 // downwind, so both signs of the shift run the same straight-line code.
+// Offsets within a row are 32-bit (nx * Nv < 2^31 is checked on the host) and
+// advance by one row per element; only windows that cross the periodic seam
+// take the wrapping path.
 template <class T, int CX>
 __global__ void __launch_bounds__(256)
-pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, long long Nv, int inner,
-             double vx_lo, double dvx, double tau_dx, const T* __restrict__ finf_p,
-             typename Bits<T>::U* __restrict__ max_out) {
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c0 = blockIdx.y * CX;
-    const long long row = blockIdx.z;
-    const T finf = *finf_p;
+pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int Nv, float inv_inner, double vx_lo,
+             double dvx, double tau_dx, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
+    // work index = (v block fastest, then x chunk, then row), XCD-contiguous
+    const unsigned nvb = (Nv + 255) / 256, nch = (nx + CX - 1) / CX;
+    const unsigned w = xcd_work_index(blockIdx.x, gridDim.x);
+    const int v = (int)(w % nvb) * 256 + threadIdx.x;
+    const int c0 = (int)((w / nvb) % nch) * CX;
+    const size_t rowoff = (size_t)(w / (nvb * nch)) * nx * Nv;
+    const T* __restrict__ src = fin + rowoff;
+    T* __restrict__ dst = fout + rowoff;
+    const T F2 = T(2) * *finf_p;
     T mx = T(0);
     if (v < Nv) {
-        const int ivx = (int)(v / inner);
+        const int ivx = row_of(v, inv_inner);
         const double s = (vx_lo + (ivx + 0.5) * dvx) * tau_dx;
         const bool pos = s >= 0.0;
         const Shift<T> sh(fabs(s));
-        const int K = (int)(sh.K % nx);
-        const T* __restrict__ src = fin + row * nx * Nv + v;
-        T* __restrict__ dst = fout + row * nx * Nv + v;
+        const int K = sh.K < nx ? (int)sh.K : (int)(sh.K % nx);
         int idx = pos ? (c0 - K - 2) : (c0 + K + CX + 1);
-        idx %= nx;
-        if (idx < 0) idx += nx;
+        while (idx < 0) idx += nx;
+        while (idx >= nx) idx -= nx;
         const int step = pos ? 1 : -1;
+        const unsigned dstep = pos ? (unsigned)Nv : (unsigned)(-Nv);
+        unsigned off = (unsigned)idx * (unsigned)Nv + (unsigned)v;
         T W[CX + 3];
+        const bool wraps = pos ? (idx + CX + 2 >= nx) : (idx - CX - 2 < 0);
+        if (!wraps) {
 #pragma unroll
-        for (int w = 0; w < CX + 3; ++w) {
-            W[w] = src[(long long)idx * Nv];
-            idx += step;
-            if (idx >= nx) idx -= nx;
-            if (idx < 0) idx += nx;
+            for (int w = 0; w < CX + 3; ++w) {
+                W[w] = src[off];
+                off += dstep;
+            }
+        } else {
+            const unsigned span = (unsigned)nx * (unsigned)Nv;
+#pragma unroll
+            for (int w = 0; w < CX + 3; ++w) {
+                W[w] = src[off];
+                idx += step;
+                off += dstep;
+                if (idx == nx) {
+                    idx = 0;
+                    off -= span;
+                } else if (idx < 0) {
+                    idx = nx - 1;
+                    off += span;
+                }
+            }
         }
-        T phi_prev = pfc_phi(W[0], W[1], W[2], sh.a, sh.c1, sh.c2, finf);
+        T o[CX];
+        T D = W[2] - W[1];
+        T phi_prev = pfc_phi_d(W[1], W[1] - W[0], D, sh.a, sh.ac1, sh.ac2, F2);
 #pragma unroll
         for (int r = 0; r < CX; ++r) {
-            const T phi_next = pfc_phi(W[r + 1], W[r + 2], W[r + 3], sh.a, sh.c1, sh.c2, finf);
-            const T o = fmax(W[r + 2] + phi_prev - phi_next, T(0));
+            const T Dn = W[r + 3] - W[r + 2];
+            const T phi_next = pfc_phi_d(W[r + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
+            o[r] = fmax(W[r + 2] + phi_prev - phi_next, T(0));
             phi_prev = phi_next;
-            const int oi = pos ? (c0 + r) : (c0 + CX - 1 - r);
-            if (oi < nx) {
-                dst[(long long)oi * Nv] = o;
-                mx = fmax(mx, o);
+            D = Dn;
+        }
+        unsigned ooff = (unsigned)(pos ? c0 : c0 + CX - 1) * (unsigned)Nv + (unsigned)v;
+        if (c0 + CX <= nx) {
+#pragma unroll
+            for (int r = 0; r < CX; ++r) {
+                dst[ooff] = o[r];
+                mx = fmax(mx, o[r]);
+                ooff += dstep;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < CX; ++r) {
+                if ((pos ? c0 + r : c0 + CX - 1 - r) < nx) {
+                    dst[ooff] = o[r];
+                    mx = fmax(mx, o[r]);
+                }
+                ooff += dstep;
             }
         }
     }
@@ -71,57 +111,104 @@ pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, long long 
 // by its mirror pencil at -v_y in reverse row order is one periodic pencil of
 // length 2 ny moving uniformly by v_y tau / dy > 0.  A thread owns one pair and
 // CY consecutive positions of the doubled pencil.  Odd nvy: the v_y = 0 pencil
-// pairs with itself at zero shift (an exact copy).
+// pairs with itself at zero shift (an exact copy).  Windows inside one half of
+// the doubled pencil advance a pointer by one row (+ or -) per element; only
+// windows that touch a wall or the seam map each position.
+template <class T>
+__device__ __forceinline__ const T* pos_ptr(const T* up, const T* dn, int p, int ny, size_t rs) {
+    return p < ny ? up + (size_t)p * rs : dn + (size_t)(2 * ny - 1 - p) * rs;
+}
+
 template <class T, int CY>
 __global__ void __launch_bounds__(256)
-pfc_y_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, long long Nv, int nvx,
-             int nvy, int nvz, double vy_lo, double dvy, double tau_dy, const T* __restrict__ finf_p,
+pfc_y_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, int Nv, int nvx, int nvy, int nvz,
+             float inv_nvz, float inv_half, double vy_lo, double dvy, double tau_dy, const T* __restrict__ finf_p,
              typename Bits<T>::U* __restrict__ max_out) {
     const int half = (nvy + 1) / 2;                 // pairs per (ivx, ivz), incl. a v_y = 0 self-pair
-    const long long npairs = (long long)nvx * half * nvz;
-    const long long pid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c0 = blockIdx.y * CY;
-    const int ix = blockIdx.z;
-    const T finf = *finf_p;
+    const int npairs = nvx * half * nvz;
+    // work index = (pair block fastest, then y chunk, then x cell), XCD-contiguous
+    const unsigned npb = (unsigned)(nvx * ((nvy + 1) / 2) * nvz + 255) / 256, nch = (2 * ny + CY - 1) / CY;
+    const unsigned wi = xcd_work_index(blockIdx.x, gridDim.x);
+    const int pid = (int)(wi % npb) * 256 + threadIdx.x;
+    const int c0 = (int)((wi / npb) % nch) * CY;
+    const int ix = (int)(wi / (npb * nch));
+    const T F2 = T(2) * *finf_p;
     T mx = T(0);
     if (pid < npairs) {
-        const int ivz = (int)(pid % nvz);
-        const long long rest = pid / nvz;
-        const int jh = (int)(rest % half);
-        const int ivx = (int)(rest / half);
+        const int r1 = row_of(pid, inv_nvz);
+        const int ivz = pid - r1 * nvz;
+        const int ivx = row_of(r1, inv_half);
+        const int jh = r1 - ivx * half;
         const int jup = nvy - half + jh;            // v_y >= 0 half
         const int jdn = nvy - 1 - jup;              // its mirror
-        const long long vup = ((long long)ivx * nvy + jup) * nvz + ivz;
-        const long long vdn = ((long long)ivx * nvy + jdn) * nvz + ivz;
+        const size_t rs = (size_t)nx * Nv;
+        const T* up = fin + (size_t)ix * Nv + (size_t)(ivx * nvy + jup) * nvz + ivz;
+        const T* dn = fin + (size_t)ix * Nv + (size_t)(ivx * nvy + jdn) * nvz + ivz;
         const double s = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
         const Shift<T> sh(s);
         const int L2 = 2 * ny;
-        const int K = (int)(sh.K % L2);
-        const long long rowstride = (long long)nx * Nv;
-        const T* __restrict__ src = fin + (long long)ix * Nv;
-        T* __restrict__ dst = fout + (long long)ix * Nv;
-        int p = (c0 - K - 2) % L2;
-        if (p < 0) p += L2;
+        const int K = sh.K < L2 ? (int)sh.K : (int)(sh.K % L2);
+        int p = c0 - K - 2;
+        while (p < 0) p += L2;
         T W[CY + 3];
+        if (p + CY + 2 < ny) {                       // window inside the +v_y half
+            const T* q = up + (size_t)p * rs;
 #pragma unroll
-        for (int w = 0; w < CY + 3; ++w) {
-            const long long off = (p < ny) ? (long long)p * rowstride + vup
-                                           : (long long)(L2 - 1 - p) * rowstride + vdn;
-            W[w] = src[off];
-            if (++p == L2) p = 0;
+            for (int w = 0; w < CY + 3; ++w) {
+                W[w] = *q;
+                q += rs;
+            }
+        } else if (p >= ny && p + CY + 2 < L2) {     // window inside the mirrored half
+            const T* q = dn + (size_t)(L2 - 1 - p) * rs;
+#pragma unroll
+            for (int w = 0; w < CY + 3; ++w) {
+                W[w] = *q;
+                q -= rs;
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < CY + 3; ++w) {
+                W[w] = *pos_ptr(up, dn, p, ny, rs);
+                if (++p == L2) p = 0;
+            }
         }
-        T phi_prev = pfc_phi(W[0], W[1], W[2], sh.a, sh.c1, sh.c2, finf);
+        T* oup = fout + (up - fin);
+        T* odn = fout + (dn - fin);
+        T D = W[2] - W[1];
+        T phi_prev = pfc_phi_d(W[1], W[1] - W[0], D, sh.a, sh.ac1, sh.ac2, F2);
+        T o[CY];
 #pragma unroll
         for (int r = 0; r < CY; ++r) {
-            const T phi_next = pfc_phi(W[r + 1], W[r + 2], W[r + 3], sh.a, sh.c1, sh.c2, finf);
-            const T o = fmax(W[r + 2] + phi_prev - phi_next, T(0));
+            const T Dn = W[r + 3] - W[r + 2];
+            const T phi_next = pfc_phi_d(W[r + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
+            o[r] = fmax(W[r + 2] + phi_prev - phi_next, T(0));
             phi_prev = phi_next;
-            const int q = c0 + r;
-            if (q < L2) {
-                const long long off = (q < ny) ? (long long)q * rowstride + vup
-                                               : (long long)(L2 - 1 - q) * rowstride + vdn;
-                dst[off] = o;
-                mx = fmax(mx, o);
+            D = Dn;
+        }
+        if (c0 + CY <= ny) {
+            T* q = oup + (size_t)c0 * rs;
+#pragma unroll
+            for (int r = 0; r < CY; ++r) {
+                *q = o[r];
+                mx = fmax(mx, o[r]);
+                q += rs;
+            }
+        } else if (c0 >= ny && c0 + CY <= L2) {
+            T* q = odn + (size_t)(L2 - 1 - c0) * rs;
+#pragma unroll
+            for (int r = 0; r < CY; ++r) {
+                *q = o[r];
+                mx = fmax(mx, o[r]);
+                q -= rs;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < CY; ++r) {
+                const int qq = c0 + r;
+                if (qq < L2) {
+                    *const_cast<T*>(pos_ptr<T>(oup, odn, qq, ny, rs)) = o[r];
+                    mx = fmax(mx, o[r]);
+                }
             }
         }
     }
@@ -221,39 +308,41 @@ __device__ __forceinline__ void sweep3(T* blk, int d, double sigma, const V3Para
             const double vx = P.lo[0] + (ix + 0.5) * P.dv[0], vy = P.lo[1] + (iy + 0.5) * P.dv[1];
             acc = EB[2] + vx * EB[4] - vy * EB[3];
         }
-        const double s = P.qm * acc * sigma / P.dv[d];
+        const double s = P.qm * acc * sigma * P.inv_dv[d];
         const bool pos = s >= 0.0;
         const Shift<T> sh(fabs(s));
-        // pencil in upwind-to-downwind order; element k at shared index
+        // beyond n + 2 cells every output but the wall cell is 0 either way
+        const int K = sh.K > (long long)(n + 2) ? n + 2 : (int)sh.K;
+        // pencil in upwind-to-downwind order: element k lives at first + k * step
         const int first = pos ? base : base + (n - 1) * stride;
         const int step = pos ? stride : -stride;
-        T g[NMAX + 2];
-        g[0] = T(0);
-        g[NMAX + 1] = T(0);
+        // shifted window W[j + 2] = g_{j - K} for j = -2 .. n-1 (zero outside the box),
+        // so output p reads W at static positions p-2 .. p+1
+        T W[NMAX + 2];
 #pragma unroll
-        for (int k = 0; k < NMAX; ++k) g[k + 1] = (k < n) ? blk[first + k * step] : T(0);
-        // h_k = g_k + phi(k-1) - phi(k), k = 0..n; phi of ghost cells is 0
-        T h[NMAX + 1];
-        T pm = T(0);
-#pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-            const T p0 = (k < n) ? pfc_phi(g[k], g[k + 1], g[k + 2], sh.a, sh.c1, sh.c2, finf) : T(0);
-            h[k] = g[k + 1] + pm - p0;
-            if (k == n - 1) h[NMAX] = p0;          // outflow into the ghost beyond the wall
-            pm = (k < n) ? p0 : pm;
+        for (int j = -2; j < NMAX; ++j) {
+            const int src = j - K;
+            const bool in = j < n && src >= 0;
+            const T v = blk[first + (in ? src : 0) * step];
+            W[j + 2] = in ? v : T(0);
         }
-        const long long K = sh.K;
-        T top = h[NMAX];
+        // wall cell: every cell that reaches it stays, plus the partial flux of
+        // the cell K below: sum_{m >= n-1-K} g_m + phi(g_{n-3-K}, g_{n-2-K}, g_{n-1-K})
+        T top = T(0);
+        for (int m = (n - 1 - K > 0 ? n - 1 - K : 0); m < n; ++m) top += blk[first + m * step];
 #pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-            if (k < n) {
-                const long long t = (long long)k + K;
-                if (t >= n - 1) top += h[k];
-                else blk[first + (int)t * step] = fmax(h[k], T(0));
-                if ((long long)k < K && k < n - 1) blk[first + k * step] = T(0);
-            }
+        for (int p = 0; p < NMAX; ++p)
+            if (p == n - 1) top += pfc_phi(W[p], W[p + 1], W[p + 2], sh.a, sh.c1, sh.c2, finf);
+        T phi_prev = pfc_phi(W[0], W[1], W[2], sh.a, sh.c1, sh.c2, finf);   // phi at window position -1
+#pragma unroll
+        for (int p = 0; p < NMAX; ++p) {
+            // W[p + 3] exists for p < NMAX - 1; the last position is the wall cell or unused
+            const T wn = (p + 3 < NMAX + 2) ? W[(p + 3 < NMAX + 2) ? p + 3 : NMAX + 1] : T(0);
+            const T phi_next = pfc_phi(W[p + 1], W[p + 2], wn, sh.a, sh.c1, sh.c2, finf);
+            const T o = (p == n - 1) ? top : W[p + 2] + phi_prev - phi_next;
+            phi_prev = phi_next;
+            if (p < n) blk[first + p * step] = fmax(o, T(0));
         }
-        blk[first + (n - 1) * step] = fmax(top, T(0));
     }
 }
 
@@ -273,10 +362,7 @@ pfc_v3_kernel(const T* fin, T* fout, const double* __restrict__ E, const double*
         EB[3 + threadIdx.x] = B ? B[cell * 3 + threadIdx.x] : 0.0;
     }
     const T* src = fin + cell * nv;
-    for (int e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int iz = e % P.nvz, r = e / P.nvz;
-        blk[r * pz + iz] = src[e];
-    }
+    for (int e = threadIdx.x; e < nv; e += blockDim.x) blk[e + row_of(e, P.inv_nvz) * (pz - P.nvz)] = src[e];
     __syncthreads();
     double ebl[6];
 #pragma unroll
@@ -295,8 +381,127 @@ pfc_v3_kernel(const T* fin, T* fout, const double* __restrict__ E, const double*
     T* dst = fout + cell * nv;
     T mx = T(0);
     for (int e = threadIdx.x; e < nv; e += blockDim.x) {
-        const int iz = e % P.nvz, r = e / P.nvz;
-        const T o = blk[r * pz + iz];
+        const T o = blk[e + row_of(e, P.inv_nvz) * (pz - P.nvz)];
+        dst[e] = o;
+        mx = fmax(mx, o);
+    }
+    if (max_out) block_max_to(mx, max_out);
+}
+
+// ---------------------------------------------------------------------------
+// The same operator for cubic velocity blocks with compile-time edge N: every
+// pencil has length N and stride known at compile time, so the window, the
+// differences and the partial fluxes of one pencil are straight-line code.
+// Per element and sweep: one difference, one partial flux (8 operations),
+// the output (3) and one shared-memory read and write.  Waves whose lanes all
+// have K = 0 (the common case: |s| < 1) skip the shifted-window selects.
+template <class T, int N>
+__device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3Params& P, const double* EB, T F2) {
+    constexpr int PZ = N | 1;
+    for (int pen = threadIdx.x; pen < N * N; pen += blockDim.x) {
+        const int i1 = pen / N, i2 = pen % N;
+        int base, stride;
+        double acc;
+        if (d == 0) {           // pencil (iy, iz): a_x = (q/m)(Ex + vy Bz - vz By)
+            base = i1 * PZ + i2;
+            stride = N * PZ;
+            acc = EB[0] + (P.lo[1] + (i1 + 0.5) * P.dv[1]) * EB[5] - (P.lo[2] + (i2 + 0.5) * P.dv[2]) * EB[4];
+        } else if (d == 1) {    // pencil (ix, iz): a_y = (q/m)(Ey + vz Bx - vx Bz)
+            base = i1 * N * PZ + i2;
+            stride = PZ;
+            acc = EB[1] + (P.lo[2] + (i2 + 0.5) * P.dv[2]) * EB[3] - (P.lo[0] + (i1 + 0.5) * P.dv[0]) * EB[5];
+        } else {                // pencil (ix, iy): a_z = (q/m)(Ez + vx By - vy Bx)
+            base = (i1 * N + i2) * PZ;
+            stride = 1;
+            acc = EB[2] + (P.lo[0] + (i1 + 0.5) * P.dv[0]) * EB[4] - (P.lo[1] + (i2 + 0.5) * P.dv[1]) * EB[3];
+        }
+        const double s = P.qm * acc * sigma * P.inv_dv[d];
+        const bool pos = s >= 0.0;
+        const ShiftT<T> sh(fabs(s));
+        const int K = sh.K > N + 2 ? N + 2 : sh.K;
+        const int first = pos ? base : base + (N - 1) * stride;
+        const int step = pos ? stride : -stride;
+        // W[j + 2] = g_{j - K}, j = -2 .. N-1, zero outside the box
+        T W[N + 2];
+        T top;
+        if (__all(K == 0)) {
+            W[0] = T(0);
+            W[1] = T(0);
+            int a = first;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                W[j + 2] = blk[a];
+                a += step;
+            }
+            top = W[N + 1];
+        } else {
+            int a = first - (K + 2) * step;
+#pragma unroll
+            for (int j = -2; j < N; ++j) {
+                const bool in = j - K >= 0;
+                const T v = blk[in ? a : first];
+                W[j + 2] = in ? v : T(0);
+                a += step;
+            }
+            // every cell within K of the wall ends in the wall cell
+            top = T(0);
+            for (int m = (N - 1 - K > 0 ? N - 1 - K : 0); m < N; ++m) top += blk[first + m * step];
+        }
+        const T* w = W;
+        T D = w[1] - w[0];                       // D_i = w_i - w_{i-1}
+        T Dn = w[2] - w[1];
+        T phi_prev = pfc_phi_d(w[1], D, Dn, sh.a, sh.ac1, sh.ac2, F2);   // phi at window index 1
+        D = Dn;
+        int a = first;
+#pragma unroll
+        for (int p = 0; p < N - 1; ++p) {
+            Dn = w[p + 3] - w[p + 2];
+            const T phi_next = pfc_phi_d(w[p + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
+            blk[a] = fmax(w[p + 2] + phi_prev - phi_next, T(0));
+            phi_prev = phi_next;
+            D = Dn;
+            a += step;
+        }
+        // wall cell: the cells that reach it plus the partial flux at window index N
+        blk[a] = fmax(top + phi_prev, T(0));
+    }
+}
+
+template <class T, int N>
+__global__ void __launch_bounds__(256)
+pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const double* __restrict__ B, V3Params P,
+                   const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
+    constexpr int PZ = N | 1;
+    constexpr int NV = N * N * N;
+    __shared__ T blk[N * N * PZ];
+    __shared__ double EB[6];
+    const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
+    const T F2 = T(2) * *finf_p;
+    if (threadIdx.x < 3) {
+        EB[threadIdx.x] = E[cell * 3 + threadIdx.x];
+        EB[3 + threadIdx.x] = B ? B[cell * 3 + threadIdx.x] : 0.0;
+    }
+    const T* src = fin + cell * NV;
+    for (int e = threadIdx.x; e < NV; e += blockDim.x) blk[e + (e / N) * (PZ - N)] = src[e];
+    __syncthreads();
+    double ebl[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ebl[k] = EB[k];
+    const double half = 0.5 * P.tau;
+    sweep_cube<T, N>(blk, 0, half, P, ebl, F2);
+    __syncthreads();
+    sweep_cube<T, N>(blk, 1, half, P, ebl, F2);
+    __syncthreads();
+    sweep_cube<T, N>(blk, 2, P.tau, P, ebl, F2);
+    __syncthreads();
+    sweep_cube<T, N>(blk, 1, half, P, ebl, F2);
+    __syncthreads();
+    sweep_cube<T, N>(blk, 0, half, P, ebl, F2);
+    __syncthreads();
+    T* dst = fout + cell * NV;
+    T mx = T(0);
+    for (int e = threadIdx.x; e < NV; e += blockDim.x) {
+        const T o = blk[e + (e / N) * (PZ - N)];
         dst[e] = o;
         mx = fmax(mx, o);
     }
@@ -326,20 +531,22 @@ constexpr int kChunkY = 16;
 template <class T>
 hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, int inner, double vx_lo,
                         double dvx, double tau_dx, const void* finf, void* max_out, hipStream_t st) {
-    dim3 grid((unsigned)((Nv + 255) / 256), (unsigned)((nx + kChunkX - 1) / kChunkX), (unsigned)rows);
-    hipLaunchKernelGGL((pfc_x_kernel<T, kChunkX>), grid, dim3(256), 0, st, fin, fout, nx, Nv, inner, vx_lo,
-                       dvx, tau_dx, (const T*)finf, (typename Bits<T>::U*)max_out);
+    dim3 grid((unsigned)(((Nv + 255) / 256) * ((nx + kChunkX - 1) / kChunkX) * rows));
+    hipLaunchKernelGGL((pfc_x_kernel<T, kChunkX>), grid, dim3(256), 0, st, fin, fout, nx, (int)Nv,
+                       1.0f / (float)inner, vx_lo, dvx, tau_dx, (const T*)finf, (typename Bits<T>::U*)max_out);
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_pfc_y(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vy_lo,
                         double dvy, double tau_dy, const void* finf, void* max_out, hipStream_t st) {
-    const long long Nv = (long long)nvx * nvy * nvz;
-    const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
-    dim3 grid((unsigned)((npairs + 255) / 256), (unsigned)((2 * ny + kChunkY - 1) / kChunkY), (unsigned)nx);
-    hipLaunchKernelGGL((pfc_y_kernel<T, kChunkY>), grid, dim3(256), 0, st, fin, fout, nx, ny, Nv, nvx, nvy,
-                       nvz, vy_lo, dvy, tau_dy, (const T*)finf, (typename Bits<T>::U*)max_out);
+    const int Nv = nvx * nvy * nvz;
+    const int half = (nvy + 1) / 2;
+    const long long npairs = (long long)nvx * half * nvz;
+    dim3 grid((unsigned)(((npairs + 255) / 256) * ((2 * ny + kChunkY - 1) / kChunkY) * nx));
+    hipLaunchKernelGGL((pfc_y_kernel<T, kChunkY>), grid, dim3(256), 0, st, fin, fout, nx, ny, Nv, nvx, nvy, nvz,
+                       1.0f / (float)nvz, 1.0f / (float)half, vy_lo, dvy, tau_dy, (const T*)finf,
+                       (typename Bits<T>::U*)max_out);
     return hipGetLastError();
 }
 
@@ -368,7 +575,18 @@ hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E
     int threads = ((maxpen + 63) / 64) * 64;
     if (threads > 256) threads = 256;
     if (threads < 64) threads = 64;
-    if (nmax <= 8) {
+    const bool cube = P.nvx == P.nvy && P.nvy == P.nvz;
+    auto* mo = (typename Bits<T>::U*)max_out;
+    if (cube && P.nvx == 16) {
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 16>), dim3((unsigned)cells), dim3(256), 0, st, fin, fout, E, B, P,
+                           (const T*)finf, mo);
+    } else if (cube && P.nvx == 12) {
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 12>), dim3((unsigned)cells), dim3(192), 0, st, fin, fout, E, B, P,
+                           (const T*)finf, mo);
+    } else if (cube && P.nvx == 8) {
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 8>), dim3((unsigned)cells), dim3(64), 0, st, fin, fout, E, B, P,
+                           (const T*)finf, mo);
+    } else if (nmax <= 8) {
         hipLaunchKernelGGL((pfc_v3_kernel<T, 8>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, E, B,
                            P, (const T*)finf, (typename Bits<T>::U*)max_out);
     } else if (nmax <= 16) {

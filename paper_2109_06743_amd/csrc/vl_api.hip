@@ -181,9 +181,11 @@ vl_status advect_v_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double
     for (int d = 0; d < 3; ++d) {
         P.lo[d] = sp.v_lo[d];
         P.dv[d] = dv_of(sp, d);
+        P.inv_dv[d] = 1.0 / P.dv[d];
     }
     P.qm = sp.q / sp.m;
     P.tau = tau;
+    P.inv_nvz = 1.0f / (float)sp.nv[2];
     VL_HIP((vl::launch_pfc_v3<T>(fin, fout, ctx->cells, E, B, P, finf, max_out, st)));
     return VL_OK;
 }

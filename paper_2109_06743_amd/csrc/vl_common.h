@@ -19,6 +19,17 @@ template <> struct Bits<double> {
     static __device__ __forceinline__ U of(double x) { return (U)__double_as_longlong(x); }
 };
 
+// Workgroups are handed to the 8 XCDs round-robin in launch order.  This maps
+// the launch index to a work index so that each XCD gets one contiguous range
+// of work items: blocks resident on one XCD (sharing its L2) then touch
+// neighbouring data instead of every eighth item.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_work_index(unsigned b, unsigned nblocks) {
+    const unsigned xcd = b % kXcds, local = b / kXcds;
+    const unsigned per = nblocks / kXcds, rem = nblocks % kXcds;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
 template <class T>
 __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
@@ -86,12 +97,38 @@ __device__ __forceinline__ T pfc_phi(T fm, T f0, T fp, T a, T c1, T c2, T finf) 
     return a * (f0 + c1 * lp + c2 * lm);
 }
 
+template <class T>
+__device__ __forceinline__ T med3(T x, T lo, T hi);
+template <>
+__device__ __forceinline__ float med3<float>(float x, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+template <>
+__device__ __forceinline__ double med3<double>(double x, double lo, double hi) {
+    return fmin(fmax(x, lo), hi);
+}
+
+// The same partial flux in the form the sweep kernels use: from the cell value
+// w and its upwind/downwind differences dm = w - w_up, dp = w_down - w (each
+// difference is shared by two neighbouring cells), with a*c1, a*c2 folded and
+// F2 = 2 f_inf.  2 (bound - f0) = max(F2 - 2 w, 0), and the clamps are medians
+// of three (both bounds bracket 0 for w >= 0):
+//   phi = a w + a c1 med3(dp, -r2, 2w) + a c2 med3(dm, -2w, r2).
+template <class T>
+__device__ __forceinline__ T pfc_phi_d(T w, T dm, T dp, T a, T ac1, T ac2, T F2) {
+    const T x2 = w + w;
+    const T r2 = fmax(F2 - x2, T(0));
+    const T lp = med3(dp, -r2, x2);
+    const T lm = med3(dm, -x2, r2);
+    return fma(ac1, lp, fma(ac2, lm, a * w));
+}
+
 // Split a non-negative displacement of s cells into floor and fraction, with
 // the coefficients of the partial flux (computed in FP64, rounded to T).
 template <class T>
 struct Shift {
     long long K;
-    T a, c1, c2;
+    T a, c1, c2, ac1, ac2;
     // Displacements beyond 1e9 cells are clamped there (far past any grid).
     __device__ __forceinline__ explicit Shift(double sa) {
         sa = fmin(sa, 1.0e9);
@@ -99,8 +136,30 @@ struct Shift {
         const double ad = sa - Kd;
         K = (long long)Kd;
         a = (T)ad;
-        c1 = (T)((1.0 - ad) * (2.0 - ad) / 6.0);
-        c2 = (T)((1.0 - ad) * (1.0 + ad) / 6.0);
+        const double d1 = (1.0 - ad) * (2.0 - ad) * (1.0 / 6.0), d2 = (1.0 - ad) * (1.0 + ad) * (1.0 / 6.0);
+        c1 = (T)d1;
+        c2 = (T)d2;
+        ac1 = (T)(ad * d1);
+        ac2 = (T)(ad * d2);
+    }
+};
+
+// Shift split computed in the storage type (FP32 storage keeps the
+// displacement to FP32 accuracy, which is what its cells can resolve); the
+// integer part is clamped to 2^20, beyond any pencil.
+template <class T>
+struct ShiftT {
+    int K;
+    T a, ac1, ac2;
+    __device__ __forceinline__ explicit ShiftT(double sa_d) {
+        const T sa = (T)fmin(sa_d, 1048576.0);
+        const T Kf = floor(sa);
+        a = sa - Kf;
+        K = (int)Kf;
+        const T b = T(1) - a;
+        const T k6 = T(1.0 / 6.0);
+        ac1 = a * b * (T(2) - a) * k6;
+        ac2 = a * b * (T(1) + a) * k6;
     }
 };
 

@@ -28,9 +28,15 @@ hipError_t launch_pfc_v1(const T* fin, T* fout, int nx, int nv, const double* E,
                          void* max_out, hipStream_t st);
 struct V3Params {
     int nvx, nvy, nvz;
-    double lo[3], dv[3];
+    double lo[3], dv[3], inv_dv[3];
     double qm, tau;
+    float inv_nvz;   // 1/nvz, for the exact row index (e + 0.5) / nvz of small e
 };
+
+// Row index e / n for 0 <= e < 2^16 without integer division: (e + 0.5)/n is
+// at least 1/(2n) away from an integer, while the float product is off by at
+// most 2^16/n * 2^-23 < 1/(2n).
+__device__ __forceinline__ int row_of(int e, float inv_n) { return (int)(((float)e + 0.5f) * inv_n); }
 template <class T>
 hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E, const double* B, const V3Params& P,
                          const void* finf, void* max_out, hipStream_t st);
