@@ -381,12 +381,23 @@ moments3_cube_kernel(const T* __restrict__ f, double* __restrict__ mom, long lon
 // Moment fitting of one cubic cell per block (see fit3_kernel for the steps).
 // Per element: two exponentials of a quadratic in v_x whose other terms are
 // per-thread constants, the exchange and clip, and FP64 pencil sums.
+// exp(-q) with q scaled by log2(e) in FP32 (one v_exp_f32), exp() in FP64.
+template <class T> struct ExpK;
+template <> struct ExpK<float> {
+    static constexpr double scale = 1.4426950408889634;   // log2(e)
+    static __device__ __forceinline__ float e(float q) { return __builtin_amdgcn_exp2f(-q); }
+};
+template <> struct ExpK<double> {
+    static constexpr double scale = 1.0;
+    static __device__ __forceinline__ double e(double q) { return exp(-q); }
+};
+
 template <class T>
-struct QuadX {       // -(m/2) w^T T^-1 w = -(axx wx^2 + bt wx + ct) for fixed (wy, wz)
+struct QuadX {       // (m/2) w^T T^-1 w = axx wx^2 + bt wx + ct for fixed (wy, wz), times ExpK::scale
     T axx, bt, ct, ux;
     __device__ __forceinline__ void set(const double (&inv)[6], const double (&u)[3], double m, double vy,
                                         double vz) {
-        const double h = 0.5 * m, wy = vy - u[1], wz = vz - u[2];
+        const double h = 0.5 * m * ExpK<T>::scale, wy = vy - u[1], wz = vz - u[2];
         axx = (T)(h * inv[0]);
         bt = (T)(2.0 * h * (inv[1] * wy + inv[2] * wz));
         ct = (T)(h * (inv[3] * wy * wy + 2.0 * inv[4] * wy * wz + inv[5] * wz * wz));
@@ -394,7 +405,7 @@ struct QuadX {       // -(m/2) w^T T^-1 w = -(axx wx^2 + bt wx + ct) for fixed (
     }
     __device__ __forceinline__ T g(T vx) const {
         const T wx = vx - ux;
-        return expo<T>(-fma(fma(axx, wx, bt), wx, ct));
+        return ExpK<T>::e(fma(fma(axx, wx, bt), wx, ct));
     }
 };
 
@@ -431,7 +442,7 @@ fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, doub
         u_and_T(Uc + 1, nF, G.m, uF, TF);
         ok = spd_inverse(TV, iV) && spd_inverse(TF, iF);
     }
-    double nclip = 0.0;
+    int nclip = 0;
     if (ok) {
         QuadX<T> qv[NT], qf[NT];
 #pragma unroll
@@ -464,7 +475,7 @@ fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, doub
             for (int k = 0; k < N; ++k) {
                 const T vx = (T)X.v[k];
                 const T x = fv[j][k] - A * qv[j].g(vx) + Bc * qf[j].g(vx);
-                nclip += (act && x < T(0)) ? 1.0 : 0.0;
+                nclip += (act && x < T(0)) ? 1 : 0;
                 fv[j][k] = act ? fmax(x, T(0)) : T(0);
             }
         }
@@ -473,7 +484,7 @@ fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, doub
     double acc[21];
 #pragma unroll
     for (int q = 0; q < 20; ++q) acc[q] = 0.0;
-    acc[20] = nclip;
+    acc[20] = (double)nclip;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int t = tid + nthr * j;

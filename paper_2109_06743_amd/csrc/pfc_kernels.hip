@@ -110,13 +110,82 @@ pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int Nv, fl
 // y sweep between reflecting walls: the pencil at +v_y (rows 0..ny-1) followed
 // by its mirror pencil at -v_y in reverse row order is one periodic pencil of
 // length 2 ny moving uniformly by v_y tau / dy > 0.  A thread owns one pair and
-// CY consecutive positions of the doubled pencil.  Odd nvy: the v_y = 0 pencil
-// pairs with itself at zero shift (an exact copy).  Windows inside one half of
-// the doubled pencil advance a pointer by one row (+ or -) per element; only
-// windows that touch a wall or the seam map each position.
+// the CY rows [c0, c0+CY) of it twice: as positions c0.. of the +v_y half and
+// as the mirrored positions of the -v_y half, so every row a block touches is
+// read and written for both halves of each v_x plane (whole DRAM pages).  Odd
+// nvy: the v_y = 0 pencil pairs with itself at zero shift (an exact copy).
+// Windows inside one half advance a pointer by one row per element; windows
+// that touch a wall or the seam map each position.
 template <class T>
 __device__ __forceinline__ const T* pos_ptr(const T* up, const T* dn, int p, int ny, size_t rs) {
     return p < ny ? up + (size_t)p * rs : dn + (size_t)(2 * ny - 1 - p) * rs;
+}
+
+template <class T, int CY>
+__device__ __forceinline__ void y_window(const T* up, const T* dn, T* oup, T* odn, int q0, int nq, int K, int ny,
+                                         size_t rs, const ShiftT<T>& sh, T F2, T& mx) {
+    const int L2 = 2 * ny;
+    int p = q0 - K - 2;
+    while (p < 0) p += L2;
+    T W[CY + 3];
+    if (p + CY + 2 < ny) {                       // window inside the +v_y half
+        const T* q = up + (size_t)p * rs;
+#pragma unroll
+        for (int w = 0; w < CY + 3; ++w) {
+            W[w] = *q;
+            q += rs;
+        }
+    } else if (p >= ny && p + CY + 2 < L2) {     // window inside the mirrored half
+        const T* q = dn + (size_t)(L2 - 1 - p) * rs;
+#pragma unroll
+        for (int w = 0; w < CY + 3; ++w) {
+            W[w] = *q;
+            q -= rs;
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < CY + 3; ++w) {
+            W[w] = *pos_ptr(up, dn, p, ny, rs);
+            if (++p == L2) p = 0;
+        }
+    }
+    T o[CY];
+    T D = W[2] - W[1];
+    T phi_prev = pfc_phi_d(W[1], W[1] - W[0], D, sh.a, sh.ac1, sh.ac2, F2);
+#pragma unroll
+    for (int r = 0; r < CY; ++r) {
+        const T Dn = W[r + 3] - W[r + 2];
+        const T phi_next = pfc_phi_d(W[r + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
+        o[r] = fmax(W[r + 2] + phi_prev - phi_next, T(0));
+        phi_prev = phi_next;
+        D = Dn;
+    }
+    if (nq == CY && q0 + CY <= ny) {
+        T* q = oup + (size_t)q0 * rs;
+#pragma unroll
+        for (int r = 0; r < CY; ++r) {
+            *q = o[r];
+            mx = fmax(mx, o[r]);
+            q += rs;
+        }
+    } else if (nq == CY && q0 >= ny && q0 + CY <= L2) {
+        T* q = odn + (size_t)(L2 - 1 - q0) * rs;
+#pragma unroll
+        for (int r = 0; r < CY; ++r) {
+            *q = o[r];
+            mx = fmax(mx, o[r]);
+            q -= rs;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < CY; ++r) {
+            const int qq = q0 + r;
+            if (r < nq) {
+                *const_cast<T*>(pos_ptr<T>(oup, odn, qq, ny, rs)) = o[r];
+                mx = fmax(mx, o[r]);
+            }
+        }
+    }
 }
 
 template <class T, int CY>
@@ -126,8 +195,8 @@ pfc_y_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, in
              typename Bits<T>::U* __restrict__ max_out) {
     const int half = (nvy + 1) / 2;                 // pairs per (ivx, ivz), incl. a v_y = 0 self-pair
     const int npairs = nvx * half * nvz;
-    // work index = (pair block fastest, then y chunk, then x cell), XCD-contiguous
-    const unsigned npb = (unsigned)(nvx * ((nvy + 1) / 2) * nvz + 255) / 256, nch = (2 * ny + CY - 1) / CY;
+    // work index = (pair block fastest, then row chunk, then x cell), XCD-contiguous
+    const unsigned npb = (unsigned)(npairs + 255) / 256, nch = (ny + CY - 1) / CY;
     const unsigned wi = xcd_work_index(blockIdx.x, gridDim.x);
     const int pid = (int)(wi % npb) * 256 + threadIdx.x;
     const int c0 = (int)((wi / npb) % nch) * CY;
@@ -144,73 +213,16 @@ pfc_y_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, in
         const size_t rs = (size_t)nx * Nv;
         const T* up = fin + (size_t)ix * Nv + (size_t)(ivx * nvy + jup) * nvz + ivz;
         const T* dn = fin + (size_t)ix * Nv + (size_t)(ivx * nvy + jdn) * nvz + ivz;
-        const double s = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
-        const Shift<T> sh(s);
-        const int L2 = 2 * ny;
-        const int K = sh.K < L2 ? (int)sh.K : (int)(sh.K % L2);
-        int p = c0 - K - 2;
-        while (p < 0) p += L2;
-        T W[CY + 3];
-        if (p + CY + 2 < ny) {                       // window inside the +v_y half
-            const T* q = up + (size_t)p * rs;
-#pragma unroll
-            for (int w = 0; w < CY + 3; ++w) {
-                W[w] = *q;
-                q += rs;
-            }
-        } else if (p >= ny && p + CY + 2 < L2) {     // window inside the mirrored half
-            const T* q = dn + (size_t)(L2 - 1 - p) * rs;
-#pragma unroll
-            for (int w = 0; w < CY + 3; ++w) {
-                W[w] = *q;
-                q -= rs;
-            }
-        } else {
-#pragma unroll
-            for (int w = 0; w < CY + 3; ++w) {
-                W[w] = *pos_ptr(up, dn, p, ny, rs);
-                if (++p == L2) p = 0;
-            }
-        }
         T* oup = fout + (up - fin);
         T* odn = fout + (dn - fin);
-        T D = W[2] - W[1];
-        T phi_prev = pfc_phi_d(W[1], W[1] - W[0], D, sh.a, sh.ac1, sh.ac2, F2);
-        T o[CY];
-#pragma unroll
-        for (int r = 0; r < CY; ++r) {
-            const T Dn = W[r + 3] - W[r + 2];
-            const T phi_next = pfc_phi_d(W[r + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
-            o[r] = fmax(W[r + 2] + phi_prev - phi_next, T(0));
-            phi_prev = phi_next;
-            D = Dn;
-        }
-        if (c0 + CY <= ny) {
-            T* q = oup + (size_t)c0 * rs;
-#pragma unroll
-            for (int r = 0; r < CY; ++r) {
-                *q = o[r];
-                mx = fmax(mx, o[r]);
-                q += rs;
-            }
-        } else if (c0 >= ny && c0 + CY <= L2) {
-            T* q = odn + (size_t)(L2 - 1 - c0) * rs;
-#pragma unroll
-            for (int r = 0; r < CY; ++r) {
-                *q = o[r];
-                mx = fmax(mx, o[r]);
-                q -= rs;
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < CY; ++r) {
-                const int qq = c0 + r;
-                if (qq < L2) {
-                    *const_cast<T*>(pos_ptr<T>(oup, odn, qq, ny, rs)) = o[r];
-                    mx = fmax(mx, o[r]);
-                }
-            }
-        }
+        const double s = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
+        const ShiftT<T> sh(s);
+        const int L2 = 2 * ny;
+        const int K = sh.K < L2 ? sh.K : sh.K % L2;
+        const int rows = (c0 + CY <= ny) ? CY : ny - c0;
+        // rows [c0, c0+rows) as +v_y positions, then as mirrored -v_y positions
+        y_window<T, CY>(up, dn, oup, odn, c0, rows, K, ny, rs, sh, F2, mx);
+        y_window<T, CY>(up, dn, oup, odn, L2 - c0 - rows, rows, K, ny, rs, sh, F2, mx);
     }
     if (max_out) block_max_to(mx, max_out);
 }
@@ -398,25 +410,25 @@ pfc_v3_kernel(const T* fin, T* fout, const double* __restrict__ E, const double*
 template <class T, int N>
 __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3Params& P, const double* EB, T F2) {
     constexpr int PZ = N | 1;
+    // The displacement is linear in the pencil's two transverse indices:
+    // s = s0 + s1 i1 + s2 i2 (coefficients in FP64, then the storage type).
+    const double C = P.qm * sigma * P.inv_dv[d];
+    const double c0 = P.lo[0] + 0.5 * P.dv[0], c1 = P.lo[1] + 0.5 * P.dv[1], c2 = P.lo[2] + 0.5 * P.dv[2];
+    double d0, d1, d2;
+    if (d == 0) {           // pencil (iy, iz): a_x = (q/m)(Ex + vy Bz - vz By)
+        d0 = C * (EB[0] + EB[5] * c1 - EB[4] * c2); d1 = C * EB[5] * P.dv[1]; d2 = -C * EB[4] * P.dv[2];
+    } else if (d == 1) {    // pencil (ix, iz): a_y = (q/m)(Ey + vz Bx - vx Bz)
+        d0 = C * (EB[1] + EB[3] * c2 - EB[5] * c0); d1 = -C * EB[5] * P.dv[0]; d2 = C * EB[3] * P.dv[2];
+    } else {                // pencil (ix, iy): a_z = (q/m)(Ez + vx By - vy Bx)
+        d0 = C * (EB[2] + EB[4] * c0 - EB[3] * c1); d1 = C * EB[4] * P.dv[0]; d2 = -C * EB[3] * P.dv[1];
+    }
+    const T s0 = (T)d0, s1 = (T)d1, s2 = (T)d2;
     for (int pen = threadIdx.x; pen < N * N; pen += blockDim.x) {
         const int i1 = pen / N, i2 = pen % N;
-        int base, stride;
-        double acc;
-        if (d == 0) {           // pencil (iy, iz): a_x = (q/m)(Ex + vy Bz - vz By)
-            base = i1 * PZ + i2;
-            stride = N * PZ;
-            acc = EB[0] + (P.lo[1] + (i1 + 0.5) * P.dv[1]) * EB[5] - (P.lo[2] + (i2 + 0.5) * P.dv[2]) * EB[4];
-        } else if (d == 1) {    // pencil (ix, iz): a_y = (q/m)(Ey + vz Bx - vx Bz)
-            base = i1 * N * PZ + i2;
-            stride = PZ;
-            acc = EB[1] + (P.lo[2] + (i2 + 0.5) * P.dv[2]) * EB[3] - (P.lo[0] + (i1 + 0.5) * P.dv[0]) * EB[5];
-        } else {                // pencil (ix, iy): a_z = (q/m)(Ez + vx By - vy Bx)
-            base = (i1 * N + i2) * PZ;
-            stride = 1;
-            acc = EB[2] + (P.lo[0] + (i1 + 0.5) * P.dv[0]) * EB[4] - (P.lo[1] + (i2 + 0.5) * P.dv[1]) * EB[3];
-        }
-        const double s = P.qm * acc * sigma * P.inv_dv[d];
-        const bool pos = s >= 0.0;
+        const int base = d == 0 ? i1 * PZ + i2 : (d == 1 ? i1 * N * PZ + i2 : (i1 * N + i2) * PZ);
+        const int stride = d == 0 ? N * PZ : (d == 1 ? PZ : 1);
+        const T s = fma(s1, (T)i1, fma(s2, (T)i2, s0));
+        const bool pos = s >= T(0);
         const ShiftT<T> sh(fabs(s));
         const int K = sh.K > N + 2 ? N + 2 : sh.K;
         const int first = pos ? base : base + (N - 1) * stride;
@@ -427,11 +439,11 @@ __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3
         if (__all(K == 0)) {
             W[0] = T(0);
             W[1] = T(0);
-            int a = first;
+            const T* q = blk + first;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                W[j + 2] = blk[a];
-                a += step;
+                W[j + 2] = *q;
+                q += step;
             }
             top = W[N + 1];
         } else {
@@ -452,18 +464,18 @@ __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3
         T Dn = w[2] - w[1];
         T phi_prev = pfc_phi_d(w[1], D, Dn, sh.a, sh.ac1, sh.ac2, F2);   // phi at window index 1
         D = Dn;
-        int a = first;
+        T* q = blk + first;
 #pragma unroll
         for (int p = 0; p < N - 1; ++p) {
             Dn = w[p + 3] - w[p + 2];
             const T phi_next = pfc_phi_d(w[p + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
-            blk[a] = fmax(w[p + 2] + phi_prev - phi_next, T(0));
+            *q = fmax(w[p + 2] + phi_prev - phi_next, T(0));
             phi_prev = phi_next;
             D = Dn;
-            a += step;
+            q += step;
         }
         // wall cell: the cells that reach it plus the partial flux at window index N
-        blk[a] = fmax(top + phi_prev, T(0));
+        *q = fmax(top + phi_prev, T(0));
     }
 }
 
@@ -543,7 +555,7 @@ hipError_t launch_pfc_y(const T* fin, T* fout, int nx, int ny, int nvx, int nvy,
     const int Nv = nvx * nvy * nvz;
     const int half = (nvy + 1) / 2;
     const long long npairs = (long long)nvx * half * nvz;
-    dim3 grid((unsigned)(((npairs + 255) / 256) * ((2 * ny + kChunkY - 1) / kChunkY) * nx));
+    dim3 grid((unsigned)(((npairs + 255) / 256) * ((ny + kChunkY - 1) / kChunkY) * nx));
     hipLaunchKernelGGL((pfc_y_kernel<T, kChunkY>), grid, dim3(256), 0, st, fin, fout, nx, ny, Nv, nvx, nvy, nvz,
                        1.0f / (float)nvz, 1.0f / (float)half, vy_lo, dvy, tau_dy, (const T*)finf,
                        (typename Bits<T>::U*)max_out);

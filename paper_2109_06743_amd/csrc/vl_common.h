@@ -151,15 +151,16 @@ template <class T>
 struct ShiftT {
     int K;
     T a, ac1, ac2;
-    __device__ __forceinline__ explicit ShiftT(double sa_d) {
-        const T sa = (T)fmin(sa_d, 1048576.0);
+    __device__ __forceinline__ explicit ShiftT(double sa_d) { init((T)fmin(sa_d, 1048576.0)); }
+    __device__ __forceinline__ explicit ShiftT(float sa_f) { init((T)fminf(sa_f, 1048576.0f)); }
+    __device__ __forceinline__ void init(T sa) {
         const T Kf = floor(sa);
         a = sa - Kf;
         K = (int)Kf;
-        const T b = T(1) - a;
-        const T k6 = T(1.0 / 6.0);
-        ac1 = a * b * (T(2) - a) * k6;
-        ac2 = a * b * (T(1) + a) * k6;
+        // a c1 = t (2 - a), a c2 = t (1 + a) with t = a (1 - a) / 6
+        const T t = a * (T(1) - a) * T(1.0 / 6.0);
+        ac1 = fma(-t, a, t + t);
+        ac2 = fma(t, a, t);
     }
 };
 
