@@ -402,11 +402,61 @@ pfc_v3_kernel(const T* fin, T* fout, const double* __restrict__ E, const double*
 
 // ---------------------------------------------------------------------------
 // The same operator for cubic velocity blocks with compile-time edge N: every
-// pencil has length N and stride known at compile time, so the window, the
-// differences and the partial fluxes of one pencil are straight-line code.
-// Per element and sweep: one difference, one partial flux (8 operations),
-// the output (3) and one shared-memory read and write.  Waves whose lanes all
-// have K = 0 (the common case: |s| < 1) skip the shifted-window selects.
+// pencil has length N and a stride known at compile time, so a pencil is
+// straight-line code with constant shared-memory offsets.
+//
+// Sub-cell shifts (K = 0, the common case) are done in the pencil's storage
+// order whatever the sign of s.  With D_m = g_m - g_{m-1} (zero ghosts),
+// r2 = max(2 f_inf - 2 g_m, 0) and
+//   A_m = med3(D_{m+1}, -r2, 2 g_m),  B_m = med3(D_m, -2 g_m, r2),
+// the partial flux leaving cell m downwind is a g_m + a c1 A_m + a c2 B_m for
+// s > 0 and, by reflecting the pencil, a g_m - a c1 B_m - a c2 A_m for s < 0.
+// The flux through face m+1/2 (positive towards m+1) is the first for cell m
+// or minus the second for cell m+1; the wall faces carry none.  Per element:
+// one difference, eight operations for the partial flux, one select and three
+// for the update, and no address arithmetic.
+template <class T>
+__device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F2) {
+    const T x2 = w + w;
+    const T r2 = fmax(F2 - x2, T(0));
+    const T A = med3(Dp, -r2, x2);
+    const T B = med3(Dm, -x2, r2);
+    return fma(cA, A, fma(cB, B, a * w));
+}
+
+// Shifts of a cell or more (any lane of the wave): windows gathered in the
+// sweep direction, the cells within K of the far wall summed into it.
+template <class T, int N>
+__device__ __attribute__((noinline)) void pencil_shifted(T* blk, int first, int step, int K, T a, T ac1, T ac2,
+                                                          T F2) {
+    T W[N + 2];
+    int q = first - (K + 2) * step;
+#pragma unroll
+    for (int j = -2; j < N; ++j) {
+        const bool in = j - K >= 0;
+        const T v = blk[in ? q : first];
+        W[j + 2] = in ? v : T(0);
+        q += step;
+    }
+    T top = T(0);
+    for (int m = (N - 1 - K > 0 ? N - 1 - K : 0); m < N; ++m) top += blk[first + m * step];
+    T D = W[1] - W[0];
+    T Dn = W[2] - W[1];
+    T phi_prev = pfc_phi_d(W[1], D, Dn, a, ac1, ac2, F2);
+    D = Dn;
+    q = first;
+#pragma unroll
+    for (int p = 0; p < N - 1; ++p) {
+        Dn = W[p + 3] - W[p + 2];
+        const T phi_next = pfc_phi_d(W[p + 2], D, Dn, a, ac1, ac2, F2);
+        blk[q] = fmax(W[p + 2] + phi_prev - phi_next, T(0));
+        phi_prev = phi_next;
+        D = Dn;
+        q += step;
+    }
+    blk[q] = fmax(top + phi_prev, T(0));
+}
+
 template <class T, int N>
 __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3Params& P, const double* EB, T F2) {
     constexpr int PZ = N | 1;
@@ -423,68 +473,54 @@ __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3
         d0 = C * (EB[2] + EB[4] * c0 - EB[3] * c1); d1 = C * EB[4] * P.dv[0]; d2 = -C * EB[3] * P.dv[1];
     }
     const T s0 = (T)d0, s1 = (T)d1, s2 = (T)d2;
+    const int stride = d == 0 ? N * PZ : (d == 1 ? PZ : 1);
     for (int pen = threadIdx.x; pen < N * N; pen += blockDim.x) {
         const int i1 = pen / N, i2 = pen % N;
         const int base = d == 0 ? i1 * PZ + i2 : (d == 1 ? i1 * N * PZ + i2 : (i1 * N + i2) * PZ);
-        const int stride = d == 0 ? N * PZ : (d == 1 ? PZ : 1);
         const T s = fma(s1, (T)i1, fma(s2, (T)i2, s0));
         const bool pos = s >= T(0);
         const ShiftT<T> sh(fabs(s));
-        const int K = sh.K > N + 2 ? N + 2 : sh.K;
-        const int first = pos ? base : base + (N - 1) * stride;
-        const int step = pos ? stride : -stride;
-        // W[j + 2] = g_{j - K}, j = -2 .. N-1, zero outside the box
-        T W[N + 2];
-        T top;
-        if (__all(K == 0)) {
-            W[0] = T(0);
-            W[1] = T(0);
-            const T* q = blk + first;
+        if (__all(sh.K == 0)) {
+            T* pb = blk + base;
+            T w[N];
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                W[j + 2] = *q;
-                q += step;
+            for (int m = 0; m < N; ++m) w[m] = pb[m * stride];
+            const T cA = pos ? sh.ac1 : -sh.ac2;
+            const T cB = pos ? sh.ac2 : -sh.ac1;
+            // phi_m: partial flux of cell m in the lane's direction
+            T Dm = w[0];
+            T Dp = w[1] - w[0];
+            T phi_m = sub_cell_flux(w[0], Dm, Dp, sh.a, cA, cB, F2);
+            T Fprev = T(0);
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                T Fnext = T(0), phi_n = T(0);
+                if (m + 1 < N) {
+                    Dm = Dp;
+                    Dp = (m + 2 < N ? w[m + 2] : T(0)) - w[m + 1];
+                    phi_n = sub_cell_flux(w[m + 1], Dm, Dp, sh.a, cA, cB, F2);
+                    Fnext = pos ? phi_m : -phi_n;
+                }
+                pb[m * stride] = fmax(w[m] + Fprev - Fnext, T(0));
+                Fprev = Fnext;
+                phi_m = phi_n;
             }
-            top = W[N + 1];
         } else {
-            int a = first - (K + 2) * step;
-#pragma unroll
-            for (int j = -2; j < N; ++j) {
-                const bool in = j - K >= 0;
-                const T v = blk[in ? a : first];
-                W[j + 2] = in ? v : T(0);
-                a += step;
-            }
-            // every cell within K of the wall ends in the wall cell
-            top = T(0);
-            for (int m = (N - 1 - K > 0 ? N - 1 - K : 0); m < N; ++m) top += blk[first + m * step];
+            const int K = sh.K > N + 2 ? N + 2 : sh.K;
+            const int first = pos ? base : base + (N - 1) * stride;
+            pencil_shifted<T, N>(blk, first, pos ? stride : -stride, K, sh.a, sh.ac1, sh.ac2, F2);
         }
-        const T* w = W;
-        T D = w[1] - w[0];                       // D_i = w_i - w_{i-1}
-        T Dn = w[2] - w[1];
-        T phi_prev = pfc_phi_d(w[1], D, Dn, sh.a, sh.ac1, sh.ac2, F2);   // phi at window index 1
-        D = Dn;
-        T* q = blk + first;
-#pragma unroll
-        for (int p = 0; p < N - 1; ++p) {
-            Dn = w[p + 3] - w[p + 2];
-            const T phi_next = pfc_phi_d(w[p + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
-            *q = fmax(w[p + 2] + phi_prev - phi_next, T(0));
-            phi_prev = phi_next;
-            D = Dn;
-            q += step;
-        }
-        // wall cell: the cells that reach it plus the partial flux at window index N
-        *q = fmax(top + phi_prev, T(0));
     }
 }
 
-template <class T, int N>
-__global__ void __launch_bounds__(256)
+template <class T, int N, int NTH>
+__global__ void __launch_bounds__(NTH)
 pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const double* __restrict__ B, V3Params P,
                    const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
     constexpr int PZ = N | 1;
     constexpr int NV = N * N * N;
+    constexpr int PER = NV / NTH;            // values per thread (NTH divides N^3)
+    static_assert(PER * NTH == NV, "thread count must divide the block");
     __shared__ T blk[N * N * PZ];
     __shared__ double EB[6];
     const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
@@ -493,29 +529,41 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
         EB[threadIdx.x] = E[cell * 3 + threadIdx.x];
         EB[3 + threadIdx.x] = B ? B[cell * 3 + threadIdx.x] : 0.0;
     }
+    // all loads of the block are issued before the first shared-memory store
     const T* src = fin + cell * NV;
-    for (int e = threadIdx.x; e < NV; e += blockDim.x) blk[e + (e / N) * (PZ - N)] = src[e];
-    __syncthreads();
-    double ebl[6];
+    T v[PER];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ebl[k] = EB[k];
+    for (int j = 0; j < PER; ++j) v[j] = src[threadIdx.x + j * NTH];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = threadIdx.x + j * NTH;
+        blk[e + (e / N) * (PZ - N)] = v[j];
+    }
+    __syncthreads();
+    // each sweep reads the fields from shared memory after its barrier, which
+    // keeps the five sweeps' shift set-ups from being hoisted (and held live)
     const double half = 0.5 * P.tau;
-    sweep_cube<T, N>(blk, 0, half, P, ebl, F2);
+    sweep_cube<T, N>(blk, 0, half, P, EB, F2);
     __syncthreads();
-    sweep_cube<T, N>(blk, 1, half, P, ebl, F2);
+    sweep_cube<T, N>(blk, 1, half, P, EB, F2);
     __syncthreads();
-    sweep_cube<T, N>(blk, 2, P.tau, P, ebl, F2);
+    sweep_cube<T, N>(blk, 2, P.tau, P, EB, F2);
     __syncthreads();
-    sweep_cube<T, N>(blk, 1, half, P, ebl, F2);
+    sweep_cube<T, N>(blk, 1, half, P, EB, F2);
     __syncthreads();
-    sweep_cube<T, N>(blk, 0, half, P, ebl, F2);
+    sweep_cube<T, N>(blk, 0, half, P, EB, F2);
     __syncthreads();
     T* dst = fout + cell * NV;
     T mx = T(0);
-    for (int e = threadIdx.x; e < NV; e += blockDim.x) {
-        const T o = blk[e + (e / N) * (PZ - N)];
-        dst[e] = o;
-        mx = fmax(mx, o);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = threadIdx.x + j * NTH;
+        v[j] = blk[e + (e / N) * (PZ - N)];
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        dst[threadIdx.x + j * NTH] = v[j];
+        mx = fmax(mx, v[j]);
     }
     if (max_out) block_max_to(mx, max_out);
 }
@@ -590,13 +638,13 @@ hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E
     const bool cube = P.nvx == P.nvy && P.nvy == P.nvz;
     auto* mo = (typename Bits<T>::U*)max_out;
     if (cube && P.nvx == 16) {
-        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 16>), dim3((unsigned)cells), dim3(256), 0, st, fin, fout, E, B, P,
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 16, 256>), dim3((unsigned)cells), dim3(256), 0, st, fin, fout, E, B, P,
                            (const T*)finf, mo);
     } else if (cube && P.nvx == 12) {
-        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 12>), dim3((unsigned)cells), dim3(192), 0, st, fin, fout, E, B, P,
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 12, 192>), dim3((unsigned)cells), dim3(192), 0, st, fin, fout, E, B, P,
                            (const T*)finf, mo);
     } else if (cube && P.nvx == 8) {
-        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 8>), dim3((unsigned)cells), dim3(64), 0, st, fin, fout, E, B, P,
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 8, 64>), dim3((unsigned)cells), dim3(64), 0, st, fin, fout, E, B, P,
                            (const T*)finf, mo);
     } else if (nmax <= 8) {
         hipLaunchKernelGGL((pfc_v3_kernel<T, 8>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, E, B,
