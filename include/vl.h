@@ -196,14 +196,18 @@ vl_status vl_step(vl_ctx* ctx, vl_state* st, double dt, vl_stream stream);
 vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mom, double* out,
                          vl_stream stream);
 
-/* Kernel timing (tracing aid).  When enabled, every launch group issued by
- * the entry points of ctx is bracketed by HIP events recorded on the stream
- * it runs on.  vl_timing_read waits for the recorded events, returns the
- * summed milliseconds and launch-group counts per category (arrays of
- * VL_T_COUNT entries) since the previous read, and clears them. */
+/* Kernel timing (tracing aid).  mask selects categories: bit k (1u << VL_T_k)
+ * brackets every launch group of category k issued by the entry points of
+ * ctx with two HIP events recorded on the stream it runs on; 0 turns timing
+ * off, VL_T_ALL times everything.  Each bracket adds two event records to the
+ * stream, so timing few categories perturbs the step least.  vl_timing_read
+ * waits for the recorded events, returns the summed milliseconds and
+ * launch-group counts per category (arrays of VL_T_COUNT entries) since the
+ * previous read, and clears them. */
 enum { VL_T_MAX = 0, VL_T_PFC_X, VL_T_PFC_Y, VL_T_PFC_V, VL_T_MOMENTS, VL_T_FLUID, VL_T_FIT, VL_T_FIELDS,
        VL_T_COPY, VL_T_COUNT };
-vl_status vl_timing_enable(vl_ctx* ctx, int32_t on);
+#define VL_T_ALL ((uint32_t)((1u << VL_T_COUNT) - 1u))
+vl_status vl_timing_enable(vl_ctx* ctx, uint32_t mask);
 vl_status vl_timing_read(vl_ctx* ctx, double* ms, int64_t* count);
 
 vl_status vl_sync(vl_ctx* ctx, vl_stream stream);       /* wait for the stream, report device errors */

@@ -20,7 +20,7 @@ struct vl_ctx {
     vl_config cfg;
     int device = -1;
     // kernel timing (vl_timing_enable / vl_timing_read)
-    bool timing = false;
+    uint32_t timing = 0;   // bit k: time launch groups of category k
     std::vector<vl_timer> pending;
     std::vector<hipEvent_t> pool;
     double t_ms[VL_T_COUNT] = {0};
@@ -76,7 +76,7 @@ struct Timed {
     hipStream_t st;
     vl_timer t{};
     bool on;
-    Timed(vl_ctx* c_, int cat, hipStream_t st_) : c(c_), st(st_), on(c_->timing) {
+    Timed(vl_ctx* c_, int cat, hipStream_t st_) : c(c_), st(st_), on(((c_->timing >> cat) & 1u) != 0) {
         if (!on) return;
         t.cat = cat;
         t.start = take_event(c);
@@ -609,9 +609,9 @@ vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mo
     return VL_OK;
 }
 
-vl_status vl_timing_enable(vl_ctx* ctx, int32_t on) {
+vl_status vl_timing_enable(vl_ctx* ctx, uint32_t mask) {
     if (!ctx) return VL_EINVAL;
-    ctx->timing = on != 0;
+    ctx->timing = mask & ((1u << VL_T_COUNT) - 1u);
     return VL_OK;
 }
 

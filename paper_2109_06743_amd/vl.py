@@ -85,7 +85,7 @@ def load():
         "vl_step": ([vp, ctypes.POINTER(State), d, vp], i32),
         "vl_mass_energy": ([vp, i32, vp, vp, vp, vp], i32),
         "vl_sync": ([vp, vp], i32),
-        "vl_timing_enable": ([vp, i32], i32),
+        "vl_timing_enable": ([vp, ctypes.c_uint32], i32),
         "vl_timing_read": ([vp, vp, vp], i32),
         "vl_status_str": ([i32], ctypes.c_char_p),
         "vl_last_error": ([vp], ctypes.c_char_p),
@@ -217,7 +217,16 @@ class Context:
         self._check(self.lib.vl_sync(self.h, _stream(stream)))
 
     def timing_enable(self, on=True):
-        self._check(self.lib.vl_timing_enable(self.h, int(bool(on))))
+        """on: True/False for every category, or an iterable of category names."""
+        if on is True:
+            mask = (1 << len(TIMING_CATEGORIES)) - 1
+        elif not on:
+            mask = 0
+        else:
+            mask = 0
+            for name in on:
+                mask |= 1 << TIMING_CATEGORIES.index(name)
+        self._check(self.lib.vl_timing_enable(self.h, mask))
 
     def timing_read(self):
         """{category: (total_ms, launch_groups)} since the previous read."""
