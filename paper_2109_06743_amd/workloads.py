@@ -168,3 +168,19 @@ CONFIGS = {
     "gem": dict(builder="gem", kwargs=dict()),
     "tail": dict(builder="tail", kwargs=dict()),
 }
+
+
+def mlp_init(seed=0):
+    """Initial parameters of the heat-flux network (13520 FP32 values, layout
+    W1[64][64] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[16][64] b4[16]):
+    Glorot-uniform weights, zero biases, the six padding output rows zero.
+    Random numbers only; the network itself lives elsewhere."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((64, 64), (64, 64), (64, 64), (16, 64)):
+        lim = math.sqrt(6.0 / (fan_in + (10 if fan_out == 16 else fan_out)))
+        W = rng.uniform(-lim, lim, size=(fan_out, fan_in))
+        if fan_out == 16:
+            W[10:] = 0.0
+        parts += [W.ravel(), np.zeros(fan_out)]
+    return np.concatenate(parts).astype(np.float32)
