@@ -59,7 +59,7 @@ typedef enum {
 
 enum { VL_F32 = 0, VL_F64 = 1 };
 enum { VL_BC_REFLECT = 0 };
-enum { VL_CLOSURE_KINETIC = 0 };
+enum { VL_CLOSURE_KINETIC = 0, VL_CLOSURE_MLP = 1 };
 enum { VL_MAX_SPECIES = 2 };
 
 typedef struct {
@@ -81,7 +81,11 @@ typedef struct {
     int32_t f_dtype;      /* VL_F32 or VL_F64 */
     double c;             /* speed of light (2X3V); eps0 = 1/c^2, mu0 = 1 */
     int32_t fit;          /* 0: standard PFC step, 1: moment fitting (Algorithm 1) */
-    int32_t closure;      /* VL_CLOSURE_KINETIC: third moment from f */
+    int32_t closure;      /* VL_CLOSURE_KINETIC: third moment from f (Algorithm 1);
+                             VL_CLOSURE_MLP (2X3V with fit = 1): heat flux from the learned
+                             network, the kinetic one as judge and fallback (see vl_step) */
+    double closure_tol;   /* VL_CLOSURE_MLP: largest accepted relative L2 error of the network's
+                             heat-flux vector against the kinetic one (e.g. 0.05) */
 } vl_config;
 
 typedef struct vl_ctx vl_ctx;
@@ -185,10 +189,65 @@ typedef struct {
     double* work;
     int64_t* counters;
     int32_t f_max_valid;
+    /* VL_CLOSURE_MLP only (NULL otherwise) */
+    const float* mlp_params;    /* VL_MLP_NPARAM network parameters (device) */
+    int32_t* closure_fallback;  /* out, int32[nspecies] (device): 1 where the step used the kinetic
+                                   third moment because the network's error exceeded closure_tol */
+    double* closure_err;        /* out, double[nspecies] (device): that relative L2 error */
 } vl_state;
 
 size_t vl_step_work_size(const vl_ctx* ctx);
 vl_status vl_step(vl_ctx* ctx, vl_state* st, double dt, vl_stream stream);
+/* With closure = VL_CLOSURE_MLP the fluid RK3 of every species takes its
+ * third moment at each stage from the network applied to that stage's fluid
+ * state (Q-calligraphic = Q_net + sym(u P) - 2 m n uuu), instead of from f.
+ * Before the fluid update the network is judged on the moments of f^{t+1}:
+ * the relative L2 error (over the species' cells) of its heat-flux vector
+ * q_i = Q_ijj against the kinetic one goes to closure_err[s]; above
+ * closure_tol the step uses the kinetic third moment instead (as with
+ * VL_CLOSURE_KINETIC) and sets closure_fallback[s].  No host synchronisation:
+ * the decision is taken on the device. */
+
+/* ---- Learned heat-flux closure (a network of this library, not of the paper;
+ * the paper's fluid-only closure is the temperature-gradient one, Eq. 5).
+ * Network: features (64) -> tanh 64 -> tanh 64 -> tanh 64 -> 16 outputs, of
+ * which the first 10 are the heat-flux tensor Q_ijk / (n m v_t^3) in the
+ * order xxx,xxy,xxz,xyy,xyz,xzz,yyy,yyz,yzz,zzz (v_t^2 = tr(T)/(3m)).
+ * Parameters: one FP32 vector of VL_MLP_NPARAM values, row-major [out][in]:
+ * W1[64][64] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[16][64] b4[16];
+ * rows 10..15 of W4 and b4 are padding (kept 0 by training).  Products use
+ * BF16-rounded weights and activations with FP32 accumulation (MFMA). */
+enum { VL_MLP_IN = 64, VL_MLP_WIDTH = 64, VL_MLP_OUT = 10, VL_MLP_OUT_PAD = 16, VL_MLP_NPARAM = 13520 };
+
+/* Features of every spatial cell of species s (2X3V) from a moment array whose
+ * first ten entries per cell are (n, nu, P): raw moments (stride 20) or a
+ * fluid state (stride 10).  x: uint16 BF16 [cells][64]; scale: double
+ * [cells] = n m v_t^3 (0 for a cell with n <= 1e-12 or tr T <= 0, whose
+ * features are 0).  Features: u/v_t, T/T_ref, then for n/n_c, u/v_t, T/T_ref
+ * on the 3x3 stencil the differences d_x, d_y, d_xx, d_yy, d_xy (grid units;
+ * x periodic, y mirrored at the walls), a species one-hot, zero padding. */
+vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t stride, uint16_t* x,
+                          double* scale, vl_stream stream);
+/* Training targets: normalised kinetic heat flux [cells][16] (FP32, entries
+ * 10..15 zero) from raw moments [cells][20] of species s. */
+vl_status vl_mlp_targets(vl_ctx* ctx, int32_t s, const double* mom, float* y, vl_stream stream);
+/* y[n][16] = network(x[n][64]).  n >= 1.  x must be 8-byte and y 16-byte
+ * aligned (VL_EINVAL otherwise), as for the training calls below. */
+vl_status vl_mlp_forward(vl_ctx* ctx, const float* params, const uint16_t* x, int64_t n, float* y,
+                         vl_stream stream);
+/* Scratch (floats) for vl_mlp_gradient / vl_mlp_train_step with n samples. */
+size_t vl_mlp_work_size(int64_t n);
+/* Mean squared error over the n samples and 10 outputs and its gradient:
+ * grad_loss[0..VL_MLP_NPARAM-1] = gradient, grad_loss[VL_MLP_NPARAM] = loss
+ * (FP32, device).  Deterministic (fixed-order sums). */
+vl_status vl_mlp_gradient(vl_ctx* ctx, const float* params, const uint16_t* x, const float* y, int64_t n,
+                          float* work, float* grad_loss, vl_stream stream);
+/* vl_mlp_gradient followed by one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias correction with the 1-based step) on params, with moment vectors
+ * adam_m, adam_v (VL_MLP_NPARAM floats each, zero before step 1). */
+vl_status vl_mlp_train_step(vl_ctx* ctx, float* params, float* adam_m, float* adam_v, int64_t step, double lr,
+                            const uint16_t* x, const float* y, int64_t n, float* work, float* grad_loss,
+                            vl_stream stream);
 
 /* Diagnostics: total mass of species s (sum f dV dX, FP64) and the
  * kinetic+thermal energy sum tr(P)/2 dX (3V) or P/2 dX (1V) from a raw

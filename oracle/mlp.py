@@ -311,3 +311,33 @@ def gradient_closure_divergence(U, m, q, dx, dy):
     lap = ((np.roll(T6, -1, axis=1) - 2.0 * T6 + np.roll(T6, 1, axis=1)) / dx ** 2
            + (Tg[2:] - 2.0 * T6 + Tg[:-2]) / dy ** 2)
     return -(CHI * d_s) * (n * vt)[..., None] * lap
+
+
+# ------------------------------------------------- the closure in a step ----
+def network_heat_flux(U, m, species, params):
+    """Normalised network output y[ny, nx, 16] and scale[ny, nx] for the cells
+    of U[ny, nx, >=10]."""
+    ny, nx = U.shape[:2]
+    x, scale = features_bf16(U, m, species)
+    y, _ = forward(params, x)
+    return y.reshape(ny, nx, N_OUT_PAD), scale.reshape(ny, nx)
+
+
+def closure_qcal(U, m, species, params):
+    """Q-calligraphic of every cell from the network applied to U."""
+    y, scale = network_heat_flux(U, m, species, params)
+    return qcal_from_closure(U, y, scale, m)
+
+
+def judge_error(mom, m, species, params):
+    """Relative L2 error over the cells of the network's heat-flux vector
+    q_i = sum_j Q_ijj against the kinetic one, both from raw moments mom."""
+    y, scale = network_heat_flux(mom[..., :10], m, species, params)
+    Qn = scale[..., None] * y[..., :N_OUT]
+    Qk = heat_flux(mom, m)
+
+    def qvec(Q):
+        return np.stack([Q[..., 0] + Q[..., 3] + Q[..., 5], Q[..., 1] + Q[..., 6] + Q[..., 8],
+                         Q[..., 2] + Q[..., 7] + Q[..., 9]], axis=-1)
+    qn, qk = qvec(Qn), qvec(Qk)
+    return float(np.sqrt(((qn - qk) ** 2).sum()) / max(np.sqrt((qk ** 2).sum()), 1e-300))

@@ -16,10 +16,16 @@ solver), with these readings where it is silent:
   before fitting, at t+1/2 their mean (Algorithm 1, "interpolate").
 * With fitting switched off the step is the standard PFC Vlasov step (the
   fluid is not advanced).
+* Learned closure (cfg["closure"] == "mlp", 2X3V; not in the paper): the
+  network (oracle.mlp) is judged on the moments of f^{t+1} before fitting;
+  if its heat-flux error exceeds cfg["closure_tol"] (or when st["fallback"]
+  says so for that species) the step is the kinetic one, otherwise the fluid
+  RK3 takes each stage's Q-calligraphic from the network applied to that
+  stage's state.
 """
 import numpy as np
 
-from . import fields, fluid, moments, vlasov
+from . import fields, fluid, mlp, moments, vlasov
 
 
 # ---------------------------------------------------------------- 1X1V ----
@@ -81,7 +87,8 @@ def step_2x3v(st, cfg, dt):
     E_h, B_h = fields.cell_centred(F)
     E_0, B_0 = fields.cell_centred(F_t)
     fields_t1 = (2.0 * E_h - E_0, 2.0 * B_h - B_0)
-    out = {"f": [], "U": [], "mom_pre": [], "mom_post": [], "clipped": 0, "skipped": 0}
+    out = {"f": [], "U": [], "mom_pre": [], "mom_post": [], "clipped": 0, "skipped": 0,
+           "closure_err": [], "fallback": []}
     for k, sp in enumerate(species):
         q, m = sp["q"], sp["m"]
         v, dv = _grids(cfg, sp)
@@ -91,8 +98,19 @@ def step_2x3v(st, cfg, dt):
         mom_pre = moments.raw_moments_3v(f, v, dv, m)
         U = st["U"][k]
         if cfg.get("fit"):
-            U = fluid.rk3_3v(U, st["mom_post"][k][..., 10:], mom_pre[..., 10:],
-                             (E_0, B_0), fields_t1, (E_h, B_h), q, m, dx, dy, dt)
+            use_net = False
+            if cfg.get("closure") == "mlp":
+                err = mlp.judge_error(mom_pre, m, k, st["mlp_params"])
+                fb = st["fallback"][k] if st.get("fallback") is not None else not (err <= cfg["closure_tol"])
+                out["closure_err"].append(err)
+                out["fallback"].append(bool(fb))
+                use_net = not fb
+            if use_net:
+                U = fluid.rk3_3v_stagewise(U, lambda V, k=k, m=m: mlp.closure_qcal(V, m, k, st["mlp_params"]),
+                                           (E_0, B_0), fields_t1, (E_h, B_h), q, m, dx, dy, dt)
+            else:
+                U = fluid.rk3_3v(U, st["mom_post"][k][..., 10:], mom_pre[..., 10:],
+                                 (E_0, B_0), fields_t1, (E_h, B_h), q, m, dx, dy, dt)
             f, U, cl, sk = moments.moment_fit_3v(f, mom_pre, U, m, v, dv)
             out["clipped"] += cl
             out["skipped"] += sk

@@ -275,8 +275,6 @@ hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom
     double* U2 = U1 + cells * 10;
     double* Hx = U2 + cells * 10;
     double* Hy = Hx + cells * 10;
-    FluidArgs A{nx, ny, m, q, dx, dy};
-    dim3 blk(64), gc((nx + 63) / 64, ny), gy((nx + 63) / 64, ny + 1);
     struct Stage { const double* Us; const double* Un; double* Uo; const double* QA; const double* QB; double wa, wb;
                    const double* E; const double* B; double a, b; };
     const Stage S[3] = {
@@ -285,11 +283,23 @@ hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom
         {U2, U, U, mom_t, mom_t1, 0.5, 0.5, E_th, B_th, 1.0 / 3.0, 2.0 / 3.0},
     };
     for (int k = 0; k < 3; ++k) {
-        hipLaunchKernelGGL(flux_x3_kernel, gc, blk, 0, st, S[k].Us, S[k].QA, S[k].QB, S[k].wa, S[k].wb, A, Hx);
-        hipLaunchKernelGGL(flux_y3_kernel, gy, blk, 0, st, S[k].Us, S[k].QA, S[k].QB, S[k].wa, S[k].wb, A, Hy);
-        hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, S[k].Us, S[k].Un, S[k].Uo, Hx, Hy, S[k].E, S[k].B, S[k].a,
-                           S[k].b, dt, A);
+        const hipError_t e = launch_fluid_stage_3v(S[k].Us, S[k].Un, S[k].Uo, S[k].QA, S[k].QB, S[k].wa, S[k].wb,
+                                                   S[k].E, S[k].B, S[k].a, S[k].b, dt, nx, ny, q, m, dx, dy, Hx, Hy,
+                                                   st);
+        if (e != hipSuccess) return e;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
+                                 double wa, double wb, const double* E, const double* B, double a, double b, double dt,
+                                 int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
+                                 hipStream_t st) {
+    FluidArgs A{nx, ny, m, q, dx, dy};
+    dim3 blk(64), gc((nx + 63) / 64, ny), gy((nx + 63) / 64, ny + 1);
+    hipLaunchKernelGGL(flux_x3_kernel, gc, blk, 0, st, Us, QA, QB, wa, wb, A, Hx);
+    hipLaunchKernelGGL(flux_y3_kernel, gy, blk, 0, st, Us, QA, QB, wa, wb, A, Hy);
+    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A);
     return hipGetLastError();
 }
 

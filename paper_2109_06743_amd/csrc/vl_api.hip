@@ -133,9 +133,18 @@ size_t fluid_doubles(const vl_config& c) {
     return 9 * (size_t)c.nx;
 }
 
+// Learned-closure scratch of the step: features (BF16 [cells][64] = 16
+// doubles per cell), scale (1), network outputs (FP32 [cells][16] = 8), third
+// moment (20 per cell, raw-moment layout), judge partials.
+size_t mlp_step_doubles(const vl_config& c) {
+    if (c.closure != VL_CLOSURE_MLP) return 0;
+    const size_t cells = (size_t)c.nx * c.ny;
+    return 45 * cells + vl::mlp_judge_part_doubles() + 2;
+}
+
 size_t step_doubles(const vl_config& c) {
     const size_t cells = (size_t)c.nx * c.ny;
-    if (c.dim_v == 3) return yee_doubles(c) + 18 * cells + fluid_doubles(c);
+    if (c.dim_v == 3) return yee_doubles(c) + 18 * cells + fluid_doubles(c) + mlp_step_doubles(c);
     return 4 * (size_t)c.nx + 3 * (size_t)c.nx + fluid_doubles(c);
 }
 
@@ -249,6 +258,50 @@ vl_status fluid_step_impl(vl_ctx* ctx, int s, double* U, const double* mom_t, co
     return VL_OK;
 }
 
+// Fluid RK3 of species s with the learned third moment (2X3V): judge the
+// network on mom_t1 (moments of f^{t+1}), then run the three stages, each
+// with the network's Q-calligraphic of that stage's state, or the kinetic
+// one where the judge set the fallback flag.
+vl_status fluid_step_mlp(vl_ctx* ctx, int s, const vl_state* S, const double* E_t, const double* B_t,
+                         const double* E_t1, const double* B_t1, const double* E_th, const double* B_th, double dt,
+                         double* fwork, double* mwork, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const vl_species& sp = c.sp[s];
+    const long long cells = ctx->cells;
+    float* y = (float*)mwork;                           // 16-byte aligned (the caller aligns mwork)
+    unsigned short* x = (unsigned short*)(mwork + 8 * cells);
+    double* scale = mwork + 24 * cells;
+    double* qc = mwork + 25 * cells;
+    double* part = mwork + 45 * cells;
+    const double* mom_t = S->mom_post[s];
+    const double* mom_t1 = S->mom_pre[s];
+    int* fb = S->closure_fallback + s;
+    Timed tm(ctx, VL_T_FLUID, st);
+    VL_HIP(vl::launch_mlp_features(mom_t1, 20, c.nx, c.ny, sp.m, s, x, scale, st));
+    VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, cells, y, st));
+    VL_HIP(vl::launch_mlp_judge(mom_t1, scale, y, cells, sp.m, c.closure_tol, part, fb, S->closure_err + s, st));
+    double* U = S->U[s];
+    double* U1 = fwork;
+    double* U2 = U1 + cells * 10;
+    double* Hx = U2 + cells * 10;
+    double* Hy = Hx + cells * 10;
+    struct Stage { const double* Us; const double* Un; double* Uo; const double* QA; const double* QB; double wa, wb;
+                   const double* E; const double* B; double a, b; };
+    const Stage G[3] = {
+        {U, U, U1, mom_t, mom_t, 1.0, 0.0, E_t, B_t, 0.0, 1.0},
+        {U1, U, U2, mom_t1, mom_t1, 1.0, 0.0, E_t1, B_t1, 0.75, 0.25},
+        {U2, U, U, mom_t, mom_t1, 0.5, 0.5, E_th, B_th, 1.0 / 3.0, 2.0 / 3.0},
+    };
+    for (int k = 0; k < 3; ++k) {
+        VL_HIP(vl::launch_mlp_features(G[k].Us, 10, c.nx, c.ny, sp.m, s, x, scale, st));
+        VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, cells, y, st));
+        VL_HIP(vl::launch_mlp_qcal(G[k].Us, scale, y, fb, G[k].QA, G[k].QB, G[k].wa, G[k].wb, cells, sp.m, qc, st));
+        VL_HIP(vl::launch_fluid_stage_3v(G[k].Us, G[k].Un, G[k].Uo, qc, qc, 1.0, 0.0, G[k].E, G[k].B, G[k].a, G[k].b,
+                                         dt, c.nx, c.ny, sp.q, sp.m, dx_of(c), dy_of(c), Hx, Hy, st));
+    }
+    return VL_OK;
+}
+
 #define DISPATCH(ctx, call_f32, call_f64) ((ctx)->cfg.f_dtype == VL_F32 ? (call_f32) : (call_f64))
 
 template <class T>
@@ -272,6 +325,8 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         double* E_1 = B_h + 3 * cells;
         double* B_1 = E_1 + 3 * cells;
         double* fwork = B_1 + 3 * cells;
+        double* mwork = fwork + fluid_doubles(c);
+        mwork += ((uintptr_t)mwork & 15u) ? 1 : 0;         // network outputs are stored as 16-byte vectors
         {
             Timed tm(ctx, VL_T_FIELDS, st);
             if (c.fit) {
@@ -302,9 +357,12 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
                 return r;
             if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
             if (c.fit) {
-                if ((r = fluid_step_impl(ctx, s, S->U[s], S->mom_post[s], S->mom_pre[s], E_t, B_t, E_1, B_1, E_h, B_h,
-                                         dt, fwork, st)) != VL_OK)
-                    return r;
+                if (c.closure == VL_CLOSURE_MLP)
+                    r = fluid_step_mlp(ctx, s, S, E_t, B_t, E_1, B_1, E_h, B_h, dt, fwork, mwork, st);
+                else
+                    r = fluid_step_impl(ctx, s, S->U[s], S->mom_post[s], S->mom_pre[s], E_t, B_t, E_1, B_1, E_h, B_h,
+                                        dt, fwork, st);
+                if (r != VL_OK) return r;
                 if ((r = fit_typed<T>(ctx, s, f, f, S->mom_pre[s], S->U[s], S->mom_post[s], S->counters,
                                       slot(ctx, 0, s), st)) != VL_OK)
                     return r;
@@ -407,7 +465,12 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
     if (c.f_dtype != VL_F32 && c.f_dtype != VL_F64) return VL_EINVAL;
     if (c.dim_x == 2 && !finite_pos(c.c)) return VL_EINVAL;
     if (c.fit != 0 && c.fit != 1) return VL_EINVAL;
-    if (c.closure != VL_CLOSURE_KINETIC) return VL_ENOTSUP;
+    if (c.closure == VL_CLOSURE_MLP) {
+        if (c.dim_v != 3 || c.fit != 1) return VL_ENOTSUP;   // the learned closure serves the 2X3V fitting step
+        if (!(std::isfinite(c.closure_tol) && c.closure_tol >= 0.0)) return VL_EINVAL;
+    } else if (c.closure != VL_CLOSURE_KINETIC) {
+        return VL_ENOTSUP;
+    }
     const size_t elem = c.f_dtype == VL_F32 ? 4 : 8;
     for (int s = 0; s < c.nspecies; ++s) {
         const vl_species& sp = c.sp[s];
@@ -582,10 +645,77 @@ vl_status vl_step(vl_ctx* ctx, vl_state* S, double dt, vl_stream stream) {
         if (S->f[s] == S->f_tmp[s]) return fail(ctx, VL_EALIAS, "f and f_tmp alias");
         if (S->mom_pre[s] == S->mom_post[s]) return fail(ctx, VL_EALIAS, "mom_pre and mom_post alias");
     }
+    if (c.closure == VL_CLOSURE_MLP && (!S->mlp_params || !S->closure_fallback || !S->closure_err))
+        return fail(ctx, VL_EINVAL, "the learned closure needs mlp_params, closure_fallback and closure_err");
     vl_status r;
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     return DISPATCH(ctx, step_typed<float>(ctx, S, dt, st), step_typed<double>(ctx, S, dt, st));
+}
+
+vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t stride, uint16_t* x, double* scale,
+                          vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (ctx->cfg.dim_v != 3) return fail(ctx, VL_ENOTSUP, "the learned closure is defined for 2X3V");
+    if (!mom || !x || !scale) return fail(ctx, VL_EINVAL, "null argument");
+    if (stride != 10 && stride != 20) return fail(ctx, VL_EINVAL, "stride must be 10 or 20");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    const vl_config& c = ctx->cfg;
+    VL_HIP(vl::launch_mlp_features(mom, stride, c.nx, c.ny, c.sp[s].m, s, x, scale, (hipStream_t)stream));
+    return VL_OK;
+}
+
+vl_status vl_mlp_targets(vl_ctx* ctx, int32_t s, const double* mom, float* y, vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (ctx->cfg.dim_v != 3) return fail(ctx, VL_ENOTSUP, "the learned closure is defined for 2X3V");
+    if (!mom || !y) return fail(ctx, VL_EINVAL, "null argument");
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    VL_HIP(vl::launch_mlp_targets(mom, ctx->cells, ctx->cfg.sp[s].m, y, (hipStream_t)stream));
+    return VL_OK;
+}
+
+vl_status vl_mlp_forward(vl_ctx* ctx, const float* params, const uint16_t* x, int64_t n, float* y,
+                         vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    if (!params || !x || !y) return fail(ctx, VL_EINVAL, "null argument");
+    if (n < 1) return fail(ctx, VL_EINVAL, "n must be >= 1");
+    if (((uintptr_t)x & 7u) || ((uintptr_t)y & 15u)) return fail(ctx, VL_EINVAL, "x must be 8-, y 16-byte aligned");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    VL_HIP(vl::launch_mlp_forward(params, x, n, y, (hipStream_t)stream));
+    return VL_OK;
+}
+
+size_t vl_mlp_work_size(int64_t n) { return n < 1 ? 0 : vl::mlp_part_floats(n); }
+
+vl_status vl_mlp_gradient(vl_ctx* ctx, const float* params, const uint16_t* x, const float* y, int64_t n,
+                          float* work, float* grad_loss, vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    if (!params || !x || !y || !work || !grad_loss) return fail(ctx, VL_EINVAL, "null argument");
+    if (n < 1) return fail(ctx, VL_EINVAL, "n must be >= 1");
+    if (((uintptr_t)x & 7u) || ((uintptr_t)y & 15u)) return fail(ctx, VL_EINVAL, "x must be 8-, y 16-byte aligned");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    VL_HIP(vl::launch_mlp_gradient(params, x, y, n, work, grad_loss, (hipStream_t)stream));
+    return VL_OK;
+}
+
+vl_status vl_mlp_train_step(vl_ctx* ctx, float* params, float* adam_m, float* adam_v, int64_t step, double lr,
+                            const uint16_t* x, const float* y, int64_t n, float* work, float* grad_loss,
+                            vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    if (!params || !adam_m || !adam_v || !x || !y || !work || !grad_loss) return fail(ctx, VL_EINVAL, "null argument");
+    if (n < 1 || step < 1) return fail(ctx, VL_EINVAL, "n and step must be >= 1");
+    if (((uintptr_t)x & 7u) || ((uintptr_t)y & 15u)) return fail(ctx, VL_EINVAL, "x must be 8-, y 16-byte aligned");
+    if (!finite_pos(lr)) return fail(ctx, VL_EINVAL, "lr must be finite and > 0");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    VL_HIP(vl::launch_mlp_gradient(params, x, y, n, work, grad_loss, st));
+    VL_HIP(vl::launch_mlp_adam(params, adam_m, adam_v, grad_loss, step, lr, st));
+    return VL_OK;
 }
 
 vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mom, double* out, vl_stream stream) {

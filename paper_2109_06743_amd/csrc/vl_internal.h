@@ -72,6 +72,32 @@ hipError_t launch_fluid_rk3_1v(double* U, const double* mom_t, const double* mom
                                const double* E_t1, const double* E_th, double dt, int nx, double q, double m,
                                double dx, double* work, hipStream_t st);
 
+// One SSP-RK3 stage of the 3V fluid: Uo = a Un + b (Us + dt L(Us)), third
+// moment wa QA + wb QB (raw-moment layout, entries 10..19 of 20 per cell).
+hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
+                                 double wa, double wb, const double* E, const double* B, double a, double b, double dt,
+                                 int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
+                                 hipStream_t st);
+
+// learned heat-flux closure (mlp_kernels.hip)
+constexpr int kMlpParams = 13520;
+hipError_t launch_mlp_features(const double* M, int stride, int nx, int ny, double m, int species,
+                               unsigned short* x, double* scale, hipStream_t st);
+hipError_t launch_mlp_targets(const double* M, long long cells, double m, float* y, hipStream_t st);
+hipError_t launch_mlp_forward(const float* P, const unsigned short* x, long long n, float* y, hipStream_t st);
+size_t mlp_grad_blocks(long long n);
+size_t mlp_part_floats(long long n);
+hipError_t launch_mlp_gradient(const float* P, const unsigned short* x, const float* t, long long n, float* part,
+                               float* grad, hipStream_t st);
+hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, long long step, double lr,
+                           hipStream_t st);
+hipError_t launch_mlp_qcal(const double* U, const double* scale, const float* y, const int* fallback,
+                           const double* QA, const double* QB, double wa, double wb, long long cells, double m,
+                           double* qc, hipStream_t st);
+size_t mlp_judge_part_doubles();
+hipError_t launch_mlp_judge(const double* M, const double* scale, const float* y, long long cells, double m,
+                            double tol, double* part, int* fallback, double* err, hipStream_t st);
+
 template <class T>
 hipError_t launch_mass_energy(const T* f, const double* mom, long long cells, long long nv, int kmom, int dimv,
                               double dV, double dX, double* out, double* part, hipStream_t st);

@@ -19,7 +19,10 @@ STATUS = {0: "VL_OK", 1: "VL_EINVAL", 2: "VL_EALIAS", 3: "VL_ENOTSUP", 4: "VL_ED
 EXPORTS = ["vl_create", "vl_destroy", "vl_pfc_advect_x", "vl_pfc_advect_v", "vl_moments", "vl_moment_fit",
            "vl_poisson", "vl_yee_size", "vl_maxwell_half_step", "vl_cell_fields", "vl_fluid_work_size",
            "vl_fluid_step", "vl_step_work_size", "vl_step", "vl_mass_energy", "vl_sync", "vl_status_str",
-           "vl_last_error", "vl_version", "vl_timing_enable", "vl_timing_read"]
+           "vl_last_error", "vl_version", "vl_timing_enable", "vl_timing_read", "vl_mlp_features",
+           "vl_mlp_targets", "vl_mlp_forward", "vl_mlp_work_size", "vl_mlp_gradient", "vl_mlp_train_step"]
+VL_CLOSURE_KINETIC, VL_CLOSURE_MLP = 0, 1
+MLP_IN, MLP_OUT, MLP_OUT_PAD, MLP_NPARAM = 64, 10, 16, 13520
 TIMING_CATEGORIES = ["max", "pfc_x", "pfc_y", "pfc_v", "moments", "fluid", "fit", "fields", "copy"]
 
 
@@ -39,14 +42,16 @@ class Config(ctypes.Structure):
                 ("ny", ctypes.c_int32), ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
                 ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double), ("bc_y", ctypes.c_int32),
                 ("nspecies", ctypes.c_int32), ("sp", Species * MAX_SPECIES), ("f_dtype", ctypes.c_int32),
-                ("c", ctypes.c_double), ("fit", ctypes.c_int32), ("closure", ctypes.c_int32)]
+                ("c", ctypes.c_double), ("fit", ctypes.c_int32), ("closure", ctypes.c_int32),
+                ("closure_tol", ctypes.c_double)]
 
 
 class State(ctypes.Structure):
     _fields_ = [("f", ctypes.c_void_p * MAX_SPECIES), ("f_tmp", ctypes.c_void_p * MAX_SPECIES),
                 ("mom_post", ctypes.c_void_p * MAX_SPECIES), ("mom_pre", ctypes.c_void_p * MAX_SPECIES),
                 ("U", ctypes.c_void_p * MAX_SPECIES), ("fields", ctypes.c_void_p), ("work", ctypes.c_void_p),
-                ("counters", ctypes.c_void_p), ("f_max_valid", ctypes.c_int32)]
+                ("counters", ctypes.c_void_p), ("f_max_valid", ctypes.c_int32), ("mlp_params", ctypes.c_void_p),
+                ("closure_fallback", ctypes.c_void_p), ("closure_err", ctypes.c_void_p)]
 
 
 _lib = None
@@ -87,6 +92,12 @@ def load():
         "vl_sync": ([vp, vp], i32),
         "vl_timing_enable": ([vp, ctypes.c_uint32], i32),
         "vl_timing_read": ([vp, vp, vp], i32),
+        "vl_mlp_features": ([vp, i32, vp, i32, vp, vp, vp], i32),
+        "vl_mlp_targets": ([vp, i32, vp, vp, vp], i32),
+        "vl_mlp_forward": ([vp, vp, vp, ctypes.c_int64, vp, vp], i32),
+        "vl_mlp_work_size": ([ctypes.c_int64], sz),
+        "vl_mlp_gradient": ([vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp], i32),
+        "vl_mlp_train_step": ([vp, vp, vp, vp, ctypes.c_int64, d, vp, vp, ctypes.c_int64, vp, vp, vp], i32),
         "vl_status_str": ([i32], ctypes.c_char_p),
         "vl_last_error": ([vp], ctypes.c_char_p),
         "vl_version": ([], ctypes.c_char_p),
@@ -104,7 +115,8 @@ def make_config(cfg, f_dtype="f32"):
     c = Config()
     c.f_dtype = VL_F32 if f_dtype in ("f32", "float32", np.float32) else VL_F64
     c.fit = int(bool(cfg.get("fit", False)))
-    c.closure = 0
+    c.closure = VL_CLOSURE_MLP if cfg.get("closure") == "mlp" else VL_CLOSURE_KINETIC
+    c.closure_tol = float(cfg.get("closure_tol", 0.0))
     c.bc_y = 0
     if cfg["kind"] == "1x1v":
         c.dim_x, c.dim_v = 1, 1
@@ -216,6 +228,33 @@ class Context:
     def sync(self, stream=None):
         self._check(self.lib.vl_sync(self.h, _stream(stream)))
 
+    # ---- learned heat-flux closure -----------------------------------------
+    def mlp_features(self, s, mom, stride, x, scale, stream=None):
+        """x: int16 tensor [cells, 64] (BF16 bits), scale: float64 [cells]."""
+        self._check(self.lib.vl_mlp_features(self.h, s, _ptr(mom), int(stride), _ptr(x), _ptr(scale),
+                                             _stream(stream)))
+
+    def mlp_targets(self, s, mom, y, stream=None):
+        self._check(self.lib.vl_mlp_targets(self.h, s, _ptr(mom), _ptr(y), _stream(stream)))
+
+    def mlp_forward(self, params, x, y, n=None, stream=None):
+        n = x.shape[0] if n is None else n
+        self._check(self.lib.vl_mlp_forward(self.h, _ptr(params), _ptr(x), int(n), _ptr(y), _stream(stream)))
+
+    def mlp_work_size(self, n):
+        return int(self.lib.vl_mlp_work_size(int(n)))
+
+    def mlp_gradient(self, params, x, y, work, grad_loss, n=None, stream=None):
+        n = x.shape[0] if n is None else n
+        self._check(self.lib.vl_mlp_gradient(self.h, _ptr(params), _ptr(x), _ptr(y), int(n), _ptr(work),
+                                             _ptr(grad_loss), _stream(stream)))
+
+    def mlp_train_step(self, params, m1, m2, step, lr, x, y, work, grad_loss, n=None, stream=None):
+        n = x.shape[0] if n is None else n
+        self._check(self.lib.vl_mlp_train_step(self.h, _ptr(params), _ptr(m1), _ptr(m2), int(step), float(lr),
+                                               _ptr(x), _ptr(y), int(n), _ptr(work), _ptr(grad_loss),
+                                               _stream(stream)))
+
     def timing_enable(self, on=True):
         """on: True/False for every category, or an iterable of category names."""
         if on is True:
@@ -241,7 +280,7 @@ class Context:
 class StepState:
     """Device buffers of vl_step for one context (allocated with torch)."""
 
-    def __init__(self, ctx, f_list, fields, U_list=None, mom_post_list=None, device="cuda"):
+    def __init__(self, ctx, f_list, fields, U_list=None, mom_post_list=None, mlp_params=None, device="cuda"):
         import torch
         cfg = ctx.cfg
         dt = torch.float32 if ctx.f_dtype == "f32" else torch.float64
@@ -278,6 +317,13 @@ class StepState:
         c.work = self.work.data_ptr()
         c.counters = self.counters.data_ptr()
         c.f_max_valid = 0
+        if cfg.closure == VL_CLOSURE_MLP:
+            self.mlp_params = torch.as_tensor(mlp_params, device=device).to(torch.float32).contiguous()
+            self.closure_fallback = torch.zeros(ns, dtype=torch.int32, device=device)
+            self.closure_err = torch.zeros(ns, dtype=torch.float64, device=device)
+            c.mlp_params = self.mlp_params.data_ptr()
+            c.closure_fallback = self.closure_fallback.data_ptr()
+            c.closure_err = self.closure_err.data_ptr()
         self.c = c
 
 
