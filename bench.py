@@ -43,18 +43,28 @@ def build_workload(name):
     return cfg, f, F, label
 
 
-def run_gpu(cfg, f, F, dtype, steps, warmup):
+def total_energy(ctx, st):
+    """(mass per species, kinetic+thermal energy, field energy) of a step state."""
+    import torch
+    me = torch.zeros(2, dtype=torch.float64, device="cuda")
+    fe = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mass, kin = [], 0.0
+    for s in range(len(st.f)):
+        ctx.mass_energy(s, st.f[s], st.mom_post[s], me)
+        mass.append(me[0].item())
+        kin += me[1].item()
+    ctx.field_energy(st.fields, fe)
+    return mass, kin, fe.item()
+
+
+def run_gpu(cfg, f, F, dtype, steps, warmup, mlp_params=None):
     import torch
     from paper_2109_06743_amd import vl
     ctx = vl.Context(cfg, dtype)
-    st = vl.StepState(ctx, f, vl.yee_pack(F))
+    st = vl.StepState(ctx, f, vl.yee_pack(F), mlp_params=mlp_params)
     torch.cuda.synchronize()
     ncells = sum(x.numel() for x in st.f)
-    me0 = torch.zeros(2, dtype=torch.float64, device="cuda")
-    e0 = 0.0
-    for s in range(len(st.f)):
-        ctx.mass_energy(s, st.f[s], st.mom_post[s], me0)
-        e0 += me0[1].item()
+    mass0, kin0, fld0 = total_energy(ctx, st)
     # Warm-up steps with every kernel category timed: the per-category
     # breakdown, and which f-pass kernel dominates.
     ctx.timing_enable(True)
@@ -83,15 +93,15 @@ def run_gpu(cfg, f, F, dtype, steps, warmup):
     ctx.sync()
     tim = ctx.timing_read()
     ctx.timing_enable(False)
-    e1 = 0.0
-    mass = []
-    for s in range(len(st.f)):
-        ctx.mass_energy(s, st.f[s], st.mom_post[s], me0)
-        e1 += me0[1].item()
-        mass.append(me0[0].item())
+    mass1, kin1, fld1 = total_energy(ctx, st)
     cnt = st.counters.cpu().numpy().tolist()
+    e0, e1 = kin0 + fld0, kin1 + fld1
     res = dict(ms=ms, wall=wall, ncells=ncells, timing=tim, breakdown=breakdown, warmup=warmup, dominant=dominant,
-               kinetic_energy=(e0, e1), mass=mass, counters=cnt, elem=4 if dtype == "f32" else 8)
+               energy_rel_drift=(e1 - e0) / e0, mass_rel_drift=max(abs(b - a) / a for a, b in zip(mass0, mass1)),
+               steps_run=warmup + steps, counters=cnt, elem=4 if dtype == "f32" else 8)
+    if mlp_params is not None:
+        res["closure_err"] = st.closure_err.cpu().numpy().tolist()
+        res["closure_fallback"] = st.closure_fallback.cpu().numpy().tolist()
     del st, ctx
     torch.cuda.empty_cache()
     return res
@@ -166,6 +176,78 @@ def calibrate_copy(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
+def train_closure(cfg, f, F, gen_steps=300, start=60, every=15, epochs=12, batch=16384, lr=2e-3, seed=0):
+    """Learned heat-flux closure on the benchmark geometry: the solver generates
+    its own training data (features and normalised kinetic heat flux of every
+    cell and species, every `every` steps after `start`), the last 20 % of the
+    snapshots are held out, and the network is trained with the library's
+    BF16-MFMA gradient and Adam calls.  Returns the parameters and figures."""
+    import torch
+    from paper_2109_06743_amd import vl, workloads as W
+    ctx = vl.Context(cfg, "f32")
+    st = vl.StepState(ctx, f, vl.yee_pack(F))
+    cells = cfg["nx"] * cfg["ny"]
+    snaps = [k for k in range(1, gen_steps + 1) if k >= start and k % every == 0]
+    nsamp = len(snaps) * 2 * cells
+    X = torch.zeros(nsamp, 64, dtype=torch.int16, device="cuda")
+    Y = torch.zeros(nsamp, 16, dtype=torch.float32, device="cuda")
+    sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
+    row = 0
+    t0 = time.perf_counter()
+    for k in range(1, gen_steps + 1):
+        ctx.step(st, cfg["dt"])
+        if k in snaps:
+            for s in range(2):
+                ctx.mlp_features(s, st.mom_pre[s], 20, X[row:row + cells], sc)
+                ctx.mlp_targets(s, st.mom_pre[s], Y[row:row + cells])
+                row += cells
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    n_train = int(0.8 * len(snaps)) * 2 * cells
+    P = torch.as_tensor(W.mlp_init(seed)).cuda()
+    m1, m2 = torch.zeros_like(P), torch.zeros_like(P)
+    work = torch.zeros(ctx.mlp_work_size(batch), dtype=torch.float32, device="cuda")
+    gl = torch.zeros(vl.MLP_NPARAM + 1, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    step = 0
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    losses = []
+    a.record()
+    for ep in range(epochs):
+        perm = torch.randperm(n_train, device="cuda", generator=gen)
+        for b0 in range(0, n_train - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            step += 1
+            ctx.mlp_train_step(P, m1, m2, step, lr, X[idx], Y[idx], work, gl)
+        losses.append(gl[-1].item())
+    b.record()
+    torch.cuda.synchronize()
+    train_ms = a.elapsed_time(b)
+    # held-out: relative L2 error of the normalised heat flux
+    nh = nsamp - n_train
+    yh = torch.zeros(nh, 16, dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(P, X[n_train:].contiguous(), yh)
+    torch.cuda.synchronize()
+    d = (yh[:, :10] - Y[n_train:, :10]).double()
+    held = (d.norm() / Y[n_train:, :10].double().norm()).item()
+    # inference throughput on the held-out set
+    a.record()
+    for _ in range(5):
+        ctx.mlp_forward(P, X[n_train:].contiguous(), yh)
+    b.record()
+    torch.cuda.synchronize()
+    inf_ms = a.elapsed_time(b) / 5
+    del X, Y, st, ctx
+    torch.cuda.empty_cache()
+    return P.cpu().numpy(), {
+        "samples": nsamp, "train_samples": n_train, "heldout_samples": nh, "data_steps": gen_steps,
+        "data_seconds": round(gen_s, 2), "epochs": epochs, "batch": batch, "adam_steps": step,
+        "train_ms": round(train_ms, 1), "train_samples_per_s": round(step * batch / (train_ms * 1e-3)),
+        "loss_per_epoch": [round(x, 6) for x in losses], "heldout_rel_l2_Q": round(held, 4),
+        "forward_samples_per_s": round(nh / (inf_ms * 1e-3))}
+
+
 def cpu_baseline(seconds_cap=30.0):
     """The FP64 numpy oracle's full step on a sample of the same workload: the
     GEM set-up with the same 16^3 velocity grids and species on a 16 x 8
@@ -207,6 +289,8 @@ def main():
     ap.add_argument("--workload", default="gem", choices=["gem", "tail"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
+    ap.add_argument("--closure-tol", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -231,7 +315,7 @@ def main():
     log(f"fp32: {r32['ms']:.3f} ms/step  warm-up breakdown {r32['breakdown']}  timed {r32['timing']}")
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", max(args.steps // 2, 3), 2)
+        r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", args.steps, args.warmup)
         log(f"fp64: {r64['ms']:.3f} ms/step")
     value = r32["ncells"] / (r32["ms"] * 1e-3)
     roof = roofline(r32, label)
@@ -248,8 +332,26 @@ def main():
     if r64 is not None:
         v64 = r64["ncells"] / (r64["ms"] * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": round(r64["ms"], 4), "speedup_fp32_over_fp64": round(value / v64, 3)}
-    e0, e1 = r32["kinetic_energy"]
-    out["kinetic_energy_rel_change"] = (e1 - e0) / e0
+    out["energy_rel_drift"] = {"f32": r32["energy_rel_drift"], "steps": r32["steps_run"]}
+    out["mass_rel_drift"] = {"f32": r32["mass_rel_drift"]}
+    if r64 is not None:
+        out["energy_rel_drift"]["f64"] = r64["energy_rel_drift"]
+        out["energy_rel_drift"]["f64_steps"] = r64["steps_run"]
+        out["mass_rel_drift"]["f64"] = r64["mass_rel_drift"]
+    if not args.no_mlp and cfg["kind"] == "2x3v":
+        log("learned closure: generating data and training ...")
+        params, tr = train_closure(cfg, f, F)
+        log(f"  {tr}")
+        cfg_m = dict(cfg, closure="mlp", closure_tol=args.closure_tol)
+        rm = run_gpu(cfg_m, f, F, "f32", args.steps, args.warmup, mlp_params=params)
+        vm = rm["ncells"] / (rm["ms"] * 1e-3)
+        log(f"mlp closure: {rm['ms']:.3f} ms/step, err {rm['closure_err']}, fallback {rm['closure_fallback']}")
+        out["mlp_closure"] = {
+            "workload": label + " + learned heat-flux closure (64-64-64-64-16 tanh MLP, BF16 MFMA)",
+            "value": vm, "unit": "cell-updates/s", "ms_per_step": round(rm["ms"], 4),
+            "closure_tol": args.closure_tol, "closure_err_last_step": rm["closure_err"],
+            "fallback_last_step": rm["closure_fallback"], "energy_rel_drift": rm["energy_rel_drift"],
+            "mass_rel_drift": rm["mass_rel_drift"], "training": tr}
     out["kernel_ms_per_step"] = {k: round(v[0] / r32["warmup"], 4) for k, v in r32["breakdown"].items() if v[1]}
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")

@@ -254,6 +254,12 @@ vl_status vl_mlp_train_step(vl_ctx* ctx, float* params, float* adam_m, float* ad
  * moment array, written to out[0..1] (device doubles). */
 vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mom, double* out,
                          vl_stream stream);
+/* Field energy (Sec. 3.2 energy budget) written to *out (device double).
+ * 2X3V: sum over the Yee points of B^2/2 + E^2/(2 c^2) times the cell area,
+ * points on the walls (rows 0 and ny of Ey, Bx, Bz) at half weight; fields is
+ * the Yee array.  1X1V: sum of E^2/2 dx over fields = E[nx].  Fixed-order
+ * sums (deterministic).  2X3V needs ny < 1024. */
+vl_status vl_field_energy(vl_ctx* ctx, const double* fields, double* out, vl_stream stream);
 
 /* Kernel timing (tracing aid).  mask selects categories: bit k (1u << VL_T_k)
  * brackets every launch group of category k issued by the entry points of

@@ -185,4 +185,57 @@ hipError_t launch_axpby(const double* x, const double* y, double a, double b, do
     return hipGetLastError();
 }
 
+// Field energy, deterministic: block partials over the rows jh = 0..ny (one
+// block column per row, fixed order), then one block adds them.
+// 2X3V: sum of B^2/2 + E^2/(2 c^2) over the Yee points, wall rows of the
+// [ny+1] arrays (Ey, Bx, Bz) at half weight; 1X1V: sum of E^2/2.
+__global__ void __launch_bounds__(256)
+field_energy_rows_kernel(YeeView F, double inv_c2, double* __restrict__ part) {
+    __shared__ double red[4];
+    const int jh = blockIdx.x;
+    const int nx = F.nx, ny = F.ny;
+    double acc[1] = {0.0};
+    const double w = (jh == 0 || jh == ny) ? 0.5 : 1.0;
+    const long long h = (long long)jh * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        double e = w * (F.Bx[h + i] * F.Bx[h + i] + F.Bz[h + i] * F.Bz[h + i] + inv_c2 * F.Ey[h + i] * F.Ey[h + i]);
+        if (jh < ny) e += F.By[h + i] * F.By[h + i] + inv_c2 * (F.Ex[h + i] * F.Ex[h + i] + F.Ez[h + i] * F.Ez[h + i]);
+        acc[0] += 0.5 * e;
+    }
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) part[jh] = acc[0];
+}
+
+__global__ void __launch_bounds__(256)
+line_energy_kernel(const double* __restrict__ E, int n, double* __restrict__ part) {
+    __shared__ double red[4];
+    double acc[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc[0] += 0.5 * E[i] * E[i];
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) part[0] = acc[0];
+}
+
+__global__ void __launch_bounds__(256)
+ordered_sum_kernel(const double* __restrict__ part, int np, double scale, double* __restrict__ out) {
+    __shared__ double red[4];
+    // thread t adds partials t, t+256, ... in order; then a fixed-order block sum
+    double acc[1] = {0.0};
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc[0] += part[i];
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) *out = acc[0] * scale;
+}
+
+hipError_t launch_field_energy(const double* fields, int dim_x, int nx, int ny, double c, double dX, double* part,
+                               double* out, hipStream_t st) {
+    if (dim_x == 2) {
+        const YeeView F = yee_view(const_cast<double*>(fields), nx, ny);
+        hipLaunchKernelGGL(field_energy_rows_kernel, dim3(ny + 1), dim3(256), 0, st, F, 1.0 / (c * c), part);
+        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(256), 0, st, part, ny + 1, dX, out);
+    } else {
+        hipLaunchKernelGGL(line_energy_kernel, dim3(1), dim3(256), 0, st, fields, nx, part);
+        hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(256), 0, st, part, 1, dX, out);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace vl

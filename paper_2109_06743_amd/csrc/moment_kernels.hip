@@ -762,12 +762,14 @@ energy_partial_kernel(const double* __restrict__ mom, long long cells, int kmom,
     if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
 }
 
-__global__ void finish_sum_kernel(const double* __restrict__ part, int np, double scale, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < np; ++i) s += part[i];
-        *out = s * scale;
-    }
+__global__ void __launch_bounds__(256)
+finish_sum_kernel(const double* __restrict__ part, int np, double scale, double* __restrict__ out) {
+    __shared__ double red[4];
+    // thread t adds partials t, t+256, ... in order; then a fixed-order block sum
+    double acc[1] = {0.0};
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc[0] += part[i];
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) *out = acc[0] * scale;
 }
 
 template <class T>
@@ -776,9 +778,9 @@ hipError_t launch_mass_energy(const T* f, const double* mom, long long cells, lo
     // out[0] = mass, out[1] = energy; part: 1024 doubles of scratch
     const int np = 1024;
     hipLaunchKernelGGL((partial_sum_kernel<T>), dim3(np), dim3(256), 0, st, f, cells * nv, part);
-    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(64), 0, st, part, np, dV * dX, out);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(256), 0, st, part, np, dV * dX, out);
     hipLaunchKernelGGL(energy_partial_kernel, dim3(np), dim3(256), 0, st, mom, cells, kmom, dimv, part);
-    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(64), 0, st, part, np, dX, out + 1);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(256), 0, st, part, np, dX, out + 1);
     return hipGetLastError();
 }
 

@@ -739,6 +739,19 @@ vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mo
     return VL_OK;
 }
 
+vl_status vl_field_energy(vl_ctx* ctx, const double* fields, double* out, vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    if (!fields || !out) return fail(ctx, VL_EINVAL, "null argument");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    const vl_config& c = ctx->cfg;
+    if (c.dim_x == 2 && (size_t)c.ny + 1 > (size_t)kPartials)
+        return fail(ctx, VL_ENOTSUP, "field energy partials hold at most %d rows", kPartials - 1);
+    VL_HIP(vl::launch_field_energy(fields, c.dim_x, c.nx, c.ny, c.c, dx_of(c) * dy_of(c), ctx->part, out,
+                                   (hipStream_t)stream));
+    return VL_OK;
+}
+
 vl_status vl_timing_enable(vl_ctx* ctx, uint32_t mask) {
     if (!ctx) return VL_EINVAL;
     ctx->timing = mask & ((1u << VL_T_COUNT) - 1u);

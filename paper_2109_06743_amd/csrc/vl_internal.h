@@ -61,6 +61,8 @@ hipError_t launch_poisson(const double* mom, int N, double L, double q, double* 
 hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
                                double dt, double c, double dx, double dy, hipStream_t st);
 hipError_t launch_cell_fields(const double* yee, int nx, int ny, double* E, double* B, hipStream_t st);
+hipError_t launch_field_energy(const double* fields, int dim_x, int nx, int ny, double c, double dX, double* part,
+                               double* out, hipStream_t st);
 hipError_t launch_axpby(const double* x, const double* y, double a, double b, double* out, long long n,
                         hipStream_t st);
 

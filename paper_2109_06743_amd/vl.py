@@ -20,7 +20,8 @@ EXPORTS = ["vl_create", "vl_destroy", "vl_pfc_advect_x", "vl_pfc_advect_v", "vl_
            "vl_poisson", "vl_yee_size", "vl_maxwell_half_step", "vl_cell_fields", "vl_fluid_work_size",
            "vl_fluid_step", "vl_step_work_size", "vl_step", "vl_mass_energy", "vl_sync", "vl_status_str",
            "vl_last_error", "vl_version", "vl_timing_enable", "vl_timing_read", "vl_mlp_features",
-           "vl_mlp_targets", "vl_mlp_forward", "vl_mlp_work_size", "vl_mlp_gradient", "vl_mlp_train_step"]
+           "vl_mlp_targets", "vl_mlp_forward", "vl_mlp_work_size", "vl_mlp_gradient", "vl_mlp_train_step",
+           "vl_field_energy"]
 VL_CLOSURE_KINETIC, VL_CLOSURE_MLP = 0, 1
 MLP_IN, MLP_OUT, MLP_OUT_PAD, MLP_NPARAM = 64, 10, 16, 13520
 TIMING_CATEGORIES = ["max", "pfc_x", "pfc_y", "pfc_v", "moments", "fluid", "fit", "fields", "copy"]
@@ -89,6 +90,7 @@ def load():
         "vl_step_work_size": ([vp], sz),
         "vl_step": ([vp, ctypes.POINTER(State), d, vp], i32),
         "vl_mass_energy": ([vp, i32, vp, vp, vp, vp], i32),
+        "vl_field_energy": ([vp, vp, vp, vp], i32),
         "vl_sync": ([vp, vp], i32),
         "vl_timing_enable": ([vp, ctypes.c_uint32], i32),
         "vl_timing_read": ([vp, vp, vp], i32),
@@ -224,6 +226,9 @@ class Context:
 
     def mass_energy(self, s, f, mom, out, stream=None):
         self._check(self.lib.vl_mass_energy(self.h, s, _ptr(f), _ptr(mom), _ptr(out), _stream(stream)))
+
+    def field_energy(self, fields, out, stream=None):
+        self._check(self.lib.vl_field_energy(self.h, _ptr(fields), _ptr(out), _stream(stream)))
 
     def sync(self, stream=None):
         self._check(self.lib.vl_sync(self.h, _stream(stream)))

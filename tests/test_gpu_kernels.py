@@ -365,3 +365,31 @@ def test_fluid_step_1v():
                    dev(Eth, "f64"), None, 0.1, work)
     ctx.sync()
     np.testing.assert_allclose(host(Ud, ref.shape), ref, rtol=1e-12, atol=1e-14)
+
+
+def test_field_energy_matches_oracle():
+    import torch
+    from paper_2109_06743_amd import vl
+    from oracle import fields as OF
+    nx, ny = 20, 9
+    cfg, _, _ = W.gem(nx=nx, ny=ny, nv=8, dtype=np.float64)
+    rng = np.random.default_rng(31)
+    F = OF.Yee(nx, ny)
+    for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        setattr(F, k, rng.normal(size=getattr(F, k).shape))
+    ctx = _ctx(cfg, "f64")
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.field_energy(dev(vl.yee_pack(F), "f64"), out)
+    ctx.sync()
+    dx = (cfg["x_hi"] - cfg["x_lo"]) / nx
+    dy = (cfg["y_hi"] - cfg["y_lo"]) / ny
+    ref = OF.field_energy(F, cfg["c"], dx, dy)
+    assert abs(out.item() - ref) <= 1e-13 * abs(ref)
+    # 1X1V: E^2/2 dx
+    cfg1, _ = W.landau(nx=37, nv=16)
+    ctx1 = _ctx(cfg1, "f64")
+    E = rng.normal(size=37)
+    ctx1.field_energy(dev(E, "f64"), out)
+    ctx1.sync()
+    ref1 = 0.5 * (E * E).sum() * (cfg1["x_hi"] - cfg1["x_lo"]) / 37
+    assert abs(out.item() - ref1) <= 1e-13 * ref1
