@@ -91,8 +91,9 @@ typedef struct {
 typedef struct vl_ctx vl_ctx;
 
 /* Create a context for one problem geometry.  Host-only: validates and copies
- * *cfg; device scratch (a few hundred bytes) is allocated on first use on the
- * device current at that time.  Errors: VL_EINVAL (bad geometry, velocity
+ * *cfg; device scratch (a few kilobytes, plus 160 bytes per spatial cell for
+ * the 3V moment fitting on its first call) is allocated on first use on the
+ * device current at that time and freed by vl_destroy.  Errors: VL_EINVAL (bad geometry, velocity
  * grid not symmetric in v_y for 2X3V), VL_ENOTSUP (unsupported combination). */
 vl_status vl_create(const vl_config* cfg, vl_ctx** out);
 vl_status vl_destroy(vl_ctx* ctx);

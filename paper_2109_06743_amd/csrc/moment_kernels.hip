@@ -367,15 +367,10 @@ moments3_cube_kernel(const T* __restrict__ f, double* __restrict__ mom, long lon
 #pragma unroll
         for (int q = 0; q < 20; ++q) acc[q] += a[q];
     }
-#pragma unroll
-    for (int q = 0; q < 20; ++q) acc[q] = wave_sum(acc[q]);
+    int idx = 0, cnt = 20;
+    const double v = ReduceScatter<20, 32>::run(acc, lane, idx, cnt);
     const double dV = G.dv[0] * G.dv[1] * G.dv[2];
-    if (lane < 20) {
-        double v = 0;
-#pragma unroll
-        for (int q = 0; q < 20; ++q) v = (lane == q) ? acc[q] * (q < 4 ? dV : G.m * dV) : v;
-        mom[cell * 20 + lane] = v;
-    }
+    if ((lane & 1) == 0 && cnt > 0) mom[cell * 20 + idx] = v * (idx < 4 ? dV : G.m * dV);
 }
 
 // Moment fitting of one cubic cell per block (see fit3_kernel for the steps).
@@ -395,12 +390,12 @@ template <> struct ExpK<double> {
 template <class T>
 struct QuadX {       // (m/2) w^T T^-1 w = axx wx^2 + bt wx + ct for fixed (wy, wz), times ExpK::scale
     T axx, bt, ct, ux;
-    __device__ __forceinline__ void set(const double (&inv)[6], const double (&u)[3], double m, double vy,
-                                        double vz) {
-        const double h = 0.5 * m * ExpK<T>::scale, wy = vy - u[1], wz = vz - u[2];
-        axx = (T)(h * inv[0]);
-        bt = (T)(2.0 * h * (inv[1] * wy + inv[2] * wz));
-        ct = (T)(h * (inv[3] * wy * wy + 2.0 * inv[4] * wy * wz + inv[5] * wz * wz));
+    // a: (m/2) ExpK::scale T^-1 as (xx, xy, xz, yy, yz, zz); u: mean velocity
+    __device__ __forceinline__ void set(const double* a, const double* u, double vy, double vz) {
+        const double wy = vy - u[1], wz = vz - u[2];
+        axx = (T)a[0];
+        bt = (T)(2.0 * (a[1] * wy + a[2] * wz));
+        ct = (T)(a[3] * wy * wy + 2.0 * a[4] * wy * wz + a[5] * wz * wz);
         ux = (T)u[0];
     }
     __device__ __forceinline__ T g(T vx) const {
@@ -409,17 +404,81 @@ struct QuadX {       // (m/2) w^T T^-1 w = axx wx^2 + bt wx + ct for fixed (wy, 
     }
 };
 
-// One block per cell; thread t owns the v_x pencils at transverse positions
-// t + nthr * j (j < NT), nthr = blockDim.x.  FP32 storage uses two pencils per
-// thread (128 threads for 16^3), FP64 one (256 threads): enough values per
-// thread to amortise the reductions, few enough to stay in registers.
-template <class T, int N, int NT>
+// Per-cell set-up of the fitting (one thread per cell), so that the f pass
+// carries no FP64 divisions, square roots or branches on the moments: the
+// exponent coefficients of the two Maxwellians, the density n_V, the skip
+// decision; the fluid state is rescaled by n_V/n_F in place.
+struct FitCell {
+    double aV[6], uV[3], aF[6], uF[3];
+    double nV, ok;
+};
+static_assert(sizeof(FitCell) == kFitCellDoubles * sizeof(double), "FitCell layout");
+
 __global__ void __launch_bounds__(256)
-fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* __restrict__ U,
-                 double* __restrict__ mom_post, unsigned long long* __restrict__ counters, VGrid G, XTable X,
+fit3_params_kernel(const double* __restrict__ mom_pre, double* __restrict__ U, long long cells, double m,
+                   double kscale, FitCell* __restrict__ out, unsigned long long* __restrict__ counters) {
+    __shared__ int nskip;
+    if (threadIdx.x == 0) nskip = 0;
+    __syncthreads();
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < cells) {
+        double mp[10], Uc[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) { mp[k] = mom_pre[c * 20 + k]; Uc[k] = U[c * 10 + k]; }
+        const double nV = mp[0], nF = Uc[0];
+        double uV[3] = {0, 0, 0}, TV[6], uF[3] = {0, 0, 0}, TF[6], iV[6] = {0, 0, 0, 0, 0, 0}, iF[6] = {0, 0, 0, 0, 0, 0};
+        bool ok = nV > 1e-12 && nF > 1e-12;
+        if (ok) {
+            u_and_T(mp + 1, nV, m, uV, TV);
+            u_and_T(Uc + 1, nF, m, uF, TF);
+            ok = spd_inverse(TV, iV) && spd_inverse(TF, iF);
+        }
+        FitCell r;
+        const double h = 0.5 * m * kscale;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { r.aV[k] = h * iV[k]; r.aF[k] = h * iF[k]; }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { r.uV[k] = uV[k]; r.uF[k] = uF[k]; }
+        r.nV = nV;
+        r.ok = ok ? 1.0 : 0.0;
+        out[c] = r;
+        if (ok) {
+            const double sc = nV / nF;
+#pragma unroll
+            for (int k = 0; k < 10; ++k) U[c * 10 + k] = Uc[k] * sc;
+        } else {
+            atomicAdd(&nskip, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && counters && nskip) atomicAdd(&counters[1], (unsigned long long)nskip);
+}
+
+// One block of NW waves per cell; thread t owns the v_x pencils at transverse
+// positions t + 64 NW j (j < NT).  Two passes over f held in registers: the
+// normalisation sums of the two Maxwellians (FP32 exponentials, FP64 sums),
+// then the exchange, clip, FP64 post-fit moments and the FP64 rescale.  The
+// block sums use the reduce-scatter (block_sum_rs).
+#ifndef FIT16_NW
+#define FIT16_NW 2
+#define FIT16_NT 2
+#endif
+#ifndef FIT12_NW
+#define FIT12_NW 1
+#define FIT12_NT 3
+#endif
+template <class T, int N, int NW, int NT>
+__global__ void __launch_bounds__(64 * NW)
+#if defined(FIT_WPE)
+__attribute__((amdgpu_waves_per_eu(FIT_WPE)))
+#endif
+fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
+                 unsigned long long* __restrict__ counters, VGrid G, XTable X,
                  typename Bits<T>::U* __restrict__ max_out) {
-    __shared__ double red[21 * 4];
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    constexpr int NTH = 64 * NW;
+    __shared__ double red[NW * 21];
+    __shared__ double fin_s[21];
+    const int tid = threadIdx.x;
     const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
     const double dV = G.dv[0] * G.dv[1] * G.dv[2];
     const T* src = fin + cell * (N * N * N);
@@ -427,50 +486,44 @@ fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, doub
     T fv[NT][N];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-        const int t = tid + nthr * j;
+        const int t = tid + NTH * j;
 #pragma unroll
         for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? src[t + k * N * N] : T(0);
     }
-    double mp[10], Uc[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) { mp[k] = mom_pre[cell * 20 + k]; Uc[k] = U[cell * 10 + k]; }
-    const double nV = mp[0], nF = Uc[0];
-    double uV[3], TV[6], uF[3], TF[6], iV[6], iF[6];
-    bool ok = nV > 1e-12 && nF > 1e-12;
-    if (ok) {
-        u_and_T(mp + 1, nV, G.m, uV, TV);
-        u_and_T(Uc + 1, nF, G.m, uF, TF);
-        ok = spd_inverse(TV, iV) && spd_inverse(TF, iF);
-    }
+    const FitCell& C = P[cell];
+    const bool ok = C.ok != 0.0;
+    const double nV = C.nV;
     int nclip = 0;
     if (ok) {
         QuadX<T> qv[NT], qf[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const int t = tid + nthr * j;
-            qv[j].set(iV, uV, G.m, vc(G, 1, t / N), vc(G, 2, t % N));
-            qf[j].set(iF, uF, G.m, vc(G, 1, t / N), vc(G, 2, t % N));
+            const int t = tid + NTH * j;
+            const double vy = vc(G, 1, t / N), vz = vc(G, 2, t % N);
+            qv[j].set(C.aV, C.uV, vy, vz);
+            qf[j].set(C.aF, C.uF, vy, vz);
         }
-        // normalisation sums of the two Maxwellians (FP64)
-        double s[2] = {0.0, 0.0};
+        // four interleaved partial sums per Maxwellian keep the FP64 adds
+        // from forming one serial chain
+        double sp[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            if (tid + nthr * j < N * N) {
+            if (tid + NTH * j < N * N) {
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
                     const T vx = (T)X.v[k];
-                    s[0] += (double)qv[j].g(vx);
-                    s[1] += (double)qf[j].g(vx);
+                    sp[k & 3][0] += (double)qv[j].g(vx);
+                    sp[k & 3][1] += (double)qf[j].g(vx);
                 }
             }
         }
-        block_sum<2>(s, red);
-        const T A = (T)(nV / (s[0] * dV));
-        const T Bc = (T)(nV / (s[1] * dV));
-        // exchange the Maxwellians and clip (exponentials recomputed)
+        double s[2] = {(sp[0][0] + sp[1][0]) + (sp[2][0] + sp[3][0]), (sp[0][1] + sp[1][1]) + (sp[2][1] + sp[3][1])};
+        block_sum_rs<2>(s, red, fin_s);
+        const T A = (T)(nV / (fin_s[0] * dV));
+        const T Bc = (T)(nV / (fin_s[1] * dV));
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const bool act = tid + nthr * j < N * N;
+            const bool act = tid + NTH * j < N * N;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const T vx = (T)X.v[k];
@@ -487,28 +540,31 @@ fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, doub
     acc[20] = (double)nclip;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-        const int t = tid + nthr * j;
-        double S[4] = {0.0, 0.0, 0.0, 0.0};
+        const int t = tid + NTH * j;
+        // pencil sums over even and odd v_x separately (two independent chains)
+        double Se[4] = {0.0, 0.0, 0.0, 0.0}, So[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const double g = (double)fv[j][k];
+            double* S = (k & 1) ? So : Se;
             S[0] += g;
             S[1] = fma(g, X.v[k], S[1]);
             S[2] = fma(g, X.v2[k], S[2]);
             S[3] = fma(g, X.v3[k], S[3]);
         }
+        const double S[4] = {Se[0] + So[0], Se[1] + So[1], Se[2] + So[2], Se[3] + So[3]};
         double a[20];
         pencil_moments(S, vc(G, 1, t / N), vc(G, 2, t % N), a);
 #pragma unroll
         for (int q = 0; q < 20; ++q) acc[q] += a[q];
     }
-    block_sum<21>(acc, red);
-    const double scale = ok ? nV / (acc[0] * dV) : 1.0;
+    block_sum_rs<21>(acc, red, fin_s);
+    const double scale = ok ? nV / (fin_s[0] * dV) : 1.0;
     const T sc = (T)scale;
     T mx = T(0);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
-        const int t = tid + nthr * j;
+        const int t = tid + NTH * j;
         if (t < N * N) {
 #pragma unroll
             for (int k = 0; k < N; ++k) {
@@ -518,23 +574,8 @@ fit3_cube_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, doub
             }
         }
     }
-    if (mom_post && tid < 20) {
-        double v = 0;
-#pragma unroll
-        for (int q = 0; q < 20; ++q) v = (tid == q) ? acc[q] * (q < 4 ? dV : G.m * dV) * scale : v;
-        mom_post[cell * 20 + tid] = v;
-    }
-    if (ok && tid < 10) {
-        const double r = nV / nF;
-        double v = 0;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) v = (tid == k) ? Uc[k] : v;
-        U[cell * 10 + tid] = v * r;
-    }
-    if (counters && tid == 0) {
-        if (acc[20] > 0) atomicAdd(&counters[0], (unsigned long long)acc[20]);
-        if (!ok) atomicAdd(&counters[1], 1ull);
-    }
+    if (mom_post && tid < 20) mom_post[cell * 20 + tid] = fin_s[tid] * (tid < 4 ? dV : G.m * dV) * scale;
+    if (counters && tid == 0 && fin_s[20] > 0) atomicAdd(&counters[0], (unsigned long long)fin_s[20]);
     if (max_out) block_max_to(mx, max_out);
 }
 
@@ -671,7 +712,7 @@ hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, dou
 
 template <class T>
 hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
-                       long long cells, const VGridArgs& a, void* max_out, hipStream_t st) {
+                       long long cells, const VGridArgs& a, void* max_out, double* scratch, hipStream_t st) {
     VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m, 1.0f / (float)a.nv[2]};
     const int nv = a.nv[0] * a.nv[1] * a.nv[2];
     const size_t shm = sizeof(T) * (size_t)a.nv[0] * a.nv[1] * (a.nv[2] | 1);
@@ -683,17 +724,19 @@ hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, 
     if (N) {
         const XTable X = xtable(a);
         const dim3 grid((unsigned)cells);
-        constexpr int NT = sizeof(T) == 4 ? 2 : 1;
-        auto thr = [](int n) { return 64 * ((n * n + 64 * NT - 1) / (64 * NT)); };
-        if (N == 16)
-            hipLaunchKernelGGL((fit3_cube_kernel<T, 16, NT>), grid, dim3(thr(16)), 0, st, fin, fout, mom_pre, U, mom_post,
-                               cnt, G, X, mo);
-        if (N == 12)
-            hipLaunchKernelGGL((fit3_cube_kernel<T, 12, NT>), grid, dim3(thr(12)), 0, st, fin, fout, mom_pre, U, mom_post,
-                               cnt, G, X, mo);
-        if (N == 8)
-            hipLaunchKernelGGL((fit3_cube_kernel<T, 8, NT>), grid, dim3(thr(8)), 0, st, fin, fout, mom_pre, U, mom_post,
-                               cnt, G, X, mo);
+        FitCell* P = reinterpret_cast<FitCell*>(scratch);
+        hipLaunchKernelGGL(fit3_params_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, mom_pre, U,
+                           cells, a.m, ExpK<T>::scale, P, cnt);
+        // waves per cell and pencils per thread: every lane busy for 16^3, 3/4 for 12^3
+        if constexpr (sizeof(T) == 4) {
+            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, FIT16_NW, FIT16_NT>), grid, dim3(64 * FIT16_NW), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, FIT12_NW, FIT12_NT>), grid, dim3(64 * FIT12_NW), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+            if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+        } else {
+            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, 4, 1>), grid, dim3(256), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, 3, 1>), grid, dim3(192), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+            if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+        }
         return hipGetLastError();
     }
     if (ept <= 4)
@@ -727,7 +770,7 @@ hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, 
     template hipError_t launch_moments1<T>(const T*, double*, long long, int, double, double, double,            \
                                            hipStream_t);                                                        \
     template hipError_t launch_fit3<T>(const T*, T*, const double*, double*, double*, void*, long long,         \
-                                       const VGridArgs&, void*, hipStream_t);                                   \
+                                       const VGridArgs&, void*, double*, hipStream_t);                          \
     template hipError_t launch_fit1<T>(const T*, T*, const double*, double*, double*, void*, long long, int,    \
                                        double, double, double, void*, hipStream_t);
 VL_INST(float)

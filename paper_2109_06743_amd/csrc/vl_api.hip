@@ -32,6 +32,8 @@ struct vl_ctx {
     double* part = nullptr;
     long long cells = 0;
     long long nv[VL_MAX_SPECIES] = {0, 0};
+    // per-cell fitting parameters (3V), allocated on the first fit
+    double* fit_scratch = nullptr;
     char err[512] = {0};
 };
 
@@ -231,9 +233,15 @@ vl_status fit_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double* mom
     if (c.dim_v == 1)
         VL_HIP((vl::launch_fit1<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, sp.nv[0], sp.v_lo[0],
                                    dv_of(sp, 0), sp.m, max_out, st)));
-    else
+    else {
+        if (!ctx->fit_scratch) {
+            void* p = nullptr;
+            VL_HIP(hipMalloc(&p, sizeof(double) * vl::kFitCellDoubles * (size_t)ctx->cells));
+            ctx->fit_scratch = (double*)p;
+        }
         VL_HIP((vl::launch_fit3<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, grid_args(sp), max_out,
-                                   st)));
+                                   ctx->fit_scratch, st)));
+    }
     return VL_OK;
 }
 
@@ -512,6 +520,7 @@ vl_status vl_destroy(vl_ctx* ctx) {
     }
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->slots) (void)hipFree(ctx->slots);
+    if (ctx->fit_scratch) (void)hipFree(ctx->fit_scratch);
     delete ctx;
     return VL_OK;
 }

@@ -44,6 +44,73 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Reduce-scatter of K doubles over the 64 lanes of a wave by recursive
+// halving: at distance D every lane keeps one half of its array (the upper
+// half where bit D of the lane index is set), sends the other half to lane^D
+// and adds what it receives.  Moving ceil(K/2) + ceil(K/4) + ... values
+// instead of K per step, it needs about 24 exchanges for K = 21 where a
+// butterfly on every value needs 126.  Returns this lane's total; idx is the
+// value index it belongs to, valid only where cnt > 0 (odd halves are padded,
+// and a padding slot's running index can equal a real index of another lane
+// group); lanes l and l^1 hold the same value.  Every lane must call it with
+// idx = 0 and cnt = K; the summation order is fixed.
+template <int K, int D>
+struct ReduceScatter {
+    static __device__ __forceinline__ double run(const double* a, int lane, int& idx, int& cnt) {
+        constexpr int H = (K + 1) / 2;
+        const bool up = (lane & D) != 0;
+        double b[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double lo = a[i];
+            const double hi = (H + i < K) ? a[H + i] : 0.0;
+            const double send = up ? lo : hi;
+            b[i] = (up ? hi : lo) + __shfl_xor(send, D, kWave);
+        }
+        if (up) {
+            idx += H;
+            cnt -= H;
+        } else {
+            cnt = cnt < H ? cnt : H;
+        }
+        return ReduceScatter<H, D / 2>::run(b, lane, idx, cnt);
+    }
+};
+template <int D>
+struct ReduceScatter<1, D> {
+    static __device__ __forceinline__ double run(const double* a, int lane, int& idx, int& cnt) {
+        const double v = a[0] + __shfl_xor(a[0], D, kWave);
+        return ReduceScatter<1, D / 2>::run(&v, lane, idx, cnt);
+    }
+};
+template <>
+struct ReduceScatter<1, 0> {
+    static __device__ __forceinline__ double run(const double* a, int, int&, int&) { return a[0]; }
+};
+
+// Block sum of K doubles per thread (waves of 64): totals in fin[0..K-1]
+// (shared memory) for every thread after return.  red: NW*K doubles of shared
+// scratch, NW = waves in the block.  Fixed summation order.
+template <int K>
+__device__ __forceinline__ void block_sum_rs(const double (&a)[K], double* red, double* fin) {
+    // up to 32 values the last exchange (distance 1) is a full add, so lanes l
+    // and l^1 agree and the even lanes carry every index (some more than once,
+    // with identical values)
+    static_assert(K >= 1 && K <= 32, "reduce-scatter of at most 32 values");
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    int idx = 0, cnt = K;
+    const double v = ReduceScatter<K, kWave / 2>::run(a, lane, idx, cnt);
+    if ((lane & 1) == 0 && cnt > 0) red[w * K + idx] = v;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int k = 0; k < nw; ++k) s += red[k * K + threadIdx.x];
+        fin[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 // Maximum over the block, folded into *slot with one atomic per block.
 // Every thread of the block must call it (it synchronises).
 template <class T>

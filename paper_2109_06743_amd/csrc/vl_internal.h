@@ -50,9 +50,12 @@ hipError_t launch_moments3(const T* f, double* mom, long long cells, const VGrid
 template <class T>
 hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, double vlo, double dv, double m,
                            hipStream_t st);
+// Per-cell fitting parameters (cubic velocity blocks): kFitCellDoubles doubles
+// per spatial cell of device scratch.
+constexpr int kFitCellDoubles = 20;
 template <class T>
 hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
-                       long long cells, const VGridArgs& a, void* max_out, hipStream_t st);
+                       long long cells, const VGridArgs& a, void* max_out, double* scratch, hipStream_t st);
 template <class T>
 hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
                        long long cells, int nv, double vlo, double dv, double m, void* max_out, hipStream_t st);
