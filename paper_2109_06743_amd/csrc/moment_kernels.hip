@@ -296,7 +296,7 @@ fit3_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* _
             if (!ok) atomicAdd(&counters[1], 1ull);
         }
     }
-    if (max_out) block_max_to(mx, max_out);
+    if (max_out) block_max_part(mx, max_out);
 }
 
 // ------------------------------------------------------- cubic blocks -------
@@ -459,6 +459,9 @@ fit3_params_kernel(const double* __restrict__ mom_pre, double* __restrict__ U, l
 // normalisation sums of the two Maxwellians (FP32 exponentials, FP64 sums),
 // then the exchange, clip, FP64 post-fit moments and the FP64 rescale.  The
 // block sums use the reduce-scatter (block_sum_rs).
+#ifndef FIT_KEEP_G
+#define FIT_KEEP_G 0
+#endif
 #ifndef FIT16_NW
 #define FIT16_NW 2
 #define FIT16_NT 2
@@ -473,8 +476,7 @@ __global__ void __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(FIT_WPE)))
 #endif
 fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
-                 unsigned long long* __restrict__ counters, VGrid G, XTable X,
-                 typename Bits<T>::U* __restrict__ max_out) {
+                 unsigned* __restrict__ clip_part, VGrid G, XTable X, typename Bits<T>::U* __restrict__ max_out) {
     constexpr int NTH = 64 * NW;
     __shared__ double red[NW * 21];
     __shared__ double fin_s[21];
@@ -506,14 +508,22 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
         // four interleaved partial sums per Maxwellian keep the FP64 adds
         // from forming one serial chain
         double sp[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#if FIT_KEEP_G
+        T gv[NT][N], gf[NT][N];
+#endif
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             if (tid + NTH * j < N * N) {
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
                     const T vx = (T)X.v[k];
-                    sp[k & 3][0] += (double)qv[j].g(vx);
-                    sp[k & 3][1] += (double)qf[j].g(vx);
+                    const T a = qv[j].g(vx), b = qf[j].g(vx);
+#if FIT_KEEP_G
+                    gv[j][k] = a;
+                    gf[j][k] = b;
+#endif
+                    sp[k & 3][0] += (double)a;
+                    sp[k & 3][1] += (double)b;
                 }
             }
         }
@@ -526,8 +536,12 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
             const bool act = tid + NTH * j < N * N;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
+#if FIT_KEEP_G
+                const T x = fv[j][k] - A * gv[j][k] + Bc * gf[j][k];
+#else
                 const T vx = (T)X.v[k];
                 const T x = fv[j][k] - A * qv[j].g(vx) + Bc * qf[j].g(vx);
+#endif
                 nclip += (act && x < T(0)) ? 1 : 0;
                 fv[j][k] = act ? fmax(x, T(0)) : T(0);
             }
@@ -575,8 +589,8 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
         }
     }
     if (mom_post && tid < 20) mom_post[cell * 20 + tid] = fin_s[tid] * (tid < 4 ? dV : G.m * dV) * scale;
-    if (counters && tid == 0 && fin_s[20] > 0) atomicAdd(&counters[0], (unsigned long long)fin_s[20]);
-    if (max_out) block_max_to(mx, max_out);
+    if (clip_part && tid == 0) clip_part[blockIdx.x] = (unsigned)fin_s[20];
+    if (max_out) block_max_part(mx, max_out);
 }
 
 template <class T>
@@ -659,7 +673,7 @@ fit1_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* _
             if (!ok) atomicAdd(&counters[1], 1ull);
         }
     }
-    if (max_out) block_max_to(mx, max_out);
+    if (max_out) block_max_part(mx, max_out);
 }
 
 // ------------------------------------------------------------ launchers ----
@@ -710,16 +724,34 @@ hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, dou
     return hipGetLastError();
 }
 
+// counters[0] += sum of the per-block clip counts (one block, fixed order).
+__global__ void __launch_bounds__(1024)
+count_finalize_kernel(const unsigned* __restrict__ part, long long n, unsigned long long* __restrict__ counters) {
+    __shared__ unsigned long long red[16];
+    unsigned long long acc = 0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) acc += red[w];
+        counters[0] += acc;
+    }
+}
+
 template <class T>
 hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
-                       long long cells, const VGridArgs& a, void* max_out, double* scratch, hipStream_t st) {
+                       long long cells, const VGridArgs& a, void* max_out, void* part, unsigned* clip_part,
+                       double* scratch, hipStream_t st) {
     VGrid G{a.nv[0], a.nv[1], a.nv[2], {a.lo[0], a.lo[1], a.lo[2]}, {a.dv[0], a.dv[1], a.dv[2]}, a.m, 1.0f / (float)a.nv[2]};
     const int nv = a.nv[0] * a.nv[1] * a.nv[2];
     const size_t shm = sizeof(T) * (size_t)a.nv[0] * a.nv[1] * (a.nv[2] | 1);
     const int threads = 256;
     const int ept = (nv + threads - 1) / threads;
     auto* cnt = (unsigned long long*)counters;
-    auto* mo = (typename Bits<T>::U*)max_out;
+    auto* mo = (typename Bits<T>::U*)(max_out ? part : nullptr);
+    unsigned* cp = cnt ? clip_part : nullptr;
     const int N = cube_edge(a);
     if (N) {
         const XTable X = xtable(a);
@@ -729,15 +761,19 @@ hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, 
                            cells, a.m, ExpK<T>::scale, P, cnt);
         // waves per cell and pencils per thread: every lane busy for 16^3, 3/4 for 12^3
         if constexpr (sizeof(T) == 4) {
-            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, FIT16_NW, FIT16_NT>), grid, dim3(64 * FIT16_NW), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
-            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, FIT12_NW, FIT12_NT>), grid, dim3(64 * FIT12_NW), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
-            if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, FIT16_NW, FIT16_NT>), grid, dim3(64 * FIT16_NW), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, FIT12_NW, FIT12_NT>), grid, dim3(64 * FIT12_NW), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
         } else {
-            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, 4, 1>), grid, dim3(256), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
-            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, 3, 1>), grid, dim3(192), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
-            if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cnt, G, X, mo);
+            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, 4, 1>), grid, dim3(256), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, 3, 1>), grid, dim3(192), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
         }
-        return hipGetLastError();
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && cnt)
+            hipLaunchKernelGGL(count_finalize_kernel, dim3(1), dim3(1024), 0, st, clip_part, cells, cnt);
+        if (e == hipSuccess && max_out) e = launch_max_finalize<T>(part, cells, max_out, st);
+        return e == hipSuccess ? hipGetLastError() : e;
     }
     if (ept <= 4)
         hipLaunchKernelGGL((fit3_kernel<T, 4>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, mom_pre, U,
@@ -753,16 +789,21 @@ hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, 
                            mom_post, cnt, G, mo);
     else
         return hipErrorInvalidValue;
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !max_out) return e;
+    return launch_max_finalize<T>(part, cells, max_out, st);
 }
 
 template <class T>
 hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
-                       long long cells, int nv, double vlo, double dv, double m, void* max_out, hipStream_t st) {
+                       long long cells, int nv, double vlo, double dv, double m, void* max_out, void* part,
+                       hipStream_t st) {
     hipLaunchKernelGGL((fit1_kernel<T>), dim3((unsigned)cells), dim3(threads_for(nv)), sizeof(T) * (size_t)nv, st,
                        fin, fout, mom_pre, U, mom_post, (unsigned long long*)counters, nv, vlo, dv, m,
-                       (typename Bits<T>::U*)max_out);
-    return hipGetLastError();
+                       (typename Bits<T>::U*)(max_out ? part : nullptr));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !max_out) return e;
+    return launch_max_finalize<T>(part, cells, max_out, st);
 }
 
 #define VL_INST(T)                                                                                              \
@@ -770,9 +811,9 @@ hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, 
     template hipError_t launch_moments1<T>(const T*, double*, long long, int, double, double, double,            \
                                            hipStream_t);                                                        \
     template hipError_t launch_fit3<T>(const T*, T*, const double*, double*, double*, void*, long long,         \
-                                       const VGridArgs&, void*, double*, hipStream_t);                          \
+                                       const VGridArgs&, void*, void*, unsigned*, double*, hipStream_t);        \
     template hipError_t launch_fit1<T>(const T*, T*, const double*, double*, double*, void*, long long, int,    \
-                                       double, double, double, void*, hipStream_t);
+                                       double, double, double, void*, void*, hipStream_t);
 VL_INST(float)
 VL_INST(double)
 #undef VL_INST

@@ -103,7 +103,7 @@ pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int Nv, fl
             }
         }
     }
-    if (max_out) block_max_to(mx, max_out);
+    if (max_out) block_max_part(mx, max_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -224,7 +224,7 @@ pfc_y_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, in
         y_window<T, CY>(up, dn, oup, odn, c0, rows, K, ny, rs, sh, F2, mx);
         y_window<T, CY>(up, dn, oup, odn, L2 - c0 - rows, rows, K, ny, rs, sh, F2, mx);
     }
-    if (max_out) block_max_to(mx, max_out);
+    if (max_out) block_max_part(mx, max_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,7 +280,7 @@ pfc_v1_kernel(const T* fin, T* fout, int nv, const double* __restrict__ E, doubl
         dst[pos ? p : nv - 1 - p] = o;
         mx = fmax(mx, o);
     }
-    if (max_out) block_max_to(mx, max_out);
+    if (max_out) block_max_part(mx, max_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,7 +397,7 @@ pfc_v3_kernel(const T* fin, T* fout, const double* __restrict__ E, const double*
         dst[e] = o;
         mx = fmax(mx, o);
     }
-    if (max_out) block_max_to(mx, max_out);
+    if (max_out) block_max_part(mx, max_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,7 +565,7 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
         dst[threadIdx.x + j * NTH] = v[j];
         mx = fmax(mx, v[j]);
     }
-    if (max_out) block_max_to(mx, max_out);
+    if (max_out) block_max_part(mx, max_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,7 +576,7 @@ array_max_kernel(const T* __restrict__ f, long long n, typename Bits<T>::U* __re
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
         mx = fmax(mx, f[i]);
-    block_max_to(mx, out);
+    block_max_part(mx, out);
 }
 
 __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
@@ -584,40 +584,86 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long
     if (i < n) p[i] = v;
 }
 
+// Maximum of the per-block partial maxima part[0..n) into *slot (bits of
+// non-negative values order like the values).  One block, fixed order.
+template <class T>
+__global__ void __launch_bounds__(1024)
+max_finalize_kernel(const typename Bits<T>::U* __restrict__ part, long long n, typename Bits<T>::U* __restrict__ slot) {
+    using U = typename Bits<T>::U;
+    __shared__ U red[16];
+    U m = 0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) m = part[i] > m ? part[i] : m;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const U y = __shfl_xor(m, o, kWave);
+        m = y > m ? y : m;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) m = red[w] > m ? red[w] : m;
+        *slot = m;
+    }
+}
+
+template <class T>
+hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStream_t st) {
+    using U = typename Bits<T>::U;
+    hipLaunchKernelGGL((max_finalize_kernel<T>), dim3(1), dim3(1024), 0, st, (const U*)part, n, (U*)slot);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ launchers ----
+// A launcher given max_out (the slot that receives the maximum of its output)
+// has its kernel store per-block maxima in part (>= grid-size entries of 8
+// bytes) and then reduces them into the slot.
 constexpr int kChunkX = 16;
 constexpr int kChunkY = 16;
 
+long long pfc_x_blocks(int rows, int nx, long long Nv) { return ((Nv + 255) / 256) * ((nx + kChunkX - 1) / kChunkX) * rows; }
+long long pfc_y_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
+    const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
+    return ((npairs + 255) / 256) * ((ny + kChunkY - 1) / kChunkY) * nx;
+}
+constexpr long long kArrayMaxBlocks = 4096;
+
+template <class T>
+static hipError_t finish_max(void* max_out, void* part, long long blocks, hipStream_t st) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !max_out) return e;
+    return launch_max_finalize<T>(part, blocks, max_out, st);
+}
+
 template <class T>
 hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, int inner, double vx_lo,
-                        double dvx, double tau_dx, const void* finf, void* max_out, hipStream_t st) {
-    dim3 grid((unsigned)(((Nv + 255) / 256) * ((nx + kChunkX - 1) / kChunkX) * rows));
-    hipLaunchKernelGGL((pfc_x_kernel<T, kChunkX>), grid, dim3(256), 0, st, fin, fout, nx, (int)Nv,
-                       1.0f / (float)inner, vx_lo, dvx, tau_dx, (const T*)finf, (typename Bits<T>::U*)max_out);
-    return hipGetLastError();
+                        double dvx, double tau_dx, const void* finf, void* max_out, void* part, hipStream_t st) {
+    const long long blocks = pfc_x_blocks(rows, nx, Nv);
+    hipLaunchKernelGGL((pfc_x_kernel<T, kChunkX>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx, (int)Nv,
+                       1.0f / (float)inner, vx_lo, dvx, tau_dx, (const T*)finf,
+                       (typename Bits<T>::U*)(max_out ? part : nullptr));
+    return finish_max<T>(max_out, part, blocks, st);
 }
 
 template <class T>
 hipError_t launch_pfc_y(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vy_lo,
-                        double dvy, double tau_dy, const void* finf, void* max_out, hipStream_t st) {
+                        double dvy, double tau_dy, const void* finf, void* max_out, void* part, hipStream_t st) {
     const int Nv = nvx * nvy * nvz;
     const int half = (nvy + 1) / 2;
-    const long long npairs = (long long)nvx * half * nvz;
-    dim3 grid((unsigned)(((npairs + 255) / 256) * ((ny + kChunkY - 1) / kChunkY) * nx));
-    hipLaunchKernelGGL((pfc_y_kernel<T, kChunkY>), grid, dim3(256), 0, st, fin, fout, nx, ny, Nv, nvx, nvy, nvz,
-                       1.0f / (float)nvz, 1.0f / (float)half, vy_lo, dvy, tau_dy, (const T*)finf,
-                       (typename Bits<T>::U*)max_out);
-    return hipGetLastError();
+    const long long blocks = pfc_y_blocks(nx, ny, nvx, nvy, nvz);
+    hipLaunchKernelGGL((pfc_y_kernel<T, kChunkY>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx, ny, Nv,
+                       nvx, nvy, nvz, 1.0f / (float)nvz, 1.0f / (float)half, vy_lo, dvy, tau_dy, (const T*)finf,
+                       (typename Bits<T>::U*)(max_out ? part : nullptr));
+    return finish_max<T>(max_out, part, blocks, st);
 }
 
 template <class T>
 hipError_t launch_pfc_v1(const T* fin, T* fout, int nx, int nv, const double* E, double qm_tau_dv,
-                         const void* finf, void* max_out, hipStream_t st) {
+                         const void* finf, void* max_out, void* part, hipStream_t st) {
     const int threads = nv >= 256 ? 256 : ((nv + 63) / 64) * 64;
     const size_t shm = sizeof(T) * (size_t)(nv + 4);
     hipLaunchKernelGGL((pfc_v1_kernel<T>), dim3(nx), dim3(threads), shm, st, fin, fout, nv, E, qm_tau_dv,
-                       (const T*)finf, (typename Bits<T>::U*)max_out);
-    return hipGetLastError();
+                       (const T*)finf, (typename Bits<T>::U*)(max_out ? part : nullptr));
+    return finish_max<T>(max_out, part, nx, st);
 }
 
 size_t v3_shared_bytes(int nvx, int nvy, int nvz, size_t elem) {
@@ -626,7 +672,7 @@ size_t v3_shared_bytes(int nvx, int nvy, int nvz, size_t elem) {
 
 template <class T>
 hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E, const double* B,
-                         const V3Params& P, const void* finf, void* max_out, hipStream_t st) {
+                         const V3Params& P, const void* finf, void* max_out, void* part, hipStream_t st) {
     const int nmax = P.nvx > P.nvy ? (P.nvx > P.nvz ? P.nvx : P.nvz) : (P.nvy > P.nvz ? P.nvy : P.nvz);
     const size_t shm = v3_shared_bytes(P.nvx, P.nvy, P.nvz, sizeof(T));
     int maxpen = P.nvx * P.nvy;
@@ -636,40 +682,34 @@ hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E
     if (threads > 256) threads = 256;
     if (threads < 64) threads = 64;
     const bool cube = P.nvx == P.nvy && P.nvy == P.nvz;
-    auto* mo = (typename Bits<T>::U*)max_out;
+    auto* mo = (typename Bits<T>::U*)(max_out ? part : nullptr);
+    const dim3 grid((unsigned)cells);
     if (cube && P.nvx == 16) {
-        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 16, 256>), dim3((unsigned)cells), dim3(256), 0, st, fin, fout, E, B, P,
-                           (const T*)finf, mo);
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 16, 256>), grid, dim3(256), 0, st, fin, fout, E, B, P, (const T*)finf, mo);
     } else if (cube && P.nvx == 12) {
-        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 12, 192>), dim3((unsigned)cells), dim3(192), 0, st, fin, fout, E, B, P,
-                           (const T*)finf, mo);
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 12, 192>), grid, dim3(192), 0, st, fin, fout, E, B, P, (const T*)finf, mo);
     } else if (cube && P.nvx == 8) {
-        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 8, 64>), dim3((unsigned)cells), dim3(64), 0, st, fin, fout, E, B, P,
-                           (const T*)finf, mo);
+        hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 8, 64>), grid, dim3(64), 0, st, fin, fout, E, B, P, (const T*)finf, mo);
     } else if (nmax <= 8) {
-        hipLaunchKernelGGL((pfc_v3_kernel<T, 8>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, E, B,
-                           P, (const T*)finf, (typename Bits<T>::U*)max_out);
+        hipLaunchKernelGGL((pfc_v3_kernel<T, 8>), grid, dim3(threads), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
     } else if (nmax <= 16) {
-        hipLaunchKernelGGL((pfc_v3_kernel<T, 16>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, E,
-                           B, P, (const T*)finf, (typename Bits<T>::U*)max_out);
+        hipLaunchKernelGGL((pfc_v3_kernel<T, 16>), grid, dim3(threads), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
     } else if (nmax <= 32) {
-        hipLaunchKernelGGL((pfc_v3_kernel<T, 32>), dim3((unsigned)cells), dim3(threads), shm, st, fin, fout, E,
-                           B, P, (const T*)finf, (typename Bits<T>::U*)max_out);
+        hipLaunchKernelGGL((pfc_v3_kernel<T, 32>), grid, dim3(threads), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
     } else {
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return finish_max<T>(max_out, part, cells, st);
 }
 
 template <class T>
-hipError_t launch_array_max(const T* f, long long n, void* out, hipStream_t st) {
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)out, 1, 0ull);
+hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipStream_t st) {
     long long blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > kArrayMaxBlocks) blocks = kArrayMaxBlocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((array_max_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, f, n,
-                       (typename Bits<T>::U*)out);
-    return hipGetLastError();
+                       (typename Bits<T>::U*)part);
+    return finish_max<T>(out, part, blocks, st);
 }
 
 hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st) {
@@ -679,14 +719,15 @@ hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st)
 
 #define VL_INST(T)                                                                                         \
     template hipError_t launch_pfc_x<T>(const T*, T*, int, int, long long, int, double, double, double,     \
-                                        const void*, void*, hipStream_t);                                  \
+                                        const void*, void*, void*, hipStream_t);                           \
     template hipError_t launch_pfc_y<T>(const T*, T*, int, int, int, int, int, double, double, double,      \
-                                        const void*, void*, hipStream_t);                                  \
+                                        const void*, void*, void*, hipStream_t);                           \
     template hipError_t launch_pfc_v1<T>(const T*, T*, int, int, const double*, double, const void*, void*, \
-                                         hipStream_t);                                                     \
+                                         void*, hipStream_t);                                              \
     template hipError_t launch_pfc_v3<T>(const T*, T*, long long, const double*, const double*,             \
-                                         const V3Params&, const void*, void*, hipStream_t);                \
-    template hipError_t launch_array_max<T>(const T*, long long, void*, hipStream_t);
+                                         const V3Params&, const void*, void*, void*, hipStream_t);         \
+    template hipError_t launch_array_max<T>(const T*, long long, void*, void*, hipStream_t);                \
+    template hipError_t launch_max_finalize<T>(const void*, long long, void*, hipStream_t);
 VL_INST(float)
 VL_INST(double)
 #undef VL_INST

@@ -34,6 +34,11 @@ struct vl_ctx {
     long long nv[VL_MAX_SPECIES] = {0, 0};
     // per-cell fitting parameters (3V), allocated on the first fit
     double* fit_scratch = nullptr;
+    // per-block partial maxima (8 bytes each) and clip counts (4 bytes each)
+    // of the largest grid any launch of this geometry uses
+    void* bpart = nullptr;
+    unsigned* bclip = nullptr;
+    long long max_blocks = 0;
     char err[512] = {0};
 };
 
@@ -112,6 +117,10 @@ vl_status ensure_device(vl_ctx* ctx) {
     void* p = nullptr;
     VL_HIP(hipMalloc(&p, bytes));
     VL_HIP(hipMemset(p, 0, bytes));
+    void* q = nullptr;
+    VL_HIP(hipMalloc(&q, 12 * (size_t)ctx->max_blocks));
+    ctx->bpart = q;
+    ctx->bclip = (unsigned*)((char*)q + 8 * (size_t)ctx->max_blocks);
     ctx->slots = (unsigned long long*)p;
     ctx->dft = (double*)(ctx->slots + kSlots * VL_MAX_SPECIES);
     ctx->part = ctx->dft + 2 * (size_t)ctx->cfg.nx + 2;
@@ -159,18 +168,18 @@ vl_status advect_x_typed(vl_ctx* ctx, int s, const T* fin, T* fout, T* fwork, do
     if (c.dim_x == 1) {
         Timed tm(ctx, VL_T_PFC_X, st);
         VL_HIP((vl::launch_pfc_x<T>(fin, fout, 1, c.nx, sp.nv[0], 1, sp.v_lo[0], dv_of(sp, 0), tau / dx_of(c), finf,
-                                    max_x, st)));
+                                    max_x, ctx->bpart, st)));
         return VL_OK;
     }
     const int inner = sp.nv[1] * sp.nv[2];
     {
         Timed tm(ctx, VL_T_PFC_X, st);
         VL_HIP((vl::launch_pfc_x<T>(fin, fwork, c.ny, c.nx, ctx->nv[s], inner, sp.v_lo[0], dv_of(sp, 0), tau / dx_of(c),
-                                finf, nullptr, st)));
+                                finf, nullptr, ctx->bpart, st)));
     }
     Timed tm(ctx, VL_T_PFC_Y, st);
     VL_HIP((vl::launch_pfc_y<T>(fwork, fout, c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2], sp.v_lo[1], dv_of(sp, 1),
-                                tau / dy_of(c), finf, max_y, st)));
+                                tau / dy_of(c), finf, max_y, ctx->bpart, st)));
     return VL_OK;
 }
 
@@ -182,7 +191,7 @@ vl_status advect_v_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double
     Timed tm(ctx, VL_T_PFC_V, st);
     if (c.dim_v == 1) {
         VL_HIP((vl::launch_pfc_v1<T>(fin, fout, c.nx, sp.nv[0], E, sp.q / sp.m * tau / dv_of(sp, 0), finf, max_out,
-                                     st)));
+                                     ctx->bpart, st)));
         return VL_OK;
     }
     vl::V3Params P;
@@ -197,7 +206,7 @@ vl_status advect_v_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double
     P.qm = sp.q / sp.m;
     P.tau = tau;
     P.inv_nvz = 1.0f / (float)sp.nv[2];
-    VL_HIP((vl::launch_pfc_v3<T>(fin, fout, ctx->cells, E, B, P, finf, max_out, st)));
+    VL_HIP((vl::launch_pfc_v3<T>(fin, fout, ctx->cells, E, B, P, finf, max_out, ctx->bpart, st)));
     return VL_OK;
 }
 
@@ -232,7 +241,7 @@ vl_status fit_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double* mom
     Timed tm(ctx, VL_T_FIT, st);
     if (c.dim_v == 1)
         VL_HIP((vl::launch_fit1<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, sp.nv[0], sp.v_lo[0],
-                                   dv_of(sp, 0), sp.m, max_out, st)));
+                                   dv_of(sp, 0), sp.m, max_out, ctx->bpart, st)));
     else {
         if (!ctx->fit_scratch) {
             void* p = nullptr;
@@ -240,7 +249,7 @@ vl_status fit_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double* mom
             ctx->fit_scratch = (double*)p;
         }
         VL_HIP((vl::launch_fit3<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, grid_args(sp), max_out,
-                                   ctx->fit_scratch, st)));
+                                   ctx->bpart, ctx->bclip, ctx->fit_scratch, st)));
     }
     return VL_OK;
 }
@@ -248,7 +257,7 @@ vl_status fit_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double* mom
 template <class T>
 vl_status array_max_typed(vl_ctx* ctx, int s, const T* f, void* out, hipStream_t st) {
     Timed tm(ctx, VL_T_MAX, st);
-    VL_HIP((vl::launch_array_max<T>(f, ctx->cells * ctx->nv[s], out, st)));
+    VL_HIP((vl::launch_array_max<T>(f, ctx->cells * ctx->nv[s], out, ctx->bpart, st)));
     return VL_OK;
 }
 
@@ -352,12 +361,9 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         for (int s = 0; s < ns; ++s) {
             T* f = (T*)S->f[s];
             T* tmp = (T*)S->f_tmp[s];
-            VL_HIP(vl::launch_fill_u64(slot(ctx, 1, s), 1, 0ull, st));
-            VL_HIP(vl::launch_fill_u64(slot(ctx, 2, s), 1, 0ull, st));
             if ((r = advect_x_typed<T>(ctx, s, f, f, tmp, 0.5 * dt, slot(ctx, 0, s), nullptr, slot(ctx, 1, s), st)) !=
                 VL_OK)
                 return r;
-            VL_HIP(vl::launch_fill_u64(slot(ctx, 0, s), 1, 0ull, st));
             if ((r = advect_v_typed<T>(ctx, s, f, f, E_h, B_h, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) != VL_OK)
                 return r;
             if ((r = advect_x_typed<T>(ctx, s, f, f, tmp, 0.5 * dt, slot(ctx, 2, s), nullptr,
@@ -394,12 +400,9 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         T* f = (T*)S->f[s];
         T* tmp = (T*)S->f_tmp[s];
         const double L = c.x_hi - c.x_lo;
-        VL_HIP(vl::launch_fill_u64(slot(ctx, 1, s), 1, 0ull, st));
-        VL_HIP(vl::launch_fill_u64(slot(ctx, 2, s), 1, 0ull, st));
         if ((r = advect_x_typed<T>(ctx, s, f, tmp, nullptr, 0.5 * dt, slot(ctx, 0, s), slot(ctx, 1, s), nullptr, st)) !=
             VL_OK)
             return r;
-        VL_HIP(vl::launch_fill_u64(slot(ctx, 0, s), 1, 0ull, st));
         if ((r = moments_typed<T>(ctx, s, tmp, mom_half, st)) != VL_OK) return r;
         {
             Timed tm(ctx, VL_T_FIELDS, st);
@@ -507,6 +510,20 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
     ctx->cfg = c;
     ctx->cells = (long long)c.nx * c.ny;
     for (int s = 0; s < c.nspecies; ++s) ctx->nv[s] = (long long)c.sp[s].nv[0] * c.sp[s].nv[1] * c.sp[s].nv[2];
+    // largest grid of a launch that produces a maximum (sizes the per-block partials)
+    long long mb = vl::kMaxArrayBlocks;
+    if (ctx->cells > mb) mb = ctx->cells;
+    for (int s = 0; s < c.nspecies; ++s) {
+        const vl_species& sp = c.sp[s];
+        const long long bx = c.dim_x == 1 ? vl::pfc_x_blocks(1, c.nx, sp.nv[0])
+                                          : vl::pfc_x_blocks(c.ny, c.nx, ctx->nv[s]);
+        if (bx > mb) mb = bx;
+        if (c.dim_x == 2) {
+            const long long by = vl::pfc_y_blocks(c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2]);
+            if (by > mb) mb = by;
+        }
+    }
+    ctx->max_blocks = mb;
     *out = ctx;
     return VL_OK;
 }
@@ -521,6 +538,7 @@ vl_status vl_destroy(vl_ctx* ctx) {
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->slots) (void)hipFree(ctx->slots);
     if (ctx->fit_scratch) (void)hipFree(ctx->fit_scratch);
+    if (ctx->bpart) (void)hipFree(ctx->bpart);
     delete ctx;
     return VL_OK;
 }

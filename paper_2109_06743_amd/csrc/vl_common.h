@@ -111,10 +111,13 @@ __device__ __forceinline__ void block_sum_rs(const double (&a)[K], double* red, 
     __syncthreads();
 }
 
-// Maximum over the block, folded into *slot with one atomic per block.
-// Every thread of the block must call it (it synchronises).
+// Maximum over the block of non-negative values, stored (as its bit pattern)
+// in part[blockIdx.x].  No atomics: many blocks folding into one address
+// serialise at the memory-side atomic unit, so a second launch
+// (launch_max_finalize) reduces the partials.  Every thread of the block must
+// call it (it synchronises).
 template <class T>
-__device__ __forceinline__ void block_max_to(T v, typename Bits<T>::U* slot) {
+__device__ __forceinline__ void block_max_part(T v, typename Bits<T>::U* part) {
     __shared__ T red[16];
     const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
     const int nthr = blockDim.x * blockDim.y * blockDim.z;
@@ -124,7 +127,7 @@ __device__ __forceinline__ void block_max_to(T v, typename Bits<T>::U* slot) {
     if (tid == 0) {
         T m = red[0];
         for (int w = 1; w < (nthr + kWave - 1) / kWave; ++w) m = fmax(m, red[w]);
-        atomicMax(slot, Bits<T>::of(m));
+        part[blockIdx.x] = Bits<T>::of(m);
     }
 }
 

@@ -19,13 +19,13 @@ struct V3Params;  // pfc_kernels.hip
 
 template <class T>
 hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, int inner, double vx_lo, double dvx,
-                        double tau_dx, const void* finf, void* max_out, hipStream_t st);
+                        double tau_dx, const void* finf, void* max_out, void* part, hipStream_t st);
 template <class T>
 hipError_t launch_pfc_y(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vy_lo, double dvy,
-                        double tau_dy, const void* finf, void* max_out, hipStream_t st);
+                        double tau_dy, const void* finf, void* max_out, void* part, hipStream_t st);
 template <class T>
 hipError_t launch_pfc_v1(const T* fin, T* fout, int nx, int nv, const double* E, double qm_tau_dv, const void* finf,
-                         void* max_out, hipStream_t st);
+                         void* max_out, void* part, hipStream_t st);
 struct V3Params {
     int nvx, nvy, nvz;
     double lo[3], dv[3], inv_dv[3];
@@ -39,10 +39,18 @@ struct V3Params {
 __device__ __forceinline__ int row_of(int e, float inv_n) { return (int)(((float)e + 0.5f) * inv_n); }
 template <class T>
 hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E, const double* B, const V3Params& P,
-                         const void* finf, void* max_out, hipStream_t st);
+                         const void* finf, void* max_out, void* part, hipStream_t st);
 size_t v3_shared_bytes(int nvx, int nvy, int nvz, size_t elem);
 template <class T>
-hipError_t launch_array_max(const T* f, long long n, void* out, hipStream_t st);
+hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipStream_t st);
+// Launchers that produce a maximum store per-block partials in `part` (8 bytes
+// per block of their grid) and reduce them into the slot in a second launch;
+// these give the grid sizes, to size `part`.
+long long pfc_x_blocks(int rows, int nx, long long Nv);
+long long pfc_y_blocks(int nx, int ny, int nvx, int nvy, int nvz);
+constexpr long long kMaxArrayBlocks = 4096;
+template <class T>
+hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStream_t st);
 hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st);
 
 template <class T>
@@ -55,10 +63,12 @@ hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, dou
 constexpr int kFitCellDoubles = 20;
 template <class T>
 hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
-                       long long cells, const VGridArgs& a, void* max_out, double* scratch, hipStream_t st);
+                       long long cells, const VGridArgs& a, void* max_out, void* part, unsigned* clip_part,
+                       double* scratch, hipStream_t st);
 template <class T>
 hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,
-                       long long cells, int nv, double vlo, double dv, double m, void* max_out, hipStream_t st);
+                       long long cells, int nv, double vlo, double dv, double m, void* max_out, void* part,
+                       hipStream_t st);
 
 hipError_t launch_poisson(const double* mom, int N, double L, double q, double* ab, double* E, hipStream_t st);
 hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
