@@ -4,9 +4,10 @@
 // point values at the faces, local Lax-Friedrichs flux with speed
 // |u_d| + sqrt(3 p_dd / (m n)), and SSP-RK3 (Shu-Osher) in time.
 //
-// Face fluxes are computed once per face by their own kernels (x faces, y
-// faces), then a per-cell kernel forms L(U) = -div H + S(U, E, B) and the RK
-// stage combination U_out = a U_n + b (U_s + dt L).
+// Face fluxes are computed once per face (both directions in one launch, one
+// thread per face and component), then a per-cell kernel forms
+// L(U) = -div H + S(U, E, B) and the RK stage combination
+// U_out = a U_n + b (U_s + dt L).
 //
 // Component orders: U = (n, nu_x, nu_y, nu_z, Pxx, Pxy, Pxz, Pyy, Pyz, Pzz);
 // Qcal (from the raw moment vector, offset 10) = (xxx, xxy, xxz, xyy, xyz,
@@ -69,28 +70,6 @@ struct FluidArgs {
     double dx, dy;
 };
 
-// Load U and Qcal (20 values) of cell (j, i); j may lie beyond a wall: the
-// mirror cell with odd components negated.  x is periodic.
-__device__ __forceinline__ void load_uq(const double* U, const double* QA, const double* QB, double wa, double wb,
-                                        int j, int i, const FluidArgs& A, double (&v)[20]) {
-    double sgn = 1.0;
-    bool mir = false;
-    if (j < 0) { j = -1 - j; mir = true; }
-    if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
-    i = (i % A.nx + A.nx) % A.nx;
-    const long long c = (long long)j * A.nx + i;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        sgn = mir ? par_u(k) : 1.0;
-        v[k] = sgn * U[c * 10 + k];
-    }
-#pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        sgn = mir ? par_q(k) : 1.0;
-        v[10 + k] = sgn * (wa * QA[c * 20 + 10 + k] + (wb != 0.0 ? wb * QB[c * 20 + 10 + k] : 0.0));
-    }
-}
-
 __device__ __forceinline__ double speed3(const double* U, int d, double m) {
     const double n = U[0];
     const double u = U[1 + d] / n;
@@ -98,65 +77,79 @@ __device__ __forceinline__ double speed3(const double* U, int d, double m) {
     return fabs(u) + sqrt(fmax(3.0 * p / (m * n), 0.0));
 }
 
-__device__ __forceinline__ void flux3(const double* U, const double* Q, int d, double m, double* F) {
-    F[0] = U[1 + d];
-    F[1] = U[4 + p_index(0, d)] / m;
-    F[2] = U[4 + p_index(1, d)] / m;
-    F[3] = U[4 + p_index(2, d)] / m;
-    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) F[4 + k] = Q[q_index(ia[k], ib[k], d)];
-}
+// Both face directions in one launch, one thread per (face, component): a
+// block takes kFaceTile consecutive faces of one row (x faces i+1/2 of row j,
+// or y faces jh-1/2 at columns i), reconstructs the 20 components (U and
+// Qcal) at both sides of each face into shared memory, then forms the 10
+// flux components.  Blocks [0, nbx) are x faces, the rest y faces.
+constexpr int kFaceTile = 32;
 
-// Numerical flux through the face between cells "left" (index 1 of the four)
-// and "right" (index 2), given the four cells along direction d.
-__device__ __forceinline__ void face_flux3(const double (&c0)[20], const double (&c1)[20], const double (&c2)[20],
-                                           const double (&c3)[20], int d, double m, double* H) {
-    double Um[10], Up[10], Qm[10], Qp[10];
-#pragma unroll
-    for (int k = 0; k < 20; ++k) {
-        double l1, r1, l2, r2;
-        cweno(c0[k], c1[k], c2[k], l1, r1);   // cell 1: its right face
-        cweno(c1[k], c2[k], c3[k], l2, r2);   // cell 2: its left face
-        if (k < 10) { Um[k] = r1; Up[k] = l2; }
-        else { Qm[k - 10] = r1; Qp[k - 10] = l2; }
+__device__ __forceinline__ double load_comp(const double* U, const double* QA, const double* QB, double wa,
+                                            double wb, int j, int i, int k, const FluidArgs& A) {
+    bool mir = false;
+    if (j < 0) { j = -1 - j; mir = true; }
+    if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
+    i = (i % A.nx + A.nx) % A.nx;
+    const long long c = (long long)j * A.nx + i;
+    double v;
+    if (k < 10) {
+        v = U[c * 10 + k];
+        if (mir) v *= par_u(k);
+    } else {
+        v = wa * QA[c * 20 + k] + (wb != 0.0 ? wb * QB[c * 20 + k] : 0.0);
+        if (mir) v *= par_q(k - 10);
     }
-    const double a = fmax(speed3(Um, d, m), speed3(Up, d, m));
-    double Fm[10], Fp[10];
-    flux3(Um, Qm, d, m, Fm);
-    flux3(Up, Qp, d, m, Fp);
-#pragma unroll
-    for (int k = 0; k < 10; ++k) H[k] = 0.5 * (Fp[k] + Fm[k]) - 0.5 * a * (Up[k] - Um[k]);
+    return v;
 }
 
-// x faces: face i+1/2 of row j, i = 0..nx-1 -> Hx[(j*nx + i)*10]
-__global__ void flux_x3_kernel(const double* __restrict__ U, const double* __restrict__ QA,
-                               const double* __restrict__ QB, double wa, double wb, FluidArgs A,
-                               double* __restrict__ Hx) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= A.nx) return;
-    double c0[20], c1[20], c2[20], c3[20];
-    load_uq(U, QA, QB, wa, wb, j, i - 1, A, c0);
-    load_uq(U, QA, QB, wa, wb, j, i, A, c1);
-    load_uq(U, QA, QB, wa, wb, j, i + 1, A, c2);
-    load_uq(U, QA, QB, wa, wb, j, i + 2, A, c3);
-    face_flux3(c0, c1, c2, c3, 0, A.m, Hx + ((long long)j * A.nx + i) * 10);
-}
-
-// y faces: face jh-1/2 (between rows jh-1 and jh), jh = 0..ny -> Hy[(jh*nx + i)*10]
-__global__ void flux_y3_kernel(const double* __restrict__ U, const double* __restrict__ QA,
-                               const double* __restrict__ QB, double wa, double wb, FluidArgs A,
-                               double* __restrict__ Hy) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int jh = blockIdx.y;
-    if (i >= A.nx) return;
-    double c0[20], c1[20], c2[20], c3[20];
-    load_uq(U, QA, QB, wa, wb, jh - 2, i, A, c0);
-    load_uq(U, QA, QB, wa, wb, jh - 1, i, A, c1);
-    load_uq(U, QA, QB, wa, wb, jh, i, A, c2);
-    load_uq(U, QA, QB, wa, wb, jh + 1, i, A, c3);
-    face_flux3(c0, c1, c2, c3, 1, A.m, Hy + ((long long)jh * A.nx + i) * 10);
+__global__ void __launch_bounds__(kFaceTile * 20)
+faces3_kernel(const double* __restrict__ U, const double* __restrict__ QA, const double* __restrict__ QB, double wa,
+              double wb, FluidArgs A, int nbx_row, int nbx, double* __restrict__ Hx, double* __restrict__ Hy) {
+    __shared__ double Lm[kFaceTile][20], Lp[kFaceTile][20];   // minus (left/below) and plus sides
+    const bool yface = (int)blockIdx.x >= nbx;
+    const int b = yface ? (int)blockIdx.x - nbx : (int)blockIdx.x;
+    const int row = b / nbx_row;                   // j for x faces, jh for y faces
+    const int i0 = (b % nbx_row) * kFaceTile;
+    const int f = threadIdx.x % kFaceTile, k = threadIdx.x / kFaceTile;
+    const int i = i0 + f;
+    if (i < A.nx) {
+        double c0, c1, c2, c3;
+        if (!yface) {
+            c0 = load_comp(U, QA, QB, wa, wb, row, i - 1, k, A);
+            c1 = load_comp(U, QA, QB, wa, wb, row, i, k, A);
+            c2 = load_comp(U, QA, QB, wa, wb, row, i + 1, k, A);
+            c3 = load_comp(U, QA, QB, wa, wb, row, i + 2, k, A);
+        } else {
+            c0 = load_comp(U, QA, QB, wa, wb, row - 2, i, k, A);
+            c1 = load_comp(U, QA, QB, wa, wb, row - 1, i, k, A);
+            c2 = load_comp(U, QA, QB, wa, wb, row, i, k, A);
+            c3 = load_comp(U, QA, QB, wa, wb, row + 1, i, k, A);
+        }
+        double l1, r1, l2, r2;
+        cweno(c0, c1, c2, l1, r1);   // cell below/left of the face: its upper face value
+        cweno(c1, c2, c3, l2, r2);   // cell above/right: its lower face value
+        Lm[f][k] = r1;
+        Lp[f][k] = l2;
+    }
+    __syncthreads();
+    if (k >= 10 || i >= A.nx) return;
+    const int d = yface ? 1 : 0;
+    const double a = fmax(speed3(Lm[f], d, A.m), speed3(Lp[f], d, A.m));
+    // flux component k: n -> nu_d, nu_i -> P_id / m, P_ab -> Qcal_abd
+    int src;
+    double sc = 1.0;
+    if (k == 0) {
+        src = 1 + d;
+    } else if (k < 4) {
+        src = 4 + p_index(k - 1, d);
+        sc = 1.0 / A.m;
+    } else {
+        const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+        src = 10 + q_index(ia[k - 4], ib[k - 4], d);
+    }
+    const double Fm = Lm[f][src] * sc, Fp = Lp[f][src] * sc;
+    double* H = yface ? Hy : Hx;
+    H[((long long)row * A.nx + i) * 10 + k] = 0.5 * (Fp + Fm) - 0.5 * a * (Lp[f][k] - Lm[f][k]);
 }
 
 // U_out = a U_n + b (U_s + dt L(U_s)); U_out may alias U_n (each cell reads
@@ -296,9 +289,11 @@ hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
                                  hipStream_t st) {
     FluidArgs A{nx, ny, m, q, dx, dy};
-    dim3 blk(64), gc((nx + 63) / 64, ny), gy((nx + 63) / 64, ny + 1);
-    hipLaunchKernelGGL(flux_x3_kernel, gc, blk, 0, st, Us, QA, QB, wa, wb, A, Hx);
-    hipLaunchKernelGGL(flux_y3_kernel, gy, blk, 0, st, Us, QA, QB, wa, wb, A, Hy);
+    dim3 blk(64), gc((nx + 63) / 64, ny);
+    const int nbx_row = (nx + kFaceTile - 1) / kFaceTile;
+    const int nbx = nbx_row * ny, nby = nbx_row * (ny + 1);
+    hipLaunchKernelGGL(faces3_kernel, dim3(nbx + nby), dim3(kFaceTile * 20), 0, st, Us, QA, QB, wa, wb, A, nbx_row,
+                       nbx, Hx, Hy);
     hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A);
     return hipGetLastError();
 }

@@ -724,12 +724,25 @@ hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, dou
     return hipGetLastError();
 }
 
-// counters[0] += sum of the per-block clip counts (one block, fixed order).
+// counters[0] += sum of the per-block clip counts (one block, 16-byte loads,
+// fixed order).
 __global__ void __launch_bounds__(1024)
 count_finalize_kernel(const unsigned* __restrict__ part, long long n, unsigned long long* __restrict__ counters) {
     __shared__ unsigned long long red[16];
     unsigned long long acc = 0;
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    const long long n16 = n / 4;
+    const uint4* p16 = reinterpret_cast<const uint4*>(part);
+    for (long long b = 0; b < n16; b += 8 * (long long)blockDim.x) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long long i = b + u * (long long)blockDim.x + threadIdx.x;
+            v[u] = i < n16 ? p16[i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (unsigned long long)v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+    for (long long i = n16 * 4 + threadIdx.x; i < n; i += blockDim.x) acc += part[i];
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;

@@ -585,14 +585,32 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long
 }
 
 // Maximum of the per-block partial maxima part[0..n) into *slot (bits of
-// non-negative values order like the values).  One block, fixed order.
+// non-negative values order like the values).  One block; 16-byte loads,
+// eight in flight per thread; fixed order.
 template <class T>
 __global__ void __launch_bounds__(1024)
 max_finalize_kernel(const typename Bits<T>::U* __restrict__ part, long long n, typename Bits<T>::U* __restrict__ slot) {
     using U = typename Bits<T>::U;
+    constexpr int PER = 16 / sizeof(U);            // partials per 16-byte load
     __shared__ U red[16];
     U m = 0;
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) m = part[i] > m ? part[i] : m;
+    const long long n16 = n / PER;
+    const uint4* p16 = reinterpret_cast<const uint4*>(part);
+    for (long long b = 0; b < n16; b += 8 * (long long)blockDim.x) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long long i = b + u * (long long)blockDim.x + threadIdx.x;
+            v[u] = i < n16 ? p16[i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const U* e = reinterpret_cast<const U*>(&v[u]);
+#pragma unroll
+            for (int k = 0; k < PER; ++k) m = e[k] > m ? e[k] : m;
+        }
+    }
+    for (long long i = n16 * PER + threadIdx.x; i < n; i += blockDim.x) m = part[i] > m ? part[i] : m;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         const U y = __shfl_xor(m, o, kWave);

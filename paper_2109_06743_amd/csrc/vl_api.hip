@@ -523,7 +523,7 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
             if (by > mb) mb = by;
         }
     }
-    ctx->max_blocks = mb;
+    ctx->max_blocks = (mb + 3) / 4 * 4;   // keeps the clip partials 16-byte aligned after the maxima
     *out = ctx;
     return VL_OK;
 }
