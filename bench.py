@@ -109,8 +109,7 @@ def run_gpu(cfg, f, F, dtype, steps, warmup, mlp_params=None):
 
 # kernel category -> (source files of its kernels, kernel name in the profiles)
 KERNEL_SOURCES = {
-    "pfc_x": ("pfc_kernels.hip", "pfc_x_kernel"),
-    "pfc_y": ("pfc_kernels.hip", "pfc_y_kernel"),
+    "pfc_x": ("pfc_kernels.hip", "pfc_xy_kernel"),    # 2X3V: x and y sweeps fused
     "pfc_v": ("pfc_kernels.hip", "pfc_v3_cube_kernel"),
     "fit": ("moment_kernels.hip", "fit3_cube_kernel"),
     "moments": ("moment_kernels.hip", "moments3_cube_kernel"),
@@ -147,7 +146,7 @@ def recorded_traffic(category, workload):
 # Algorithmic bytes per phase-space cell and launch, in units of the f
 # element size: one read and one write of one species' f (moments: one read);
 # halo re-reads and the small spatial arrays are not counted.
-ALG_BYTES_PER_CELL = {"pfc_x": 2, "pfc_y": 2, "pfc_v": 2, "fit": 2, "moments": 1}
+ALG_BYTES_PER_CELL = {"pfc_x": 2, "pfc_v": 2, "fit": 2, "moments": 1}
 
 
 def roofline(res, workload):

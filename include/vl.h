@@ -100,10 +100,11 @@ vl_status vl_destroy(vl_ctx* ctx);
 
 /* Free streaming X(tau) of species s (Eq. 1, v . grad f; split PFC sweeps,
  * Sec. 2.1): x-sweep by v_x tau/dx cells (periodic), then in 2X3V a y-sweep
- * by v_y tau/dy cells between reflecting walls.  The PFC limiter bound is
- * the maximum of f_in.  f_in is not modified.  In 2X3V f_work (same size as
- * f) receives the intermediate x-swept array; in 1X1V it may be NULL.
- * f_out must not alias f_in or f_work (VL_EALIAS). */
+ * by v_y tau/dy cells between reflecting walls, both with the PFC limiter
+ * bound max(f_in).  In 2X3V the two sweeps run fused in one pass (the
+ * x-swept array is never stored).  f_in is not modified.  f_work is not
+ * used (may be NULL; kept for source compatibility).  f_out must not alias
+ * f_in (VL_EALIAS). */
 vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, void* f_work,
                           double tau, vl_stream stream);
 
@@ -165,7 +166,8 @@ vl_status vl_fluid_step(vl_ctx* ctx, int32_t s, double* U, const double* mom_t, 
 
 /* Full time step (Algorithm 1).  All pointers are device buffers.
  *   f[s]        in: f^t, out: f^{t+1}
- *   f_tmp[s]    scratch of the same size as f[s]
+ *   f_tmp[s]    scratch of the same size as f[s] (holds f between X(dt/2) and
+ *               the second X(dt/2))
  *   mom_post[s] in: raw moments of f^t; out: of f^{t+1} (after fitting)
  *   mom_pre[s]  out: raw moments of f^{t+1} before fitting
  *   U[s]        fluid state (used when fit = 1), in/out

@@ -107,100 +107,30 @@ pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int Nv, fl
 }
 
 // ---------------------------------------------------------------------------
-// y sweep between reflecting walls: the pencil at +v_y (rows 0..ny-1) followed
-// by its mirror pencil at -v_y in reverse row order is one periodic pencil of
-// length 2 ny moving uniformly by v_y tau / dy > 0.  A thread owns one pair and
-// the CY rows [c0, c0+CY) of it twice: as positions c0.. of the +v_y half and
-// as the mirrored positions of the -v_y half, so every row a block touches is
-// read and written for both halves of each v_x plane (whole DRAM pages).  Odd
-// nvy: the v_y = 0 pencil pairs with itself at zero shift (an exact copy).
-// Windows inside one half advance a pointer by one row per element; windows
-// that touch a wall or the seam map each position.
-template <class T>
-__device__ __forceinline__ const T* pos_ptr(const T* up, const T* dn, int p, int ny, size_t rs) {
-    return p < ny ? up + (size_t)p * rs : dn + (size_t)(2 * ny - 1 - p) * rs;
-}
-
-template <class T, int CY>
-__device__ __forceinline__ void y_window(const T* up, const T* dn, T* oup, T* odn, int q0, int nq, int K, int ny,
-                                         size_t rs, const ShiftT<T>& sh, T F2, T& mx) {
-    const int L2 = 2 * ny;
-    int p = q0 - K - 2;
-    while (p < 0) p += L2;
-    T W[CY + 3];
-    if (p + CY + 2 < ny) {                       // window inside the +v_y half
-        const T* q = up + (size_t)p * rs;
-#pragma unroll
-        for (int w = 0; w < CY + 3; ++w) {
-            W[w] = *q;
-            q += rs;
-        }
-    } else if (p >= ny && p + CY + 2 < L2) {     // window inside the mirrored half
-        const T* q = dn + (size_t)(L2 - 1 - p) * rs;
-#pragma unroll
-        for (int w = 0; w < CY + 3; ++w) {
-            W[w] = *q;
-            q -= rs;
-        }
-    } else {
-#pragma unroll
-        for (int w = 0; w < CY + 3; ++w) {
-            W[w] = *pos_ptr(up, dn, p, ny, rs);
-            if (++p == L2) p = 0;
-        }
-    }
-    T o[CY];
-    T D = W[2] - W[1];
-    T phi_prev = pfc_phi_d(W[1], W[1] - W[0], D, sh.a, sh.ac1, sh.ac2, F2);
-#pragma unroll
-    for (int r = 0; r < CY; ++r) {
-        const T Dn = W[r + 3] - W[r + 2];
-        const T phi_next = pfc_phi_d(W[r + 2], D, Dn, sh.a, sh.ac1, sh.ac2, F2);
-        o[r] = fmax(W[r + 2] + phi_prev - phi_next, T(0));
-        phi_prev = phi_next;
-        D = Dn;
-    }
-    if (nq == CY && q0 + CY <= ny) {
-        T* q = oup + (size_t)q0 * rs;
-#pragma unroll
-        for (int r = 0; r < CY; ++r) {
-            *q = o[r];
-            mx = fmax(mx, o[r]);
-            q += rs;
-        }
-    } else if (nq == CY && q0 >= ny && q0 + CY <= L2) {
-        T* q = odn + (size_t)(L2 - 1 - q0) * rs;
-#pragma unroll
-        for (int r = 0; r < CY; ++r) {
-            *q = o[r];
-            mx = fmax(mx, o[r]);
-            q -= rs;
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < CY; ++r) {
-            const int qq = q0 + r;
-            if (r < nq) {
-                *const_cast<T*>(pos_ptr<T>(oup, odn, qq, ny, rs)) = o[r];
-                mx = fmax(mx, o[r]);
-            }
-        }
-    }
-}
-
-template <class T, int CY>
+// Fused X(tau) for 2X3V: the x sweep and then the y sweep with one f_inf, in
+// one pass over f.  A thread owns one (v_x, |v_y|, v_z) pair, C adjacent x
+// cells and a segment of S positions of the doubled reflecting y pencil
+// (positions 0..ny-1: rows of the +v_y half; ny..2ny-1: rows ny-1..0 of the
+// -v_y half).  It walks its segment, x-sweeping the C cells of each position
+// on the fly (a window of C+3 inputs in registers) and feeding the result to
+// the y update, f'(q) = P(q-K) + phi(q-K-1) - phi(q-K) with P the x-swept
+// pencil, so the intermediate array never reaches memory.  Per segment the x
+// sweep runs S+3 times for S outputs; the extra rows are re-read from cache.
+// Work order: x strip fastest, so neighbouring strips stream the same rows
+// at the same time.
+template <class T, int C, int S>
 __global__ void __launch_bounds__(256)
-pfc_y_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, int Nv, int nvx, int nvy, int nvz,
-             float inv_nvz, float inv_half, double vy_lo, double dvy, double tau_dy, const T* __restrict__ finf_p,
-             typename Bits<T>::U* __restrict__ max_out) {
-    const int half = (nvy + 1) / 2;                 // pairs per (ivx, ivz), incl. a v_y = 0 self-pair
+pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, int Nv, int nvx, int nvy, int nvz,
+              float inv_nvz, float inv_half, double vx_lo, double dvx, double tau_dx, double vy_lo, double dvy,
+              double tau_dy, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
+    const int half = (nvy + 1) / 2;
     const int npairs = nvx * half * nvz;
-    // work index = (pair block fastest, then row chunk, then x cell), XCD-contiguous
-    const unsigned npb = (unsigned)(npairs + 255) / 256, nch = (ny + CY - 1) / CY;
+    const int L = 2 * ny;
+    const unsigned nst = (unsigned)(nx + C - 1) / C, nseg = (unsigned)(L + S - 1) / S;
     const unsigned wi = xcd_work_index(blockIdx.x, gridDim.x);
-    const int pid = (int)(wi % npb) * 256 + threadIdx.x;
-    const int c0 = (int)((wi / npb) % nch) * CY;
-    const int ix = (int)(wi / (npb * nch));
+    const int c0 = (int)(wi % nst) * C;
+    const int i0 = (int)((wi / nst) % nseg) * S;
+    const int pid = (int)(wi / (nst * nseg)) * 256 + threadIdx.x;
     const T F2 = T(2) * *finf_p;
     T mx = T(0);
     if (pid < npairs) {
@@ -208,21 +138,88 @@ pfc_y_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, in
         const int ivz = pid - r1 * nvz;
         const int ivx = row_of(r1, inv_half);
         const int jh = r1 - ivx * half;
-        const int jup = nvy - half + jh;            // v_y >= 0 half
-        const int jdn = nvy - 1 - jup;              // its mirror
-        const size_t rs = (size_t)nx * Nv;
-        const T* up = fin + (size_t)ix * Nv + (size_t)(ivx * nvy + jup) * nvz + ivz;
-        const T* dn = fin + (size_t)ix * Nv + (size_t)(ivx * nvy + jdn) * nvz + ivz;
-        T* oup = fout + (up - fin);
-        T* odn = fout + (dn - fin);
-        const double s = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
-        const ShiftT<T> sh(s);
-        const int L2 = 2 * ny;
-        const int K = sh.K < L2 ? sh.K : sh.K % L2;
-        const int rows = (c0 + CY <= ny) ? CY : ny - c0;
-        // rows [c0, c0+rows) as +v_y positions, then as mirrored -v_y positions
-        y_window<T, CY>(up, dn, oup, odn, c0, rows, K, ny, rs, sh, F2, mx);
-        y_window<T, CY>(up, dn, oup, odn, L2 - c0 - rows, rows, K, ny, rs, sh, F2, mx);
+        const int jup = nvy - half + jh;
+        const int jdn = nvy - 1 - jup;
+        const unsigned vu = (unsigned)((ivx * nvy + jup) * nvz + ivz), vd = (unsigned)((ivx * nvy + jdn) * nvz + ivz);
+        const unsigned rs = (unsigned)nx * (unsigned)Nv;     // row stride (< 2^31, checked on the host)
+        // x: uniform shift along the row (the same for both halves)
+        const double sxd = (vx_lo + (ivx + 0.5) * dvx) * tau_dx;
+        const bool posx = sxd >= 0.0;
+        const Shift<T> shx(fabs(sxd));
+        const int Kx = shx.K < nx ? (int)shx.K : (int)(shx.K % nx);
+        // window columns, upwind to downwind, as element offsets within a row
+        unsigned coff[C + 3];
+        {
+            int col = posx ? c0 - Kx - 2 : c0 + Kx + C + 1;
+            while (col < 0) col += nx;
+            while (col >= nx) col -= nx;
+#pragma unroll
+            for (int w = 0; w < C + 3; ++w) {
+                coff[w] = (unsigned)col * (unsigned)Nv;
+                col += posx ? 1 : -1;
+                if (col == nx) col = 0;
+                if (col < 0) col = nx - 1;
+            }
+        }
+        // y: the doubled pencil moves by sy >= 0 cells
+        const double syd = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
+        const ShiftT<T> shy(syd);
+        const int Ky = shy.K < L ? shy.K : shy.K % L;
+        auto base_of = [&](int j) -> unsigned {       // start of position j (any integer) of the doubled pencil
+            j %= L;
+            if (j < 0) j += L;
+            return j < ny ? (unsigned)j * rs + vu : (unsigned)(L - 1 - j) * rs + vd;
+        };
+        auto load = [&](int j, T (&W)[C + 3]) {
+            const unsigned b = base_of(j);
+#pragma unroll
+            for (int w = 0; w < C + 3; ++w) W[w] = fin[b + coff[w]];
+        };
+        auto xsweep = [&](const T (&W)[C + 3], T (&P)[C]) {
+            T D = W[2] - W[1];
+            T phi_prev = pfc_phi_d(W[1], W[1] - W[0], D, shx.a, shx.ac1, shx.ac2, F2);
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                const T Dn = W[r + 3] - W[r + 2];
+                const T phi_next = pfc_phi_d(W[r + 2], D, Dn, shx.a, shx.ac1, shx.ac2, F2);
+                P[r] = fmax(W[r + 2] + phi_prev - phi_next, T(0));
+                phi_prev = phi_next;
+                D = Dn;
+            }
+        };
+        const int i1 = i0 + S < L ? i0 + S : L;
+        T Wn[C + 3], Pa[C], Pb[C], Pc[C], phi_prev[C];
+        load(i0 - 2, Wn);
+        xsweep(Wn, Pa);
+        load(i0 - 1, Wn);
+        xsweep(Wn, Pb);
+        load(i0, Wn);
+        xsweep(Wn, Pc);
+#pragma unroll
+        for (int r = 0; r < C; ++r) phi_prev[r] = pfc_phi_d(Pb[r], Pb[r] - Pa[r], Pc[r] - Pb[r], shy.a, shy.ac1, shy.ac2, F2);
+        load(i0 + 1, Wn);
+        for (int i = i0; i < i1; ++i) {
+            T Wc[C + 3];
+#pragma unroll
+            for (int w = 0; w < C + 3; ++w) Wc[w] = Wn[w];
+            if (i + 1 < i1) load(i + 2, Wn);           // next position's inputs in flight
+            T Pn[C];
+            xsweep(Wc, Pn);                            // P(i+1)
+            const unsigned ob = base_of(i + Ky);
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                const T phi = pfc_phi_d(Pc[r], Pc[r] - Pb[r], Pn[r] - Pc[r], shy.a, shy.ac1, shy.ac2, F2);
+                const T o = fmax(Pc[r] + phi_prev[r] - phi, T(0));
+                const int col = posx ? c0 + r : c0 + C - 1 - r;
+                if (col < nx) {
+                    fout[ob + (unsigned)col * (unsigned)Nv] = o;
+                    mx = fmax(mx, o);
+                }
+                phi_prev[r] = phi;
+                Pb[r] = Pc[r];
+                Pc[r] = Pn[r];
+            }
+        }
     }
     if (max_out) block_max_part(mx, max_out);
 }
@@ -636,13 +633,8 @@ hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStr
 // has its kernel store per-block maxima in part (>= grid-size entries of 8
 // bytes) and then reduces them into the slot.
 constexpr int kChunkX = 16;
-constexpr int kChunkY = 16;
 
 long long pfc_x_blocks(int rows, int nx, long long Nv) { return ((Nv + 255) / 256) * ((nx + kChunkX - 1) / kChunkX) * rows; }
-long long pfc_y_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
-    const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
-    return ((npairs + 255) / 256) * ((ny + kChunkY - 1) / kChunkY) * nx;
-}
 constexpr long long kArrayMaxBlocks = 4096;
 
 template <class T>
@@ -662,15 +654,22 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
     return finish_max<T>(max_out, part, blocks, st);
 }
 
+constexpr int kXyCols = 4, kXySeg = 32;
+long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
+    const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
+    return ((npairs + 255) / 256) * ((2LL * ny + kXySeg - 1) / kXySeg) * ((nx + kXyCols - 1) / kXyCols);
+}
+
 template <class T>
-hipError_t launch_pfc_y(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vy_lo,
-                        double dvy, double tau_dy, const void* finf, void* max_out, void* part, hipStream_t st) {
+hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vx_lo, double dvx,
+                         double tau_dx, double vy_lo, double dvy, double tau_dy, const void* finf, void* max_out,
+                         void* part, hipStream_t st) {
     const int Nv = nvx * nvy * nvz;
     const int half = (nvy + 1) / 2;
-    const long long blocks = pfc_y_blocks(nx, ny, nvx, nvy, nvz);
-    hipLaunchKernelGGL((pfc_y_kernel<T, kChunkY>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx, ny, Nv,
-                       nvx, nvy, nvz, 1.0f / (float)nvz, 1.0f / (float)half, vy_lo, dvy, tau_dy, (const T*)finf,
-                       (typename Bits<T>::U*)(max_out ? part : nullptr));
+    const long long blocks = pfc_xy_blocks(nx, ny, nvx, nvy, nvz);
+    hipLaunchKernelGGL((pfc_xy_kernel<T, kXyCols, kXySeg>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx,
+                       ny, Nv, nvx, nvy, nvz, 1.0f / (float)nvz, 1.0f / (float)half, vx_lo, dvx, tau_dx, vy_lo, dvy,
+                       tau_dy, (const T*)finf, (typename Bits<T>::U*)(max_out ? part : nullptr));
     return finish_max<T>(max_out, part, blocks, st);
 }
 
@@ -738,13 +737,13 @@ hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st)
 #define VL_INST(T)                                                                                         \
     template hipError_t launch_pfc_x<T>(const T*, T*, int, int, long long, int, double, double, double,     \
                                         const void*, void*, void*, hipStream_t);                           \
-    template hipError_t launch_pfc_y<T>(const T*, T*, int, int, int, int, int, double, double, double,      \
-                                        const void*, void*, void*, hipStream_t);                           \
     template hipError_t launch_pfc_v1<T>(const T*, T*, int, int, const double*, double, const void*, void*, \
                                          void*, hipStream_t);                                              \
     template hipError_t launch_pfc_v3<T>(const T*, T*, long long, const double*, const double*,             \
                                          const V3Params&, const void*, void*, void*, hipStream_t);         \
     template hipError_t launch_array_max<T>(const T*, long long, void*, void*, hipStream_t);                \
+    template hipError_t launch_pfc_xy<T>(const T*, T*, int, int, int, int, int, double, double, double, double, \
+                                         double, double, const void*, void*, void*, hipStream_t);          \
     template hipError_t launch_max_finalize<T>(const void*, long long, void*, hipStream_t);
 VL_INST(float)
 VL_INST(double)

@@ -171,15 +171,12 @@ vl_status advect_x_typed(vl_ctx* ctx, int s, const T* fin, T* fout, T* fwork, do
                                     max_x, ctx->bpart, st)));
         return VL_OK;
     }
-    const int inner = sp.nv[1] * sp.nv[2];
-    {
-        Timed tm(ctx, VL_T_PFC_X, st);
-        VL_HIP((vl::launch_pfc_x<T>(fin, fwork, c.ny, c.nx, ctx->nv[s], inner, sp.v_lo[0], dv_of(sp, 0), tau / dx_of(c),
-                                finf, nullptr, ctx->bpart, st)));
-    }
-    Timed tm(ctx, VL_T_PFC_Y, st);
-    VL_HIP((vl::launch_pfc_y<T>(fwork, fout, c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2], sp.v_lo[1], dv_of(sp, 1),
-                                tau / dy_of(c), finf, max_y, ctx->bpart, st)));
+    // 2X3V: x and y sweeps fused into one pass (the x-swept array stays in registers)
+    (void)fwork;
+    Timed tm(ctx, VL_T_PFC_X, st);
+    VL_HIP((vl::launch_pfc_xy<T>(fin, fout, c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2], sp.v_lo[0], dv_of(sp, 0),
+                                 tau / dx_of(c), sp.v_lo[1], dv_of(sp, 1), tau / dy_of(c), finf, max_y, ctx->bpart,
+                                 st)));
     return VL_OK;
 }
 
@@ -361,12 +358,14 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         for (int s = 0; s < ns; ++s) {
             T* f = (T*)S->f[s];
             T* tmp = (T*)S->f_tmp[s];
-            if ((r = advect_x_typed<T>(ctx, s, f, f, tmp, 0.5 * dt, slot(ctx, 0, s), nullptr, slot(ctx, 1, s), st)) !=
+            // X(dt/2): f -> tmp; V(dt): tmp in place; X(dt/2): tmp -> f
+            if ((r = advect_x_typed<T>(ctx, s, f, tmp, nullptr, 0.5 * dt, slot(ctx, 0, s), nullptr, slot(ctx, 1, s),
+                                       st)) != VL_OK)
+                return r;
+            if ((r = advect_v_typed<T>(ctx, s, tmp, tmp, E_h, B_h, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) !=
                 VL_OK)
                 return r;
-            if ((r = advect_v_typed<T>(ctx, s, f, f, E_h, B_h, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) != VL_OK)
-                return r;
-            if ((r = advect_x_typed<T>(ctx, s, f, f, tmp, 0.5 * dt, slot(ctx, 2, s), nullptr,
+            if ((r = advect_x_typed<T>(ctx, s, tmp, f, nullptr, 0.5 * dt, slot(ctx, 2, s), nullptr,
                                        c.fit ? nullptr : slot(ctx, 0, s), st)) != VL_OK)
                 return r;
             if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
@@ -519,7 +518,7 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
                                           : vl::pfc_x_blocks(c.ny, c.nx, ctx->nv[s]);
         if (bx > mb) mb = bx;
         if (c.dim_x == 2) {
-            const long long by = vl::pfc_y_blocks(c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2]);
+            const long long by = vl::pfc_xy_blocks(c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2]);
             if (by > mb) mb = by;
         }
     }
@@ -548,10 +547,9 @@ vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out,
     vl_status r = check_species(ctx, s);
     if (r != VL_OK) return r;
     if (!f_in || !f_out) return fail(ctx, VL_EINVAL, "null f");
-    if (ctx->cfg.dim_x == 2 && !f_work) return fail(ctx, VL_EINVAL, "2X3V needs f_work");
     if (!finite_pos(tau)) return fail(ctx, VL_EINVAL, "tau must be finite and > 0");
-    if (f_out == f_in || (f_work && (f_work == f_in || f_work == f_out)))
-        return fail(ctx, VL_EALIAS, "f_out/f_work alias");
+    if (f_out == f_in) return fail(ctx, VL_EALIAS, "f_out aliases f_in");
+    (void)f_work;
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     void* S = slot(ctx, 3, s);

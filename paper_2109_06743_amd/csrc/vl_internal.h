@@ -21,9 +21,6 @@ template <class T>
 hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, int inner, double vx_lo, double dvx,
                         double tau_dx, const void* finf, void* max_out, void* part, hipStream_t st);
 template <class T>
-hipError_t launch_pfc_y(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vy_lo, double dvy,
-                        double tau_dy, const void* finf, void* max_out, void* part, hipStream_t st);
-template <class T>
 hipError_t launch_pfc_v1(const T* fin, T* fout, int nx, int nv, const double* E, double qm_tau_dv, const void* finf,
                          void* max_out, void* part, hipStream_t st);
 struct V3Params {
@@ -47,7 +44,12 @@ hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipS
 // per block of their grid) and reduce them into the slot in a second launch;
 // these give the grid sizes, to size `part`.
 long long pfc_x_blocks(int rows, int nx, long long Nv);
-long long pfc_y_blocks(int nx, int ny, int nvx, int nvy, int nvz);
+long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz);
+// Fused X(tau) of 2X3V (x then y sweep, one f_inf); fout must not alias fin.
+template <class T>
+hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vx_lo, double dvx,
+                         double tau_dx, double vy_lo, double dvy, double tau_dy, const void* finf, void* max_out,
+                         void* part, hipStream_t st);
 constexpr long long kMaxArrayBlocks = 4096;
 template <class T>
 hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStream_t st);

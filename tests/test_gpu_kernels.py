@@ -82,7 +82,11 @@ def test_integer_shift_is_bitwise_exact(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("nx,ny,nv,tau", [(12, 6, 8, 0.5), (20, 9, 6, 1.7)])
+@pytest.mark.parametrize("nx,ny,nv,tau", [(12, 6, 8, 0.5), (20, 9, 6, 1.7),
+                                          # x strips with a ragged last strip, several y segments
+                                          # of the doubled pencil (2*ny > 32) with a short last one,
+                                          # shifts of more than a cell in x and y
+                                          (37, 41, 6, 2.3), (8, 20, 8, 0.05)])
 def test_x_sweep_2x3v(dtype, nx, ny, nv, tau):
     import torch
     cfg, _, _ = W.gem(nx=nx, ny=ny, nv=nv, dtype=np.float64)
@@ -92,8 +96,8 @@ def test_x_sweep_2x3v(dtype, nx, ny, nv, tau):
     for s, sp in enumerate(cfg["species"]):
         f = storage_round(W.random_block((ny, nx, nv, nv, nv), seed=10 + s, kind="smooth"), dtype)
         fin = dev(f, dtype)
-        fout, fwork = torch.empty_like(fin), torch.empty_like(fin)
-        ctx.pfc_advect_x(s, fin, fout, fwork, tau)
+        fout = torch.empty_like(fin)
+        ctx.pfc_advect_x(s, fin, fout, None, tau)
         ctx.sync()
         v, _ = _grid3(sp)
         ref = OV.x_advect_2x3v(f, v[0], v[1], dx, dy, tau)
