@@ -460,7 +460,7 @@ fit3_params_kernel(const double* __restrict__ mom_pre, double* __restrict__ U, l
 // then the exchange, clip, FP64 post-fit moments and the FP64 rescale.  The
 // block sums use the reduce-scatter (block_sum_rs).
 #ifndef FIT_KEEP_G
-#define FIT_KEEP_G 0
+#define FIT_KEEP_G 1
 #endif
 #ifndef FIT16_NW
 #define FIT16_NW 2

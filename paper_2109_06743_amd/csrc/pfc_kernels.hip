@@ -654,10 +654,18 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
     return finish_max<T>(max_out, part, blocks, st);
 }
 
-constexpr int kXyCols = 4, kXySeg = 32;
-long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
+// x cells per thread (FP32: 8 keeps 4 waves/SIMD; FP64 registers allow 4) and
+// doubled-pencil positions per segment
+template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
+constexpr int kXySeg = 32;
+template <class T>
+long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz) {
     const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
-    return ((npairs + 255) / 256) * ((2LL * ny + kXySeg - 1) / kXySeg) * ((nx + kXyCols - 1) / kXyCols);
+    return ((npairs + 255) / 256) * ((2LL * ny + kXySeg - 1) / kXySeg) * ((nx + xy_cols<T>() - 1) / xy_cols<T>());
+}
+long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
+    const long long a = pfc_xy_blocks_t<float>(nx, ny, nvx, nvy, nvz), b = pfc_xy_blocks_t<double>(nx, ny, nvx, nvy, nvz);
+    return a > b ? a : b;
 }
 
 template <class T>
@@ -666,8 +674,8 @@ hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy
                          void* part, hipStream_t st) {
     const int Nv = nvx * nvy * nvz;
     const int half = (nvy + 1) / 2;
-    const long long blocks = pfc_xy_blocks(nx, ny, nvx, nvy, nvz);
-    hipLaunchKernelGGL((pfc_xy_kernel<T, kXyCols, kXySeg>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx,
+    const long long blocks = pfc_xy_blocks_t<T>(nx, ny, nvx, nvy, nvz);
+    hipLaunchKernelGGL((pfc_xy_kernel<T, xy_cols<T>(), kXySeg>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx,
                        ny, Nv, nvx, nvy, nvz, 1.0f / (float)nvz, 1.0f / (float)half, vx_lo, dvx, tau_dx, vy_lo, dvy,
                        tau_dy, (const T*)finf, (typename Bits<T>::U*)(max_out ? part : nullptr));
     return finish_max<T>(max_out, part, blocks, st);
