@@ -203,7 +203,8 @@ size_t vl_step_work_size(const vl_ctx* ctx);
 vl_status vl_step(vl_ctx* ctx, vl_state* st, double dt, vl_stream stream);
 /* With closure = VL_CLOSURE_MLP the fluid RK3 of every species takes its
  * third moment at each stage from the network applied to that stage's fluid
- * state (Q-calligraphic = Q_net + sym(u P) - 2 m n uuu), instead of from f.
+ * state and that stage's magnetic field (Q-calligraphic = Q_net + sym(u P) -
+ * 2 m n uuu), instead of from f.
  * Before the fluid update the network is judged on the moments of f^{t+1}:
  * the relative L2 error (over the species' cells) of its heat-flux vector
  * q_i = Q_ijj against the kinetic one goes to closure_err[s]; above
@@ -224,13 +225,16 @@ enum { VL_MLP_IN = 64, VL_MLP_WIDTH = 64, VL_MLP_OUT = 10, VL_MLP_OUT_PAD = 16, 
 
 /* Features of every spatial cell of species s (2X3V) from a moment array whose
  * first ten entries per cell are (n, nu, P): raw moments (stride 20) or a
- * fluid state (stride 10).  x: uint16 BF16 [cells][64]; scale: double
+ * fluid state (stride 10), and the cell-centred magnetic field B [cells][3]
+ * (may be NULL: zero direction).  x: uint16 BF16 [cells][64]; scale: double
  * [cells] = n m v_t^3 (0 for a cell with n <= 1e-12 or tr T <= 0, whose
  * features are 0).  Features: u/v_t, T/T_ref, then for n/n_c, u/v_t, T/T_ref
  * on the 3x3 stencil the differences d_x, d_y, d_xx, d_yy, d_xy (grid units;
- * x periodic, y mirrored at the walls), a species one-hot, zero padding. */
-vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t stride, uint16_t* x,
-                          double* scale, vl_stream stream);
+ * x periodic, y mirrored at the walls), a species one-hot, B/|B|.  The heat
+ * flux follows the field direction (Sec. 4.1 discussion), which a
+ * temperature-gradient closure cannot represent. */
+vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t stride, const double* B,
+                          uint16_t* x, double* scale, vl_stream stream);
 /* Training targets: normalised kinetic heat flux [cells][16] (FP32, entries
  * 10..15 zero) from raw moments [cells][20] of species s. */
 vl_status vl_mlp_targets(vl_ctx* ctx, int32_t s, const double* mom, float* y, vl_stream stream);

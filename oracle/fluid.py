@@ -163,10 +163,11 @@ def rk3_3v(U, Q_t, Q_t1, fields_t, fields_t1, fields_th, q, m, dx, dy, dt):
 
 def rk3_3v_stagewise(U, qcal_of, fields_t, fields_t1, fields_th, q, m, dx, dy, dt):
     """SSP-RK3 with the third moment of each stage computed from that stage's
-    state by qcal_of(U_stage) (a closure instead of the kinetic moments)."""
-    U1 = U + dt * rhs_3v(U, qcal_of(U), *fields_t, q, m, dx, dy)
-    U2 = 0.75 * U + 0.25 * (U1 + dt * rhs_3v(U1, qcal_of(U1), *fields_t1, q, m, dx, dy))
-    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs_3v(U2, qcal_of(U2), *fields_th, q, m, dx, dy))
+    state and fields by qcal_of(U_stage, B_stage) (a closure instead of the
+    kinetic moments)."""
+    U1 = U + dt * rhs_3v(U, qcal_of(U, fields_t[1]), *fields_t, q, m, dx, dy)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * rhs_3v(U1, qcal_of(U1, fields_t1[1]), *fields_t1, q, m, dx, dy))
+    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs_3v(U2, qcal_of(U2, fields_th[1]), *fields_th, q, m, dx, dy))
 
 
 # ------------------------------------------------------- 1V (1X1V) --------

@@ -24,7 +24,10 @@ the network is in the paper; every choice below is a reading:
            neighbour); x periodic, y mirrored at the walls with the sign of
            u_y, T_xy, T_yz flipped (reflection symmetry of the particles).
     59-60  species one-hot (0: first species, 1: second)
-    61-63  zero
+    61-63  direction B/|B| of the cell-centred magnetic field (0 where |B| <=
+           1e-12 or no field is given): the paper observes that the heat
+           flux follows B, which the temperature-gradient closure cannot see
+           (Sec. 4.1 discussion).
   A cell with n <= 1e-12 or tr(T) <= 0 gets all-zero features and scale 0.
 * Target: the heat-flux tensor normalised by n m v_t^3, ten components in
   the order of oracle.moments.TRIPLES, padded to 16 outputs with zeros.
@@ -112,8 +115,9 @@ def _y_parity_uT():
     return pu, pT
 
 
-def features(U, m, species):
-    """U[ny, nx, >=10] -> (x[ny*nx, 64] FP64 before rounding, scale[ny*nx])."""
+def features(U, m, species, B=None):
+    """U[ny, nx, >=10], B[ny, nx, 3] or None -> (x[ny*nx, 64] FP64 before
+    rounding, scale[ny*nx])."""
     U = np.asarray(U, dtype=np.float64)
     ny, nx = U.shape[:2]
     n, u, T6 = _local(U, m)
@@ -159,14 +163,19 @@ def features(U, m, species):
         for d, arr in enumerate((d_x, d_y, d_xx, d_yy, d_xy)):
             x[..., 9 + 5 * k + d] = arr[..., k]
     x[..., 59 + species] = 1.0
+    if B is not None:
+        B = np.asarray(B, dtype=np.float64).reshape(ny, nx, 3)
+        bn = np.sqrt((B * B).sum(-1))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            x[..., 61:64] = np.where((bn > 1e-12)[..., None], B / bn[..., None], 0.0)
     x = np.where(ok[..., None], x, 0.0)
     scale = np.where(ok, n * m * vt ** 3, 0.0)
     return x.reshape(ny * nx, N_IN), scale.reshape(ny * nx)
 
 
-def features_bf16(U, m, species):
+def features_bf16(U, m, species, B=None):
     """Features as the network sees them: FP64 -> FP32 -> BF16."""
-    x, scale = features(U, m, species)
+    x, scale = features(U, m, species, B)
     return bf16_round(to_f32(x)), scale
 
 
@@ -314,25 +323,25 @@ def gradient_closure_divergence(U, m, q, dx, dy):
 
 
 # ------------------------------------------------- the closure in a step ----
-def network_heat_flux(U, m, species, params):
+def network_heat_flux(U, m, species, params, B=None):
     """Normalised network output y[ny, nx, 16] and scale[ny, nx] for the cells
-    of U[ny, nx, >=10]."""
+    of U[ny, nx, >=10] (B: cell-centred field for the direction features)."""
     ny, nx = U.shape[:2]
-    x, scale = features_bf16(U, m, species)
+    x, scale = features_bf16(U, m, species, B)
     y, _ = forward(params, x)
     return y.reshape(ny, nx, N_OUT_PAD), scale.reshape(ny, nx)
 
 
-def closure_qcal(U, m, species, params):
+def closure_qcal(U, m, species, params, B=None):
     """Q-calligraphic of every cell from the network applied to U."""
-    y, scale = network_heat_flux(U, m, species, params)
+    y, scale = network_heat_flux(U, m, species, params, B)
     return qcal_from_closure(U, y, scale, m)
 
 
-def judge_error(mom, m, species, params):
+def judge_error(mom, m, species, params, B=None):
     """Relative L2 error over the cells of the network's heat-flux vector
     q_i = sum_j Q_ijj against the kinetic one, both from raw moments mom."""
-    y, scale = network_heat_flux(mom[..., :10], m, species, params)
+    y, scale = network_heat_flux(mom[..., :10], m, species, params, B)
     Qn = scale[..., None] * y[..., :N_OUT]
     Qk = heat_flux(mom, m)
 

@@ -17,7 +17,8 @@ solver), with these readings where it is silent:
 * With fitting switched off the step is the standard PFC Vlasov step (the
   fluid is not advanced).
 * Learned closure (cfg["closure"] == "mlp", 2X3V; not in the paper): the
-  network (oracle.mlp) is judged on the moments of f^{t+1} before fitting;
+  network (oracle.mlp) is judged on the moments of f^{t+1} before fitting
+  with the field direction of (E, B)^{t+1} (the extrapolated stage field);
   if its heat-flux error exceeds cfg["closure_tol"] (or when st["fallback"]
   says so for that species) the step is the kinetic one, otherwise the fluid
   RK3 takes each stage's Q-calligraphic from the network applied to that
@@ -100,13 +101,13 @@ def step_2x3v(st, cfg, dt):
         if cfg.get("fit"):
             use_net = False
             if cfg.get("closure") == "mlp":
-                err = mlp.judge_error(mom_pre, m, k, st["mlp_params"])
+                err = mlp.judge_error(mom_pre, m, k, st["mlp_params"], fields_t1[1])
                 fb = st["fallback"][k] if st.get("fallback") is not None else not (err <= cfg["closure_tol"])
                 out["closure_err"].append(err)
                 out["fallback"].append(bool(fb))
                 use_net = not fb
             if use_net:
-                U = fluid.rk3_3v_stagewise(U, lambda V, k=k, m=m: mlp.closure_qcal(V, m, k, st["mlp_params"]),
+                U = fluid.rk3_3v_stagewise(U, lambda V, Bs, k=k, m=m: mlp.closure_qcal(V, m, k, st["mlp_params"], Bs),
                                            (E_0, B_0), fields_t1, (E_h, B_h), q, m, dx, dy, dt)
             else:
                 U = fluid.rk3_3v(U, st["mom_post"][k][..., 10:], mom_pre[..., 10:],

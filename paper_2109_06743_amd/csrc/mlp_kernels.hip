@@ -164,8 +164,9 @@ __device__ __forceinline__ float sum16(float v) {
 
 // --------------------------------------------------------------- features --
 // Per cell: n, u, T (6) of the centre and its 8 neighbours (x periodic, y
-// mirrored with u_y, T_xy, T_yz negated) -> 64 features rounded FP64 -> FP32
-// -> BF16, and the scale n m v_t^3.
+// mirrored with u_y, T_xy, T_yz negated), the species and the direction of
+// the cell-centred magnetic field -> 64 features rounded FP64 -> FP32 ->
+// BF16, and the scale n m v_t^3.
 __device__ __forceinline__ bool local_nuT(const double* __restrict__ M, int stride, long long c, double m,
                                           bool mir, double& n, double (&u)[3], double (&T)[6]) {
     n = M[c * stride];
@@ -185,8 +186,8 @@ __device__ __forceinline__ bool local_nuT(const double* __restrict__ M, int stri
 }
 
 __global__ void __launch_bounds__(64)
-mlp_features_kernel(const double* __restrict__ M, int stride, int nx, int ny, double m, int species,
-                    unsigned short* __restrict__ x, double* __restrict__ scale) {
+mlp_features_kernel(const double* __restrict__ M, int stride, const double* __restrict__ B, int nx, int ny,
+                    double m, int species, unsigned short* __restrict__ x, double* __restrict__ scale) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= nx) return;
@@ -239,6 +240,15 @@ mlp_features_kernel(const double* __restrict__ M, int stride, int nx, int ny, do
             f[9 + 5 * k + 4] = (float)((phi[2][2][k] - phi[0][2][k] - phi[2][0][k] + phi[0][0][k]) / 4.0);
         }
         f[59 + species] = 1.f;
+        if (B) {     // direction of the cell-centred magnetic field
+            const double bx = B[c * 3], by = B[c * 3 + 1], bz = B[c * 3 + 2];
+            const double bn = sqrt(bx * bx + by * by + bz * bz);
+            if (bn > 1e-12) {
+                f[61] = (float)(bx / bn);
+                f[62] = (float)(by / bn);
+                f[63] = (float)(bz / bn);
+            }
+        }
     }
     unsigned short* o = x + c * kIn;
 #pragma unroll
@@ -537,10 +547,10 @@ __global__ void mlp_judge_finish_kernel(const double* __restrict__ part, int nbl
 // --------------------------------------------------------------- launchers --
 constexpr int kJudgeBlocks = 256;
 
-hipError_t launch_mlp_features(const double* M, int stride, int nx, int ny, double m, int species,
+hipError_t launch_mlp_features(const double* M, int stride, const double* B, int nx, int ny, double m, int species,
                                unsigned short* x, double* scale, hipStream_t st) {
-    hipLaunchKernelGGL(mlp_features_kernel, dim3((nx + 63) / 64, ny), dim3(64), 0, st, M, stride, nx, ny, m, species,
-                       x, scale);
+    hipLaunchKernelGGL(mlp_features_kernel, dim3((nx + 63) / 64, ny), dim3(64), 0, st, M, stride, B, nx, ny, m,
+                       species, x, scale);
     return hipGetLastError();
 }
 

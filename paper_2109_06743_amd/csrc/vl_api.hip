@@ -291,7 +291,7 @@ vl_status fluid_step_mlp(vl_ctx* ctx, int s, const vl_state* S, const double* E_
     const double* mom_t1 = S->mom_pre[s];
     int* fb = S->closure_fallback + s;
     Timed tm(ctx, VL_T_FLUID, st);
-    VL_HIP(vl::launch_mlp_features(mom_t1, 20, c.nx, c.ny, sp.m, s, x, scale, st));
+    VL_HIP(vl::launch_mlp_features(mom_t1, 20, B_t1, c.nx, c.ny, sp.m, s, x, scale, st));
     VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, cells, y, st));
     VL_HIP(vl::launch_mlp_judge(mom_t1, scale, y, cells, sp.m, c.closure_tol, part, fb, S->closure_err + s, st));
     double* U = S->U[s];
@@ -307,7 +307,7 @@ vl_status fluid_step_mlp(vl_ctx* ctx, int s, const vl_state* S, const double* E_
         {U2, U, U, mom_t, mom_t1, 0.5, 0.5, E_th, B_th, 1.0 / 3.0, 2.0 / 3.0},
     };
     for (int k = 0; k < 3; ++k) {
-        VL_HIP(vl::launch_mlp_features(G[k].Us, 10, c.nx, c.ny, sp.m, s, x, scale, st));
+        VL_HIP(vl::launch_mlp_features(G[k].Us, 10, G[k].B, c.nx, c.ny, sp.m, s, x, scale, st));
         VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, cells, y, st));
         VL_HIP(vl::launch_mlp_qcal(G[k].Us, scale, y, fb, G[k].QA, G[k].QB, G[k].wa, G[k].wb, cells, sp.m, qc, st));
         VL_HIP(vl::launch_fluid_stage_3v(G[k].Us, G[k].Un, G[k].Uo, qc, qc, 1.0, 0.0, G[k].E, G[k].B, G[k].a, G[k].b,
@@ -678,8 +678,8 @@ vl_status vl_step(vl_ctx* ctx, vl_state* S, double dt, vl_stream stream) {
     return DISPATCH(ctx, step_typed<float>(ctx, S, dt, st), step_typed<double>(ctx, S, dt, st));
 }
 
-vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t stride, uint16_t* x, double* scale,
-                          vl_stream stream) {
+vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t stride, const double* B, uint16_t* x,
+                          double* scale, vl_stream stream) {
     vl_status r = check_species(ctx, s);
     if (r != VL_OK) return r;
     if (ctx->cfg.dim_v != 3) return fail(ctx, VL_ENOTSUP, "the learned closure is defined for 2X3V");
@@ -687,7 +687,7 @@ vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t str
     if (stride != 10 && stride != 20) return fail(ctx, VL_EINVAL, "stride must be 10 or 20");
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     const vl_config& c = ctx->cfg;
-    VL_HIP(vl::launch_mlp_features(mom, stride, c.nx, c.ny, c.sp[s].m, s, x, scale, (hipStream_t)stream));
+    VL_HIP(vl::launch_mlp_features(mom, stride, B, c.nx, c.ny, c.sp[s].m, s, x, scale, (hipStream_t)stream));
     return VL_OK;
 }
 

@@ -98,7 +98,7 @@ hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo,
 
 // learned heat-flux closure (mlp_kernels.hip)
 constexpr int kMlpParams = 13520;
-hipError_t launch_mlp_features(const double* M, int stride, int nx, int ny, double m, int species,
+hipError_t launch_mlp_features(const double* M, int stride, const double* B, int nx, int ny, double m, int species,
                                unsigned short* x, double* scale, hipStream_t st);
 hipError_t launch_mlp_targets(const double* M, long long cells, double m, float* y, hipStream_t st);
 hipError_t launch_mlp_forward(const float* P, const unsigned short* x, long long n, float* y, hipStream_t st);

@@ -94,7 +94,7 @@ def load():
         "vl_sync": ([vp, vp], i32),
         "vl_timing_enable": ([vp, ctypes.c_uint32], i32),
         "vl_timing_read": ([vp, vp, vp], i32),
-        "vl_mlp_features": ([vp, i32, vp, i32, vp, vp, vp], i32),
+        "vl_mlp_features": ([vp, i32, vp, i32, vp, vp, vp, vp], i32),
         "vl_mlp_targets": ([vp, i32, vp, vp, vp], i32),
         "vl_mlp_forward": ([vp, vp, vp, ctypes.c_int64, vp, vp], i32),
         "vl_mlp_work_size": ([ctypes.c_int64], sz),
@@ -234,9 +234,10 @@ class Context:
         self._check(self.lib.vl_sync(self.h, _stream(stream)))
 
     # ---- learned heat-flux closure -----------------------------------------
-    def mlp_features(self, s, mom, stride, x, scale, stream=None):
-        """x: int16 tensor [cells, 64] (BF16 bits), scale: float64 [cells]."""
-        self._check(self.lib.vl_mlp_features(self.h, s, _ptr(mom), int(stride), _ptr(x), _ptr(scale),
+    def mlp_features(self, s, mom, stride, x, scale, B=None, stream=None):
+        """x: int16 tensor [cells, 64] (BF16 bits), scale: float64 [cells];
+        B: cell-centred magnetic field [cells, 3] or None."""
+        self._check(self.lib.vl_mlp_features(self.h, s, _ptr(mom), int(stride), _ptr(B), _ptr(x), _ptr(scale),
                                              _stream(stream)))
 
     def mlp_targets(self, s, mom, y, stream=None):

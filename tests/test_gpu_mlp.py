@@ -60,13 +60,16 @@ def test_features_and_targets_match_oracle():
     cfg, moms = _perturbed_gem_moments(nx, ny, nv, 3)
     ctx = vl.Context(cfg, "f32")
     cells = nx * ny
+    Bf = np.random.default_rng(4).normal(size=(ny, nx, 3))
+    Bf[2, 3] = 0.0                                       # a cell without field
     for s, sp in enumerate(cfg["species"]):
-        for stride, arr in ((20, moms[s]), (10, moms[s][..., :10])):
+        for stride, arr, B in ((20, moms[s], None), (10, moms[s][..., :10], Bf), (20, moms[s], Bf)):
             x = torch.zeros(cells * 64, dtype=torch.int16, device="cuda")
             sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
-            ctx.mlp_features(s, _t(arr.reshape(-1), torch.float64), stride, x, sc)
+            ctx.mlp_features(s, _t(arr.reshape(-1), torch.float64), stride, x, sc,
+                             B=None if B is None else _t(B.reshape(-1), torch.float64))
             ctx.sync()
-            xr, scr = OM.features_bf16(arr, sp["m"], s)
+            xr, scr = OM.features_bf16(arr, sp["m"], s, B)
             xg = _bf16_values(x).reshape(cells, 64)
             # FP64 rounding order may differ: allow one BF16 unit, and require
             # nearly every feature to be identical
@@ -252,39 +255,45 @@ def test_closure_fallback_equals_kinetic_step():
 # ------------------------------------------------------------- the gain ----
 def _gem_snapshots(nx, ny, nv, steps, every, start):
     """Run the GEM set-up on the GPU (FP32 f, fitting on) and collect the
-    post-step raw moments of both species every `every` steps."""
+    post-step raw moments of both species and the cell-centred B every
+    `every` steps."""
     import torch
     from paper_2109_06743_amd import vl
     cfg, f, F0 = W.gem(nx=nx, ny=ny, nv=nv, dt=0.003, fit=True, dtype=np.float32)
     ctx = vl.Context(cfg, "f32")
     st = vl.StepState(ctx, f, vl.yee_pack(F0))
+    cells = nx * ny
+    E = torch.zeros(cells * 3, dtype=torch.float64, device="cuda")
     snaps = []
     for k in range(1, steps + 1):
         ctx.step(st, cfg["dt"])
         if k >= start and k % every == 0:
-            snaps.append([m.clone() for m in st.mom_pre])
+            B = torch.zeros(cells * 3, dtype=torch.float64, device="cuda")
+            ctx.cell_fields(st.fields, E, B)
+            snaps.append(([m.clone() for m in st.mom_pre], B))
     ctx.sync()
     return cfg, ctx, snaps
 
 
 def test_trained_network_beats_gradient_closure():
     """Train on the solver's own moments and kinetic heat flux (GEM set-up,
-    32x16 x 16^3, both species), then compare on later, held-out snapshots the
-    heat-flux divergence (the term the fluid update uses) predicted by the
-    network and by Eq. 5 against the kinetic one."""
+    32x16 x 16^3, both species), then compare on held-out snapshots (every
+    fifth) the heat-flux divergence (the term the fluid update uses) predicted
+    by the network and by Eq. 5 against the kinetic one."""
     import torch
     nx, ny, nv = 32, 16, 16
     cfg, ctx, snaps = _gem_snapshots(nx, ny, nv, steps=600, every=15, start=60)
     cells = nx * ny
-    n_train = int(0.8 * len(snaps))
+    train = [sn for i, sn in enumerate(snaps) if i % 5 != 2]
+    held = [sn for i, sn in enumerate(snaps) if i % 5 == 2]
     xs, ys = [], []
-    for snap in snaps[:n_train]:
+    for mom, B in train:
         for s in range(2):
             x = torch.zeros(cells, 64, dtype=torch.int16, device="cuda")
             sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
             y = torch.zeros(cells, 16, dtype=torch.float32, device="cuda")
-            ctx.mlp_features(s, snap[s], 20, x, sc)
-            ctx.mlp_targets(s, snap[s], y)
+            ctx.mlp_features(s, mom[s], 20, x, sc, B=B)
+            ctx.mlp_targets(s, mom[s], y)
             xs.append(x)
             ys.append(y)
     X = torch.cat(xs).contiguous()
@@ -310,15 +319,15 @@ def test_trained_network_beats_gradient_closure():
     dx = (cfg["x_hi"] - cfg["x_lo"]) / nx
     dy = (cfg["y_hi"] - cfg["y_lo"]) / ny
     err_net, err_grad = [], []
-    for snap in snaps[n_train:]:
+    for momt, B in held:
         for s, sp in enumerate(cfg["species"]):
             x = torch.zeros(cells, 64, dtype=torch.int16, device="cuda")
             sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
             y = torch.zeros(cells, 16, dtype=torch.float32, device="cuda")
-            ctx.mlp_features(s, snap[s], 20, x, sc)
+            ctx.mlp_features(s, momt[s], 20, x, sc, B=B)
             ctx.mlp_forward(P, x, y)
             ctx.sync()
-            mom = host(snap[s]).reshape(ny, nx, 20)
+            mom = host(momt[s]).reshape(ny, nx, 20)
             Qk = OM.heat_flux(mom, sp["m"])
             Qn = host(sc).reshape(ny, nx, 1) * host(y).reshape(ny, nx, 16)[..., :10]
             dk = OM.divergence_heat_flux(Qk, dx, dy)

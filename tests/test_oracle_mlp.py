@@ -325,3 +325,22 @@ def test_gradient_closure_closed_form():
     for c in (0, 3, 5):
         np.testing.assert_allclose(d[1, :, c], -OM.CHI * d_s * vt * lap, rtol=1e-10, atol=1e-14)
     np.testing.assert_allclose(d[..., [1, 2, 4]], 0.0, atol=1e-14)
+
+
+def test_field_direction_features():
+    m = 1.0
+
+    def fn(x, y):
+        return np.full(x.shape, 1.5), np.zeros(x.shape + (3,)), _iso(0.3, x.shape)
+    U = _state(3, 4, m, fn)
+    B = np.zeros((3, 4, 3))
+    B[..., 0] = 3.0
+    B[..., 2] = -4.0
+    B[1, 2] = 0.0                                   # no field in one cell
+    x0, _ = OM.features(U, m, 1)
+    x1, _ = OM.features(U, m, 1, B)
+    x0, x1 = x0.reshape(3, 4, 64), x1.reshape(3, 4, 64)
+    np.testing.assert_array_equal(x0[..., :61], x1[..., :61])
+    np.testing.assert_allclose(x1[0, 0, 61:], [0.6, 0.0, -0.8], rtol=1e-15)
+    np.testing.assert_array_equal(x1[1, 2, 61:], 0.0)
+    np.testing.assert_array_equal(x0[..., 61:], 0.0)
