@@ -23,17 +23,23 @@ constexpr double kCwenoEps = 1e-6;
 // and centred polynomials evaluated at +-h/2 are
 //   P_L = b -+ (b - a)/2,  P_R = b -+ (c - b)/2,  P_C = b + d2/6 -+ (c - a)/4,
 // d2 = c - 2b + a, weighted with (1/4, 1/2, 1/4) / (eps + IS)^2, normalised.
+// With D = (eps + IS)^2 the normalised weights are
+//   w_L = Dc Dr / S, w_C = 2 Dl Dr / S, w_R = Dl Dc / S,
+//   S = Dc Dr + 2 Dl Dr + Dl Dc
+// (one division), and since they sum to one the point values are b plus the
+// weighted corrections (a constant state reconstructs to itself exactly).
 __device__ __forceinline__ void cweno(double a, double b, double c, double& left, double& right) {
     const double dl = b - a, dr = c - b, d2 = c - 2.0 * b + a, dc = c - a;
-    const double isl = dl * dl, isr = dr * dr, isc = (13.0 / 3.0) * d2 * d2 + 0.25 * dc * dc;
-    const double al = 0.25 / ((kCwenoEps + isl) * (kCwenoEps + isl));
-    const double ac = 0.5 / ((kCwenoEps + isc) * (kCwenoEps + isc));
-    const double ar = 0.25 / ((kCwenoEps + isr) * (kCwenoEps + isr));
-    const double inv = 1.0 / (al + ac + ar);
-    const double wl = al * inv, wc = ac * inv, wr = ar * inv;
-    const double cen = b + d2 / 6.0;
-    right = wl * (b + 0.5 * dl) + wc * (cen + 0.25 * dc) + wr * (b + 0.5 * dr);
-    left = wl * (b - 0.5 * dl) + wc * (cen - 0.25 * dc) + wr * (b - 0.5 * dr);
+    const double el = kCwenoEps + dl * dl, er = kCwenoEps + dr * dr;
+    const double ec = kCwenoEps + (13.0 / 3.0) * d2 * d2 + 0.25 * dc * dc;
+    const double Dl = el * el, Dc = ec * ec, Dr = er * er;
+    const double tl = Dc * Dr, tc = 2.0 * Dl * Dr, tr = Dl * Dc;
+    const double inv = 1.0 / (tl + tc + tr);
+    const double wl = tl * inv, wc = tc * inv, wr = tr * inv;
+    const double side = 0.5 * (wl * dl + wr * dr) + 0.25 * wc * dc;   // odd part
+    const double even = wc * (d2 * (1.0 / 6.0));                         // even part
+    right = b + (even + side);
+    left = b + (even - side);
 }
 
 // index helpers for the symmetric second and third moments
@@ -67,7 +73,7 @@ __device__ __forceinline__ double par_q(int k) {
 struct FluidArgs {
     int nx, ny;
     double m, q;
-    double dx, dy;
+    double idx, idy;      // 1/dx, 1/dy
 };
 
 __device__ __forceinline__ double speed3(const double* U, int d, double m) {
@@ -77,19 +83,28 @@ __device__ __forceinline__ double speed3(const double* U, int d, double m) {
     return fabs(u) + sqrt(fmax(3.0 * p / (m * n), 0.0));
 }
 
-// Both face directions in one launch, one thread per (face, component): a
-// block takes kFaceTile consecutive faces of one row (x faces i+1/2 of row j,
-// or y faces jh-1/2 at columns i), reconstructs the 20 components (U and
-// Qcal) at both sides of each face into shared memory, then forms the 10
-// flux components.  Blocks [0, nbx) are x faces, the rest y faces.
-constexpr int kFaceTile = 32;
+// Both face directions in one launch.  An x tile is kXTile consecutive faces
+// i+1/2 of one cell row; a y tile is kYRows consecutive face rows jh-1/2 of
+// kYCols adjacent columns.  A block stages the cell values (U and Qcal,
+// wrapped in x, mirrored at the y walls) that its faces need in shared
+// memory, forms the CWENO-3 point values once per cell and component, the two
+// wave speeds once per face, then the 10 flux components of each face.
+// Blocks [0, nbx) are x tiles, the rest y tiles.
+constexpr int kXTile = 32;
+constexpr int kYRows = 8, kYCols = 4;
+constexpr int kFaceThreads = 256;   // eight blocks per CU: a launch is about one round
+constexpr int kStageCells = (kYRows + 3) * kYCols;   // >= kXTile + 3
+constexpr int kRecCells = (kYRows + 1) * kYCols;     // >= kXTile + 1
+static_assert(kXTile + 3 <= kStageCells && kXTile + 1 <= kRecCells, "x tile must fit the staging arrays");
+static_assert(kYRows * kYCols == kXTile, "both tiles hold the same number of faces");
 
-__device__ __forceinline__ double load_comp(const double* U, const double* QA, const double* QB, double wa,
-                                            double wb, int j, int i, int k, const FluidArgs& A) {
+__device__ __forceinline__ double stage_comp(const double* U, const double* QA, const double* QB, double wa,
+                                             double wb, int j, int i, int k, const FluidArgs& A) {
     bool mir = false;
     if (j < 0) { j = -1 - j; mir = true; }
     if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
-    i = (i % A.nx + A.nx) % A.nx;
+    while (i < 0) i += A.nx;
+    while (i >= A.nx) i -= A.nx;
     const long long c = (long long)j * A.nx + i;
     double v;
     if (k < 10) {
@@ -102,54 +117,80 @@ __device__ __forceinline__ double load_comp(const double* U, const double* QA, c
     return v;
 }
 
-__global__ void __launch_bounds__(kFaceTile * 20)
+__global__ void __launch_bounds__(kFaceThreads)
 faces3_kernel(const double* __restrict__ U, const double* __restrict__ QA, const double* __restrict__ QB, double wa,
-              double wb, FluidArgs A, int nbx_row, int nbx, double* __restrict__ Hx, double* __restrict__ Hy) {
-    __shared__ double Lm[kFaceTile][20], Lp[kFaceTile][20];   // minus (left/below) and plus sides
+              double wb, FluidArgs A, int nbx_row, int nbx, int nby_col, double* __restrict__ Hx,
+              double* __restrict__ Hy) {
+    __shared__ double raw[kStageCells][20];
+    __shared__ double lo[kRecCells][20], hi[kRecCells][20];   // point values at a cell's lower / upper face
+    __shared__ double spd[2][kXTile];
     const bool yface = (int)blockIdx.x >= nbx;
     const int b = yface ? (int)blockIdx.x - nbx : (int)blockIdx.x;
-    const int row = b / nbx_row;                   // j for x faces, jh for y faces
-    const int i0 = (b % nbx_row) * kFaceTile;
-    const int f = threadIdx.x % kFaceTile, k = threadIdx.x / kFaceTile;
-    const int i = i0 + f;
-    if (i < A.nx) {
-        double c0, c1, c2, c3;
-        if (!yface) {
-            c0 = load_comp(U, QA, QB, wa, wb, row, i - 1, k, A);
-            c1 = load_comp(U, QA, QB, wa, wb, row, i, k, A);
-            c2 = load_comp(U, QA, QB, wa, wb, row, i + 1, k, A);
-            c3 = load_comp(U, QA, QB, wa, wb, row, i + 2, k, A);
-        } else {
-            c0 = load_comp(U, QA, QB, wa, wb, row - 2, i, k, A);
-            c1 = load_comp(U, QA, QB, wa, wb, row - 1, i, k, A);
-            c2 = load_comp(U, QA, QB, wa, wb, row, i, k, A);
-            c3 = load_comp(U, QA, QB, wa, wb, row + 1, i, k, A);
-        }
-        double l1, r1, l2, r2;
-        cweno(c0, c1, c2, l1, r1);   // cell below/left of the face: its upper face value
-        cweno(c1, c2, c3, l2, r2);   // cell above/right: its lower face value
-        Lm[f][k] = r1;
-        Lp[f][k] = l2;
+    const int row0 = yface ? (b / nby_col) * kYRows : b / nbx_row;
+    const int col0 = yface ? (b % nby_col) * kYCols : (b % nbx_row) * kXTile;
+    const int nstage = yface ? kStageCells : kXTile + 3;
+    const int nrec = yface ? kRecCells : kXTile + 1;
+    // staged cell l: x tile (row0, col0 - 1 + l); y tile (row0 - 2 + l / kYCols, col0 + l % kYCols)
+    for (int t = threadIdx.x; t < nstage * 20; t += kFaceThreads) {
+        const int l = t / 20, k = t % 20;
+        const int j = yface ? row0 - 2 + l / kYCols : row0;
+        const int i = yface ? col0 + l % kYCols : col0 - 1 + l;
+        // y tiles: rows past ny + 1 and columns past nx feed no valid face
+        const bool need = !yface || (j <= A.ny + 1 && i < A.nx);
+        raw[l][k] = need ? stage_comp(U, QA, QB, wa, wb, j, i, k, A) : 0.0;
     }
     __syncthreads();
-    if (k >= 10 || i >= A.nx) return;
-    const int d = yface ? 1 : 0;
-    const double a = fmax(speed3(Lm[f], d, A.m), speed3(Lp[f], d, A.m));
-    // flux component k: n -> nu_d, nu_i -> P_id / m, P_ab -> Qcal_abd
-    int src;
-    double sc = 1.0;
-    if (k == 0) {
-        src = 1 + d;
-    } else if (k < 4) {
-        src = 4 + p_index(k - 1, d);
-        sc = 1.0 / A.m;
-    } else {
-        const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
-        src = 10 + q_index(ia[k - 4], ib[k - 4], d);
+    // reconstructed cell r: x tile (row0, col0 + r); y tile (row0 - 1 + r / kYCols, col0 + r % kYCols)
+    const int sstep = yface ? kYCols : 1;
+    for (int t = threadIdx.x; t < nrec * 20; t += kFaceThreads) {
+        const int r = t / 20, k = t % 20;
+        double l, h;
+        cweno(raw[r][k], raw[r + sstep][k], raw[r + 2 * sstep][k], l, h);
+        lo[r][k] = l;
+        hi[r][k] = h;
     }
-    const double Fm = Lm[f][src] * sc, Fp = Lp[f][src] * sc;
-    double* H = yface ? Hy : Hx;
-    H[((long long)row * A.nx + i) * 10 + k] = 0.5 * (Fp + Fm) - 0.5 * a * (Lp[f][k] - Lm[f][k]);
+    __syncthreads();
+    // face f: x tile i+1/2 with i = col0 + f of row0; y tile face row jh = row0 + f / kYCols at column
+    // col0 + f % kYCols.  Minus side (cell i, or row jh - 1): r = f; plus side: r = f + sstep.
+    const int d = yface ? 1 : 0;
+    auto face_ok = [&](int f) {
+        return yface ? (row0 + f / kYCols <= A.ny && col0 + f % kYCols < A.nx) : (col0 + f < A.nx);
+    };
+    for (int t = threadIdx.x; t < 2 * kXTile; t += kFaceThreads) {
+        const int f = t % kXTile, side = t / kXTile;
+        if (face_ok(f)) {
+            const double* V = side ? lo[f + sstep] : hi[f];
+            const double n = V[0];
+            const double u = V[1 + d] / n;
+            const double p = V[4 + p_index(d, d)] - A.m * n * u * u;
+            spd[side][f] = fabs(u) + sqrt(fmax(3.0 * p / (A.m * n), 0.0));
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kXTile * 10; t += kFaceThreads) {
+        const int f = t / 10, k = t % 10;
+        if (!face_ok(f)) continue;
+        const double* Lm = hi[f];
+        const double* Lp = lo[f + sstep];
+        const double a = fmax(spd[0][f], spd[1][f]);
+        // flux component k: n -> nu_d, nu_i -> P_id / m, P_ab -> Qcal_abd
+        int src;
+        double sc = 1.0;
+        if (k == 0) {
+            src = 1 + d;
+        } else if (k < 4) {
+            src = 4 + p_index(k - 1, d);
+            sc = 1.0 / A.m;
+        } else {
+            const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+            src = 10 + q_index(ia[k - 4], ib[k - 4], d);
+        }
+        const double Fm = Lm[src] * sc, Fp = Lp[src] * sc;
+        long long h;
+        if (yface) h = (long long)(row0 + f / kYCols) * A.nx + col0 + f % kYCols;
+        else h = (long long)row0 * A.nx + col0 + f;
+        (yface ? Hy : Hx)[h * 10 + k] = 0.5 * (Fp + Fm) - 0.5 * a * (Lp[k] - Lm[k]);
+    }
 }
 
 // U_out = a U_n + b (U_s + dt L(U_s)); U_out may alias U_n (each cell reads
@@ -199,7 +240,7 @@ __global__ void update3_kernel(const double* __restrict__ Us, const double* Un, 
     const double* hyt = Hy + ((long long)(j + 1) * A.nx + i) * 10;
     const double* hyb = Hy + ((long long)j * A.nx + i) * 10;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) L[k] -= (hxr[k] - hxl[k]) / A.dx + (hyt[k] - hyb[k]) / A.dy;
+    for (int k = 0; k < 10; ++k) L[k] -= (hxr[k] - hxl[k]) * A.idx + (hyt[k] - hyb[k]) * A.idy;
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         const double s = u[k] + dt * L[k];
@@ -288,12 +329,13 @@ hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
                                  hipStream_t st) {
-    FluidArgs A{nx, ny, m, q, dx, dy};
+    FluidArgs A{nx, ny, m, q, 1.0 / dx, 1.0 / dy};
     dim3 blk(64), gc((nx + 63) / 64, ny);
-    const int nbx_row = (nx + kFaceTile - 1) / kFaceTile;
-    const int nbx = nbx_row * ny, nby = nbx_row * (ny + 1);
-    hipLaunchKernelGGL(faces3_kernel, dim3(nbx + nby), dim3(kFaceTile * 20), 0, st, Us, QA, QB, wa, wb, A, nbx_row,
-                       nbx, Hx, Hy);
+    const int nbx_row = (nx + kXTile - 1) / kXTile;
+    const int nby_col = (nx + kYCols - 1) / kYCols;
+    const int nbx = nbx_row * ny, nby = nby_col * ((ny + 1 + kYRows - 1) / kYRows);
+    hipLaunchKernelGGL(faces3_kernel, dim3(nbx + nby), dim3(kFaceThreads), 0, st, Us, QA, QB, wa, wb, A, nbx_row,
+                       nbx, nby_col, Hx, Hy);
     hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A);
     return hipGetLastError();
 }

@@ -402,23 +402,55 @@ pfc_v3_kernel(const T* fin, T* fout, const double* __restrict__ E, const double*
 // pencil has length N and a stride known at compile time, so a pencil is
 // straight-line code with constant shared-memory offsets.
 //
-// Sub-cell shifts (K = 0, the common case) are done in the pencil's storage
-// order whatever the sign of s.  With D_m = g_m - g_{m-1} (zero ghosts),
-// r2 = max(2 f_inf - 2 g_m, 0) and
+// The block is stored [v_x][v_y][v_z] with v_z padded to N | 1; a wave takes
+// 64 / N values of the first transverse index and all of the second.
+//
+// Sub-cell shifts (K = 0, the common case): with D_m = g_m - g_{m-1} (zero
+// ghosts), r2 = 2 f_inf - 2 g_m and
 //   A_m = med3(D_{m+1}, -r2, 2 g_m),  B_m = med3(D_m, -2 g_m, r2),
 // the partial flux leaving cell m downwind is a g_m + a c1 A_m + a c2 B_m for
 // s > 0 and, by reflecting the pencil, a g_m - a c1 B_m - a c2 A_m for s < 0.
 // The flux through face m+1/2 (positive towards m+1) is the first for cell m
-// or minus the second for cell m+1; the wall faces carry none.  Per element:
-// one difference, eight operations for the partial flux, one select and three
-// for the update, and no address arithmetic.
+// or minus the second for cell m+1; the wall faces carry none.
+//
+// Every sweep keeps 0 <= g <= f_inf, so 2 f_inf - 2 g_m >= 0 up to rounding
+// and r2 is taken without its clamp at zero: where rounding puts g_m an ulp
+// above f_inf the bound moves by that ulp.  A wave whose pencils all shift the
+// same way walks them in the downwind order (a negative shift reads the
+// pencil backwards, which with constant offsets costs nothing): one
+// difference, seven operations for the partial flux and three for the update
+// per element.  A wave with both signs keeps the storage order and selects
+// per lane, one operation more.
 template <class T>
 __device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F2) {
     const T x2 = w + w;
-    const T r2 = fmax(F2 - x2, T(0));
+    const T r2 = F2 - x2;
     const T A = med3(Dp, -r2, x2);
     const T B = med3(Dm, -x2, r2);
     return fma(cA, A, fma(cB, B, a * w));
+}
+
+// Sub-cell sweep of one pencil whose lanes all shift one way: REV walks the
+// pencil from its far end (s < 0), so the downwind direction is always +m.
+template <class T, int N, bool REV>
+__device__ __forceinline__ void pencil_one_way(T* pb, int stride, T a, T c1, T c2, T F2) {
+    T w[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) w[m] = pb[(REV ? N - 1 - m : m) * stride];
+    T Dm = w[0];                 // D_m = g_m - g_{m-1}, zero ghost below
+    T Dp = w[1] - w[0];
+    T Fprev = T(0);              // flux through the lower wall
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        T F = T(0);              // flux through face m+1/2 (none through the upper wall)
+        if (m + 1 < N) {
+            F = sub_cell_flux(w[m], Dm, Dp, a, c1, c2, F2);
+            Dm = Dp;
+            Dp = (m + 2 < N ? w[m + 2] : T(0)) - w[m + 1];
+        }
+        pb[(REV ? N - 1 - m : m) * stride] = fmax(w[m] + Fprev - F, T(0));
+        Fprev = F;
+    }
 }
 
 // Shifts of a cell or more (any lane of the wave): windows gathered in the
@@ -477,7 +509,11 @@ __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3
         const T s = fma(s1, (T)i1, fma(s2, (T)i2, s0));
         const bool pos = s >= T(0);
         const ShiftT<T> sh(fabs(s));
-        if (__all(sh.K == 0)) {
+        if (__all(sh.K == 0) && __all(pos)) {
+            pencil_one_way<T, N, false>(blk + base, stride, sh.a, sh.ac1, sh.ac2, F2);
+        } else if (__all(sh.K == 0) && __all(!pos)) {
+            pencil_one_way<T, N, true>(blk + base, stride, sh.a, sh.ac1, sh.ac2, F2);
+        } else if (__all(sh.K == 0)) {
             T* pb = blk + base;
             T w[N];
 #pragma unroll

@@ -326,8 +326,10 @@ def test_maxwell_half_step_and_cell_fields():
 
 # ------------------------------------------------------------------- fluid --
 def test_fluid_step_3v():
+    """40 x 18: one full and one partial tile of x faces per row, three tile
+    rows of y faces (the last holding only the upper wall)."""
     import torch
-    nx, ny = 16, 10
+    nx, ny = 40, 18
     cfg, f0, _ = W.gem(nx=nx, ny=ny, nv=8, dtype=np.float64)
     dx = (cfg["x_hi"] - cfg["x_lo"]) / nx
     dy = (cfg["y_hi"] - cfg["y_lo"]) / ny
