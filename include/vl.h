@@ -212,6 +212,38 @@ vl_status vl_step(vl_ctx* ctx, vl_state* st, double dt, vl_stream stream);
  * VL_CLOSURE_KINETIC) and sets closure_fallback[s].  No host synchronisation:
  * the decision is taken on the device. */
 
+/* ---- Ten-moment multi-fluid step with a heat-flux closure (2X3V) ----------
+ * The fluid solver of Sec. 2.3 run on its own, without a distribution
+ * function (the paper's gradient-closure fluid model).  One step:
+ * Maxwell half step with j^t = sum_s q_s (n u)_s taken from the fluid states;
+ * per species one SSP-RK3 step of Eqs. 2-4 with the fields at t, t+1
+ * (extrapolated, 2 X^{t+1/2} - X^t) and t+1/2 as in vl_step, whose third
+ * moment at every stage is a closure of that stage's state; Maxwell half step
+ * with j^{t+1}.
+ *   VL_FLUID_GRADIENT  zero heat flux in the faces' third moment
+ *                      (Qcal = sym(u P) - 2 m n uuu) and Eq. 5 as a source of
+ *                      P: -div Q = (chi/k0) n v_t lap T, chi = 2 sqrt(2/pi),
+ *                      k0 = 1/d_s, d_s = sqrt(m/q^2) (reference density 1),
+ *                      v_t = sqrt(tr T / (3 m)), lap T by central second
+ *                      differences (x periodic, y walls mirrored);
+ *   VL_FLUID_MLP       the network's heat flux at every stage (as the learned
+ *                      closure of vl_step, without the judge: there is no
+ *                      kinetic reference), from that stage's state and B.
+ * U[s] ([cells][10], FP64) and fields (the Yee array) are advanced in place;
+ * work: vl_fluid_closure_work_size doubles; mlp_params (device, VL_MLP_NPARAM
+ * floats) only for VL_FLUID_MLP.  Errors: VL_ENOTSUP unless the context is
+ * 2X3V; VL_EINVAL for a null buffer, an unknown closure or dt not finite and
+ * > 0; VL_EALIAS if U[0] == U[1]. */
+enum { VL_FLUID_GRADIENT = 0, VL_FLUID_MLP = 1 };
+typedef struct {
+    double* U[VL_MAX_SPECIES];
+    double* fields;
+    double* work;
+    const float* mlp_params;
+} vl_fluid_state;
+size_t vl_fluid_closure_work_size(const vl_ctx* ctx);   /* 0 unless 2X3V */
+vl_status vl_fluid_closure_step(vl_ctx* ctx, vl_fluid_state* st, int32_t closure, double dt, vl_stream stream);
+
 /* ---- Learned heat-flux closure (a network of this library, not of the paper;
  * the paper's fluid-only closure is the temperature-gradient one, Eq. 5).
  * Network: features (64) -> tanh 64 -> tanh 64 -> tanh 64 -> 16 outputs, of

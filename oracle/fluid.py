@@ -170,6 +170,19 @@ def rk3_3v_stagewise(U, qcal_of, fields_t, fields_t1, fields_th, q, m, dx, dy, d
     return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs_3v(U2, qcal_of(U2, fields_th[1]), *fields_th, q, m, dx, dy))
 
 
+def rk3_3v_closure(U, qcal_of, source_of, fields_t, fields_t1, fields_th, q, m, dx, dy, dt):
+    """SSP-RK3 in which every stage takes its third moment from
+    qcal_of(U_stage, B_stage) and adds source_of(U_stage) ([ny, nx, 10], or
+    None for no source) to L: the fluid model run with a heat-flux closure
+    (Sec. 2.3) instead of the kinetic third moment."""
+    def L(V, fl):
+        r = rhs_3v(V, qcal_of(V, fl[1]), *fl, q, m, dx, dy)
+        return r if source_of is None else r + source_of(V)
+    U1 = U + dt * L(U, fields_t)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * L(U1, fields_t1))
+    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * L(U2, fields_th))
+
+
 # ------------------------------------------------------- 1V (1X1V) --------
 def rhs_1v(U, Qc, E, q, m, dx):
     """L(U) on U[nx, 3] = (n, nu, P) with Q-calligraphic Qc[nx], E[nx]; periodic."""

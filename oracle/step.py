@@ -128,6 +128,49 @@ def step_2x3v(st, cfg, dt):
     return out
 
 
+def fluid_step_2x3v(st, cfg, dt, closure, params=None):
+    """The ten-moment multi-fluid model on its own (Sec. 2.3): st =
+    dict(U=[U_s], F=Yee).  The field half steps and stage fields are those of
+    step_2x3v with the currents q n u of the fluid states; every RK stage
+    takes its third moment from a closure of the stage state:
+    'gradient': zero heat flux in Q-calligraphic and Eq. 5 as the source
+    -div Q of the second-moment equation; 'mlp': the network's heat flux
+    (params) from the stage state and magnetic field."""
+    nx, ny = cfg["nx"], cfg["ny"]
+    dx = (cfg["x_hi"] - cfg["x_lo"]) / nx
+    dy = (cfg["y_hi"] - cfg["y_lo"]) / ny
+    c = cfg["c"]
+    species = cfg["species"]
+    F_t = st["F"]
+    j_t = sum(sp["q"] * st["U"][k][..., 1:4] for k, sp in enumerate(species))
+    F = fields.maxwell_half_step(F_t, j_t, dt, c, dx, dy)
+    E_h, B_h = fields.cell_centred(F)
+    E_0, B_0 = fields.cell_centred(F_t)
+    fields_t1 = (2.0 * E_h - E_0, 2.0 * B_h - B_0)
+    out = {"U": []}
+    for k, sp in enumerate(species):
+        q, m = sp["q"], sp["m"]
+        if closure == "gradient":
+            def qcal_of(V, Bs, m=m):
+                return mlp.qcal_from_closure(V, np.zeros(V.shape[:-1] + (10,)), 0.0, m)
+
+            def source_of(V, m=m, q=q):
+                S = np.zeros(V.shape)
+                S[..., 4:10] = -mlp.gradient_closure_divergence(V, m, q, dx, dy)
+                return S
+        elif closure == "mlp":
+            def qcal_of(V, Bs, m=m, k=k):
+                return mlp.closure_qcal(V, m, k, params, Bs)
+            source_of = None
+        else:
+            raise ValueError(closure)
+        out["U"].append(fluid.rk3_3v_closure(st["U"][k], qcal_of, source_of, (E_0, B_0), fields_t1, (E_h, B_h),
+                                             q, m, dx, dy, dt))
+    j_t1 = sum(sp["q"] * out["U"][k][..., 1:4] for k, sp in enumerate(species))
+    out["F"] = fields.maxwell_half_step(F, j_t1, dt, c, dx, dy)
+    return out
+
+
 def energy_2x3v(st, cfg):
     """Total energy: sum_s tr(P_s)/2 over cells (kinetic + thermal, Sec. 3.2's
     energy split summed) plus the Yee field energy."""

@@ -99,14 +99,15 @@ __global__ void yee_curl_e_kernel(YeeView F, double coef, double dx, double dy) 
 // E += coef c^2 (curl B - j); j = sum_s q_s M1_s at cell centres averaged to
 // the E positions (j_y on a wall face is 0).
 struct Currents {
-    const double* mom[2];
+    const double* mom[2];   // per species: n u_x, n u_y, n u_z at offsets 1..3 of each cell's record
     double q[2];
     int ns;
+    int stride;             // doubles per cell record (20: raw moments, 10: fluid state)
 };
 
 __device__ __forceinline__ double jc(const Currents& J, long long cell, int d) {
     double s = 0.0;
-    for (int k = 0; k < J.ns; ++k) s += J.q[k] * J.mom[k][cell * 20 + 1 + d];
+    for (int k = 0; k < J.ns; ++k) s += J.q[k] * J.mom[k][cell * J.stride + 1 + d];
     return s;
 }
 
@@ -157,10 +158,11 @@ __global__ void axpby_kernel(const double* __restrict__ x, const double* __restr
 }
 
 hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
-                               double dt, double c, double dx, double dy, hipStream_t st) {
+                               double dt, double c, double dx, double dy, hipStream_t st, int mstride) {
     YeeView F = yee_view(yee, nx, ny);
     Currents J;
     J.ns = ns;
+    J.stride = mstride;
     for (int k = 0; k < 2; ++k) {
         J.mom[k] = k < ns ? mom[k] : nullptr;
         J.q[k] = k < ns ? q[k] : 0.0;

@@ -193,12 +193,39 @@ faces3_kernel(const double* __restrict__ U, const double* __restrict__ QA, const
     }
 }
 
+// Temperature tensor T = (P - m n u u) / n of a fluid record (PAIRS order).
+__device__ __forceinline__ void temperature6(const double* V, double m, double* T) {
+    const double n = V[0];
+    const double u[3] = {V[1] / n, V[2] / n, V[3] / n};
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) T[k] = (V[4 + k] - m * n * u[pa[k]] * u[pb[k]]) / n;
+}
+
+// Temperature of cell (j, i) with x periodic and the y walls mirrored (the
+// mirrored record has n u_y, P_xy, P_yz negated, so T_xy and T_yz flip).
+__device__ __forceinline__ void temperature_at(const double* __restrict__ U, int j, int i, const FluidArgs& A,
+                                               double* T) {
+    bool mir = false;
+    if (j < 0) { j = -1 - j; mir = true; }
+    if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
+    if (i < 0) i += A.nx;
+    if (i >= A.nx) i -= A.nx;
+    const long long c = (long long)j * A.nx + i;
+    double V[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) V[k] = U[c * 10 + k] * (mir ? par_u(k) : 1.0);
+    temperature6(V, A.m, T);
+}
+
 // U_out = a U_n + b (U_s + dt L(U_s)); U_out may alias U_n (each cell reads
-// only its own U_n entry) but not U_s.
+// only its own U_n entry) but not U_s.  gchi != 0 adds the temperature-
+// gradient closure of Eq. 5 as a source of the second moment:
+// -div Q = gchi n v_t lap T, gchi = chi / k0, lap by central differences.
 __global__ void update3_kernel(const double* __restrict__ Us, const double* Un, double* Uout,
                                const double* __restrict__ Hx, const double* __restrict__ Hy,
                                const double* __restrict__ E, const double* __restrict__ B, double a, double b,
-                               double dt, FluidArgs A) {
+                               double dt, FluidArgs A, double gchi) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= A.nx) return;
@@ -241,10 +268,45 @@ __global__ void update3_kernel(const double* __restrict__ Us, const double* Un, 
     const double* hyb = Hy + ((long long)j * A.nx + i) * 10;
 #pragma unroll
     for (int k = 0; k < 10; ++k) L[k] -= (hxr[k] - hxl[k]) * A.idx + (hyt[k] - hyb[k]) * A.idy;
+    if (gchi != 0.0) {
+        double Tc[6], Te[6], Tw[6], Tn[6], Ts[6];
+        temperature6(u, A.m, Tc);
+        temperature_at(Us, j, i + 1, A, Te);
+        temperature_at(Us, j, i - 1, A, Tw);
+        temperature_at(Us, j + 1, i, A, Tn);
+        temperature_at(Us, j - 1, i, A, Ts);
+        const double vt = sqrt((Tc[0] + Tc[3] + Tc[5]) / (3.0 * A.m));
+        const double w = gchi * (u[0] * vt);
+        const double ix2 = A.idx * A.idx, iy2 = A.idy * A.idy;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            L[4 + k] += w * (((Te[k] - 2.0 * Tc[k]) + Tw[k]) * ix2 + ((Tn[k] - 2.0 * Tc[k]) + Ts[k]) * iy2);
+    }
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
         const double s = u[k] + dt * L[k];
         Uout[c * 10 + k] = (a != 0.0 ? a * Un[c * 10 + k] : 0.0) + b * s;
+    }
+}
+
+// Third moment of a fluid record with zero heat flux:
+// Qcal_abc = u_a P_bc + u_b P_ac + u_c P_ab - 2 m n u_a u_b u_c, written at
+// offsets 10..19 of 20-double records (the layout the face kernel reads).
+__global__ void qcal_q0_kernel(const double* __restrict__ U, long long cells, double m, double* __restrict__ qc) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double n = U[c * 10];
+    const double u[3] = {U[c * 10 + 1] / n, U[c * 10 + 2] / n, U[c * 10 + 3] / n};
+    double P[3][3];
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) P[pa[k]][pb[k]] = P[pb[k]][pa[k]] = U[c * 10 + 4 + k];
+    const int ta[10] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 2}, tb[10] = {0, 0, 0, 1, 1, 2, 1, 1, 2, 2},
+              tc[10] = {0, 1, 2, 1, 2, 2, 1, 2, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        const int x = ta[k], y = tb[k], z = tc[k];
+        qc[c * 20 + 10 + k] = (u[x] * P[y][z] + u[y] * P[x][z] + u[z] * P[x][y]) - 2.0 * m * n * u[x] * u[y] * u[z];
     }
 }
 
@@ -328,7 +390,7 @@ hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom
 hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
-                                 hipStream_t st) {
+                                 hipStream_t st, double gchi) {
     FluidArgs A{nx, ny, m, q, 1.0 / dx, 1.0 / dy};
     dim3 blk(64), gc((nx + 63) / 64, ny);
     const int nbx_row = (nx + kXTile - 1) / kXTile;
@@ -336,7 +398,12 @@ hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo,
     const int nbx = nbx_row * ny, nby = nby_col * ((ny + 1 + kYRows - 1) / kYRows);
     hipLaunchKernelGGL(faces3_kernel, dim3(nbx + nby), dim3(kFaceThreads), 0, st, Us, QA, QB, wa, wb, A, nbx_row,
                        nbx, nby_col, Hx, Hy);
-    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A);
+    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A, gchi);
+    return hipGetLastError();
+}
+
+hipError_t launch_qcal_q0(const double* U, long long cells, double m, double* qc, hipStream_t st) {
+    hipLaunchKernelGGL(qcal_q0_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, U, cells, m, qc);
     return hipGetLastError();
 }
 

@@ -477,7 +477,7 @@ __global__ void mlp_qcal_kernel(const double* __restrict__ U, const double* __re
                                 long long cells, double m, double* __restrict__ qc) {
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
-    if (*fallback) {
+    if (fallback && *fallback) {
 #pragma unroll
         for (int k = 0; k < 10; ++k)
             qc[c * 20 + 10 + k] = wa * QA[c * 20 + 10 + k] + (wb != 0.0 ? wb * QB[c * 20 + 10 + k] : 0.0);

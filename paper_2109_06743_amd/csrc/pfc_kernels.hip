@@ -693,7 +693,7 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
 // x cells per thread (FP32: 8 keeps 4 waves/SIMD; FP64 registers allow 4) and
 // doubled-pencil positions per segment
 template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
-constexpr int kXySeg = 32;
+constexpr int kXySeg = 64;
 template <class T>
 long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz) {
     const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;

@@ -153,6 +153,13 @@ size_t mlp_step_doubles(const vl_config& c) {
     return 45 * cells + vl::mlp_judge_part_doubles() + 2;
 }
 
+// Fluid-only closure step: the step's field arrays, the fluid scratch, the
+// third moment (20 per cell) and the network's scratch (25 per cell + 2).
+size_t fluid_closure_doubles(const vl_config& c) {
+    const size_t cells = (size_t)c.nx * c.ny;
+    return yee_doubles(c) + 18 * cells + fluid_doubles(c) + 20 * cells + 25 * cells + 2;
+}
+
 size_t step_doubles(const vl_config& c) {
     const size_t cells = (size_t)c.nx * c.ny;
     if (c.dim_v == 3) return yee_doubles(c) + 18 * cells + fluid_doubles(c) + mlp_step_doubles(c);
@@ -313,6 +320,76 @@ vl_status fluid_step_mlp(vl_ctx* ctx, int s, const vl_state* S, const double* E_
         VL_HIP(vl::launch_fluid_stage_3v(G[k].Us, G[k].Un, G[k].Uo, qc, qc, 1.0, 0.0, G[k].E, G[k].B, G[k].a, G[k].b,
                                          dt, c.nx, c.ny, sp.q, sp.m, dx_of(c), dy_of(c), Hx, Hy, st));
     }
+    return VL_OK;
+}
+
+// Ten-moment multi-fluid step without a distribution function (the fluid
+// solver of Sec. 2.3 run on its own): the field half steps of the Vlasov step
+// with the currents q n u of the fluid states, and per species the SSP-RK3
+// step whose third moment at every stage comes from a closure of that
+// stage's state: zero heat flux with the temperature-gradient closure of
+// Eq. 5 as a source of P, or the heat flux of the network.
+vl_status fluid_closure_step_impl(vl_ctx* ctx, const vl_fluid_state* S, int closure, double dt, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const int ns = c.nspecies;
+    const long long cells = ctx->cells;
+    const double q[2] = {c.sp[0].q, ns > 1 ? c.sp[1].q : 0.0};
+    const size_t ny1 = yee_doubles(c);
+    double* yee_t = S->work;
+    double* E_t = yee_t + ny1;
+    double* B_t = E_t + 3 * cells;
+    double* E_h = B_t + 3 * cells;
+    double* B_h = E_h + 3 * cells;
+    double* E_1 = B_h + 3 * cells;
+    double* B_1 = E_1 + 3 * cells;
+    double* fwork = B_1 + 3 * cells;
+    double* qc = fwork + fluid_doubles(c);
+    double* mw = qc + 20 * cells;
+    mw += ((uintptr_t)mw & 15u) ? 1 : 0;                 // network outputs are stored as 16-byte vectors
+    float* y = (float*)mw;
+    unsigned short* x = (unsigned short*)(mw + 8 * cells);
+    double* scale = mw + 24 * cells;
+    const double* Uc[2] = {S->U[0], ns > 1 ? S->U[1] : nullptr};
+    {
+        Timed tm(ctx, VL_T_FIELDS, st);
+        VL_HIP(hipMemcpyAsync(yee_t, S->fields, ny1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+        VL_HIP(vl::launch_cell_fields(yee_t, c.nx, c.ny, E_t, B_t, st));
+        VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, Uc, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 10));
+        VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, st));
+        VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 3 * cells, st));
+        VL_HIP(vl::launch_axpby(B_h, B_t, 2.0, -1.0, B_1, 3 * cells, st));
+    }
+    for (int s = 0; s < ns; ++s) {
+        const vl_species& sp = c.sp[s];
+        Timed tm(ctx, VL_T_FLUID, st);
+        double* U = S->U[s];
+        double* U1 = fwork;
+        double* U2 = U1 + cells * 10;
+        double* Hx = U2 + cells * 10;
+        double* Hy = Hx + cells * 10;
+        struct Stage { const double* Us; double* Uo; const double* E; const double* B; double a, b; };
+        const Stage G[3] = {
+            {U, U1, E_t, B_t, 0.0, 1.0},
+            {U1, U2, E_1, B_1, 0.75, 0.25},
+            {U2, U, E_h, B_h, 1.0 / 3.0, 2.0 / 3.0},
+        };
+        // chi / k0 with chi = 2 sqrt(2/pi), k0 = 1/d_s, d_s = sqrt(m / q^2)
+        const double gchi = 2.0 * sqrt(2.0 / 3.14159265358979323846) * sqrt(sp.m / (sp.q * sp.q));
+        for (int k = 0; k < 3; ++k) {
+            if (closure == VL_FLUID_GRADIENT) {
+                VL_HIP(vl::launch_qcal_q0(G[k].Us, cells, sp.m, qc, st));
+            } else {
+                VL_HIP(vl::launch_mlp_features(G[k].Us, 10, G[k].B, c.nx, c.ny, sp.m, s, x, scale, st));
+                VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, cells, y, st));
+                VL_HIP(vl::launch_mlp_qcal(G[k].Us, scale, y, nullptr, qc, qc, 1.0, 0.0, cells, sp.m, qc, st));
+            }
+            VL_HIP(vl::launch_fluid_stage_3v(G[k].Us, U, G[k].Uo, qc, qc, 1.0, 0.0, G[k].E, G[k].B, G[k].a, G[k].b,
+                                             dt, c.nx, c.ny, sp.q, sp.m, dx_of(c), dy_of(c), Hx, Hy, st,
+                                             closure == VL_FLUID_GRADIENT ? gchi : 0.0));
+        }
+    }
+    Timed tm(ctx, VL_T_FIELDS, st);
+    VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, Uc, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 10));
     return VL_OK;
 }
 
@@ -676,6 +753,26 @@ vl_status vl_step(vl_ctx* ctx, vl_state* S, double dt, vl_stream stream) {
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     return DISPATCH(ctx, step_typed<float>(ctx, S, dt, st), step_typed<double>(ctx, S, dt, st));
+}
+
+size_t vl_fluid_closure_work_size(const vl_ctx* ctx) {
+    return (ctx && ctx->cfg.dim_x == 2 && ctx->cfg.dim_v == 3) ? fluid_closure_doubles(ctx->cfg) : 0;
+}
+
+vl_status vl_fluid_closure_step(vl_ctx* ctx, vl_fluid_state* S, int32_t closure, double dt, vl_stream stream) {
+    if (!ctx || !S) return VL_EINVAL;
+    const vl_config& c = ctx->cfg;
+    if (c.dim_x != 2 || c.dim_v != 3) return fail(ctx, VL_ENOTSUP, "the ten-moment fluid step is 2X3V");
+    if (closure != VL_FLUID_GRADIENT && closure != VL_FLUID_MLP) return fail(ctx, VL_EINVAL, "unknown closure");
+    if (!finite_pos(dt)) return fail(ctx, VL_EINVAL, "dt must be finite and > 0");
+    if (!S->fields || !S->work) return fail(ctx, VL_EINVAL, "null fields/work");
+    for (int s = 0; s < c.nspecies; ++s)
+        if (!S->U[s]) return fail(ctx, VL_EINVAL, "null U[%d]", s);
+    if (c.nspecies > 1 && S->U[0] == S->U[1]) return fail(ctx, VL_EALIAS, "U[0] and U[1] alias");
+    if (closure == VL_FLUID_MLP && !S->mlp_params) return fail(ctx, VL_EINVAL, "the network closure needs mlp_params");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    return fluid_closure_step_impl(ctx, S, closure, dt, (hipStream_t)stream);
 }
 
 vl_status vl_mlp_features(vl_ctx* ctx, int32_t s, const double* mom, int32_t stride, const double* B, uint16_t* x,

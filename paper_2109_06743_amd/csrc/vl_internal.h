@@ -73,8 +73,10 @@ hipError_t launch_fit1(const T* fin, T* fout, const double* mom_pre, double* U, 
                        hipStream_t st);
 
 hipError_t launch_poisson(const double* mom, int N, double L, double q, double* ab, double* E, hipStream_t st);
+// mom[s]: per-cell records of mstride doubles holding n u at offsets 1..3
+// (raw moments: 20; fluid state: 10).
 hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
-                               double dt, double c, double dx, double dy, hipStream_t st);
+                               double dt, double c, double dx, double dy, hipStream_t st, int mstride = 20);
 hipError_t launch_cell_fields(const double* yee, int nx, int ny, double* E, double* B, hipStream_t st);
 hipError_t launch_field_energy(const double* fields, int dim_x, int nx, int ny, double c, double dX, double* part,
                                double* out, hipStream_t st);
@@ -94,7 +96,9 @@ hipError_t launch_fluid_rk3_1v(double* U, const double* mom_t, const double* mom
 hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
-                                 hipStream_t st);
+                                 hipStream_t st, double gchi = 0.0);
+// Qcal of fluid records U[cells][10] with zero heat flux, into qc[cells][20] (offsets 10..19).
+hipError_t launch_qcal_q0(const double* U, long long cells, double m, double* qc, hipStream_t st);
 
 // learned heat-flux closure (mlp_kernels.hip)
 constexpr int kMlpParams = 13520;

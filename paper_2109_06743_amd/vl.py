@@ -21,8 +21,9 @@ EXPORTS = ["vl_create", "vl_destroy", "vl_pfc_advect_x", "vl_pfc_advect_v", "vl_
            "vl_fluid_step", "vl_step_work_size", "vl_step", "vl_mass_energy", "vl_sync", "vl_status_str",
            "vl_last_error", "vl_version", "vl_timing_enable", "vl_timing_read", "vl_mlp_features",
            "vl_mlp_targets", "vl_mlp_forward", "vl_mlp_work_size", "vl_mlp_gradient", "vl_mlp_train_step",
-           "vl_field_energy"]
+           "vl_field_energy", "vl_fluid_closure_work_size", "vl_fluid_closure_step"]
 VL_CLOSURE_KINETIC, VL_CLOSURE_MLP = 0, 1
+VL_FLUID_GRADIENT, VL_FLUID_MLP = 0, 1
 MLP_IN, MLP_OUT, MLP_OUT_PAD, MLP_NPARAM = 64, 10, 16, 13520
 TIMING_CATEGORIES = ["max", "pfc_x", "pfc_y", "pfc_v", "moments", "fluid", "fit", "fields", "copy"]
 
@@ -53,6 +54,11 @@ class State(ctypes.Structure):
                 ("U", ctypes.c_void_p * MAX_SPECIES), ("fields", ctypes.c_void_p), ("work", ctypes.c_void_p),
                 ("counters", ctypes.c_void_p), ("f_max_valid", ctypes.c_int32), ("mlp_params", ctypes.c_void_p),
                 ("closure_fallback", ctypes.c_void_p), ("closure_err", ctypes.c_void_p)]
+
+
+class FluidClosureState(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_void_p * MAX_SPECIES), ("fields", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("mlp_params", ctypes.c_void_p)]
 
 
 _lib = None
@@ -89,6 +95,8 @@ def load():
         "vl_fluid_step": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, vp, vp], i32),
         "vl_step_work_size": ([vp], sz),
         "vl_step": ([vp, ctypes.POINTER(State), d, vp], i32),
+        "vl_fluid_closure_work_size": ([vp], sz),
+        "vl_fluid_closure_step": ([vp, ctypes.POINTER(FluidClosureState), i32, d, vp], i32),
         "vl_mass_energy": ([vp, i32, vp, vp, vp, vp], i32),
         "vl_field_energy": ([vp, vp, vp, vp], i32),
         "vl_sync": ([vp, vp], i32),
@@ -224,6 +232,16 @@ class Context:
     def step(self, state, dt, stream=None):
         self._check(self.lib.vl_step(self.h, ctypes.byref(state.c), float(dt), _stream(stream)))
 
+    def fluid_closure_work_size(self):
+        return int(self.lib.vl_fluid_closure_work_size(self.h))
+
+    def fluid_closure_step(self, state, dt, closure="gradient", stream=None):
+        """One ten-moment multi-fluid step (vl_fluid_closure_step) of a
+        FluidState with the Eq. 5 gradient closure or the network."""
+        kind = {"gradient": VL_FLUID_GRADIENT, "mlp": VL_FLUID_MLP}[closure]
+        self._check(self.lib.vl_fluid_closure_step(self.h, ctypes.byref(state.c), kind, float(dt),
+                                                   _stream(stream)))
+
     def mass_energy(self, s, f, mom, out, stream=None):
         self._check(self.lib.vl_mass_energy(self.h, s, _ptr(f), _ptr(mom), _ptr(out), _stream(stream)))
 
@@ -337,6 +355,28 @@ def yee_pack(F):
     """Concatenate Yee components (Ex, Ey, Ez, Bx, By, Bz) in the library's order."""
     return np.concatenate([np.asarray(getattr(F, k), dtype=np.float64).reshape(-1)
                            for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")])
+
+
+class FluidState:
+    """Device buffers of vl_fluid_closure_step: the fluid states U[s]
+    ([cells][10], FP64), the Yee array, scratch, and the network parameters
+    for the network closure."""
+
+    def __init__(self, ctx, U_list, fields, mlp_params=None, device="cuda"):
+        import torch
+        ns = ctx.cfg.nspecies
+        self.U = [torch.as_tensor(np.asarray(u, dtype=np.float64).reshape(-1)).to(device) for u in U_list[:ns]]
+        self.fields = torch.as_tensor(np.asarray(fields, dtype=np.float64).reshape(-1)).to(device)
+        self.work = torch.zeros(max(ctx.fluid_closure_work_size(), 1), dtype=torch.float64, device=device)
+        c = FluidClosureState()
+        for k in range(ns):
+            c.U[k] = self.U[k].data_ptr()
+        c.fields = self.fields.data_ptr()
+        c.work = self.work.data_ptr()
+        if mlp_params is not None:
+            self.mlp_params = torch.as_tensor(mlp_params, device=device).to(torch.float32).contiguous()
+            c.mlp_params = self.mlp_params.data_ptr()
+        self.c = c
 
 
 def yee_unpack(arr, nx, ny):

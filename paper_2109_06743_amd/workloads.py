@@ -71,9 +71,8 @@ class Yee0:
         self.Bx = np.zeros((ny + 1, nx)); self.By = np.zeros((ny, nx)); self.Bz = np.zeros((ny + 1, nx))
 
 
-def gem(nx=256, ny=128, nv=16, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5.0, psi0=0.1,
-        ve_max=12.5, vi_max=5.0, dt=0.003, steps=200, fit=True, dtype=np.float32):
-    """GEM reconnection set-up (Sec. 3.3) on an nx x ny x nv^3 grid."""
+def _gem_setup(nx, ny, nv, mass_ratio, c, lam, nb, Ti_Te, psi0, ve_max, vi_max, dt, steps, fit):
+    """GEM configuration, density, per-species (u_z, T) profiles and Yee fields."""
     Lx, Ly = 8 * math.pi, 4 * math.pi
     Te = 0.5 / (1.0 + Ti_Te)
     Ti = Ti_Te * Te
@@ -91,10 +90,6 @@ def gem(nx=256, ny=128, nv=16, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5
           - (1.0 / lam) / np.cosh(Y / lam) ** 2)
     uzi = jz * Ti / (n * (Ti + Te))
     uze = -uzi * Te / Ti
-    f = []
-    for s, (uz, T) in zip(sp, ((uze, Te), (uzi, Ti))):
-        v = [_centres(s["v_lo"][d], s["v_hi"][d], s["nv"][d]) for d in range(3)]
-        f.append(_maxwellian_block(n, uz, T, s["m"], v).astype(dtype))
     F = Yee0(nx, ny)
     dx, dy = Lx / nx, Ly / ny
     xc = -Lx / 2 + (np.arange(nx) + 0.5) * dx      # integer i
@@ -105,7 +100,36 @@ def gem(nx=256, ny=128, nv=16, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5
     F.Bx = np.tanh(YF / lam) - psi0 * (math.pi / Ly) * np.cos(2 * math.pi * XF / Lx) * np.sin(math.pi * YF / Ly)
     XB, YB = np.meshgrid(xf, yc)
     F.By = psi0 * (2 * math.pi / Lx) * np.sin(2 * math.pi * XB / Lx) * np.cos(math.pi * YB / Ly)
+    return cfg, n, ((uze, Te), (uzi, Ti)), F
+
+
+def gem(nx=256, ny=128, nv=16, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5.0, psi0=0.1,
+        ve_max=12.5, vi_max=5.0, dt=0.003, steps=200, fit=True, dtype=np.float32):
+    """GEM reconnection set-up (Sec. 3.3) on an nx x ny x nv^3 grid."""
+    cfg, n, prof, F = _gem_setup(nx, ny, nv, mass_ratio, c, lam, nb, Ti_Te, psi0, ve_max, vi_max, dt, steps, fit)
+    f = []
+    for s, (uz, T) in zip(cfg["species"], prof):
+        v = [_centres(s["v_lo"][d], s["v_hi"][d], s["nv"][d]) for d in range(3)]
+        f.append(_maxwellian_block(n, uz, T, s["m"], v).astype(dtype))
     return cfg, f, F
+
+
+def gem_fluid(nx=256, ny=128, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5.0, psi0=0.1, dt=0.003,
+              steps=200):
+    """The GEM set-up for the ten-moment fluid model alone: per species the
+    fluid record U[ny, nx, 10] = (n, n u, P) of the drifting Maxwellian,
+    P = n T I + m n u u (u along z), and the same Yee fields."""
+    cfg, n, prof, F = _gem_setup(nx, ny, 4, mass_ratio, c, lam, nb, Ti_Te, psi0, 12.5, 5.0, dt, steps, False)
+    cfg["name"] = f"gem fluid {nx}x{ny} mi/me={mass_ratio:g}"
+    U = []
+    for s, (uz, T) in zip(cfg["species"], prof):
+        V = np.zeros((ny, nx, 10))
+        V[..., 0] = n
+        V[..., 3] = n * uz
+        V[..., 4] = V[..., 7] = n * T
+        V[..., 9] = n * T + s["m"] * n * uz * uz
+        U.append(V)
+    return cfg, U, F
 
 
 def tail(nx=1024, ny=512, nv=12, mass_ratio=100.0, c=30.0, lam=0.6, Ti_Te=3.0, Bg=0.1, noise=1e-4,

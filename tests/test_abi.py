@@ -93,5 +93,25 @@ def test_entry_points_reject_bad_arguments_before_device_use(lib):
     s = vl.State()
     assert lib.vl_step(h, ctypes.byref(s), 0.1, None) == 1
     assert lib.vl_step(h, None, 0.1, None) == 1
+    fs = vl.FluidClosureState()
+    assert lib.vl_fluid_closure_step(h, ctypes.byref(fs), 0, 0.1, None) == 3    # 1X1V: no ten-moment fluid
+    assert lib.vl_fluid_closure_work_size(h) == 0
     assert b"" != lib.vl_last_error(h)
+    lib.vl_destroy(h)
+
+
+def test_fluid_closure_step_rejects_bad_arguments(lib):
+    cfg, _, _ = workloads.gem_fluid(nx=8, ny=4)
+    st, h = _create(cfg)
+    assert lib.vl_fluid_closure_work_size(h) > 0
+    fs = vl.FluidClosureState()
+    fs.U[0], fs.U[1], fs.fields, fs.work = 0x1000, 0x2000, 0x3000, 0x4000
+    assert lib.vl_fluid_closure_step(h, ctypes.byref(fs), 7, 0.1, None) == 1        # unknown closure
+    assert lib.vl_fluid_closure_step(h, ctypes.byref(fs), 0, -0.1, None) == 1
+    assert lib.vl_fluid_closure_step(h, ctypes.byref(fs), 1, 0.1, None) == 1        # network closure, no params
+    fs.U[1] = 0x1000
+    assert lib.vl_fluid_closure_step(h, ctypes.byref(fs), 0, 0.1, None) == 2        # U[0] aliases U[1]
+    fs.U[1], fs.work = 0x2000, None
+    assert lib.vl_fluid_closure_step(h, ctypes.byref(fs), 0, 0.1, None) == 1
+    assert lib.vl_fluid_closure_step(h, None, 0, 0.1, None) == 1
     lib.vl_destroy(h)
