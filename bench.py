@@ -13,6 +13,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -296,6 +297,71 @@ def run_closure(cfg, end, params, steps, warmup):
                 energy_rel_drift=(e1 - e0) / e0, mass_rel_drift=max(abs(b - a) / a for a, b in zip(mass0, mass1)))
 
 
+def run_fluid_closure(nx, ny, closure, params, steps, warmup):
+    """The ten-moment fluid model alone (vl_fluid_closure_step) on the GEM
+    set-up with the Eq. 5 gradient closure or the network's heat flux: time
+    per step, per-category breakdown and mass drift."""
+    import torch
+    from paper_2109_06743_amd import vl
+    from paper_2109_06743_amd import workloads as W
+    cfg, U, F = W.gem_fluid(nx=nx, ny=ny)
+    # explicit limits: the Yee solver (c dt <= h / sqrt 2) and the parabolic
+    # Eq. 5 term (RK3 with the 5-point Laplacian: D dt <= 0.3 h^2, D = chi d_s v_t)
+    h = min((cfg["x_hi"] - cfg["x_lo"]) / nx, (cfg["y_hi"] - cfg["y_lo"]) / ny)
+    chi = 2.0 * math.sqrt(2.0 / math.pi)
+    D = max(chi * math.sqrt(sp["m"]) / abs(sp["q"])
+            * math.sqrt(float(np.max((u[..., 4] + u[..., 7] + u[..., 9]) / (3.0 * u[..., 0] * sp["m"]))))
+            for sp, u in zip(cfg["species"], U))
+    dt = 0.5 * min(h / (cfg["c"] * math.sqrt(2.0)), 0.3 * h * h / D)
+    cfg["dt"] = dt
+    ctx = vl.Context(cfg, "f64")
+    fs = vl.FluidState(ctx, U, vl.yee_pack(F), mlp_params=params if closure == "mlp" else None)
+    mass0 = [u.view(-1, 10)[:, 0].sum().item() for u in fs.U]
+    ctx.fluid_closure_step(fs, cfg["dt"], closure)
+    ctx.sync()
+    ctx.timing_enable(True)
+    nb = max(warmup - 1, 1)
+    for _ in range(nb):
+        ctx.fluid_closure_step(fs, cfg["dt"], closure)
+    ctx.sync()
+    br = ctx.timing_read()
+    ctx.timing_enable(False)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        ctx.fluid_closure_step(fs, cfg["dt"], closure)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    mass1 = [u.view(-1, 10)[:, 0].sum().item() for u in fs.U]
+    finite = all(bool(torch.isfinite(u).all()) for u in fs.U)
+    del fs, ctx
+    torch.cuda.empty_cache()
+    return dict(ms=ms, cells=nx * ny * len(U), breakdown={k: round(v[0] / nb, 4) for k, v in br.items() if v[1]},
+                mass_rel_drift=max(abs(q - p) / p for p, q in zip(mass0, mass1)), steps_run=1 + nb + steps,
+                dt=dt, finite=finite)
+
+
+def fluid_closure_report(args, trained_params):
+    """Both closures of the fluid-only model on the GEM set-up at --fluid-grid."""
+    from paper_2109_06743_amd import workloads as W
+    fnx, fny = args.fluid_grid
+    net = trained_params if trained_params is not None else W.mlp_init(0)
+    runs = []
+    for closure in ("gradient", "mlp"):
+        rf = run_fluid_closure(fnx, fny, closure, net, args.steps, args.warmup)
+        log(f"fluid-only {fnx}x{fny} {closure} closure: {rf['ms']:.3f} ms/step {rf['breakdown']}")
+        runs.append({"closure": closure, "value": rf["cells"] / (rf["ms"] * 1e-3), "unit": "cell-updates/s",
+                     "ms_per_step": round(rf["ms"], 4), "kernel_ms_per_step": rf["breakdown"],
+                     "mass_rel_drift": rf["mass_rel_drift"], "steps_run": rf["steps_run"], "dt": rf["dt"],
+                     "state_finite": rf["finite"]})
+    which = "trained above" if trained_params is not None else "untrained, Glorot init"
+    return {"workload": f"GEM ten-moment two-fluid model {fnx}x{fny} x 2 species, FP64, closures: Eq. 5 "
+                        f"temperature gradient / network ({which})",
+            "runs": runs}
+
+
 def cpu_baseline(seconds_cap=30.0):
     """The FP64 numpy oracle's full step on a sample of the same workload: the
     GEM set-up with the same 16^3 velocity grids and species on a 16 x 8
@@ -340,6 +406,10 @@ def main():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
     ap.add_argument("--closure-tol", type=float, nargs="+", default=[0.25, 1.0],
                     help="judge tolerances of the learned-closure runs (one run each)")
+    ap.add_argument("--no-fluid-closure", action="store_true", help="skip the fluid-only closure runs")
+    ap.add_argument("--fluid-grid", type=int, nargs=2, default=[2048, 1024], metavar=("NX", "NY"))
+    ap.add_argument("--only-fluid-closure", action="store_true",
+                    help="only the fluid-only closure runs (one JSON object), e.g. for profiling")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -356,6 +426,9 @@ def main():
     if not os.path.exists(B.LIB):
         B.build()
     torch.cuda.set_device(0)
+    if args.only_fluid_closure:
+        print(json.dumps({"fluid_closure": fluid_closure_report(args, None)}), flush=True)
+        return
     t0 = time.perf_counter()
     cfg, f, F, label = build_workload(args.workload)
     log(f"workload {label}: built in {time.perf_counter() - t0:.1f} s")
@@ -406,6 +479,8 @@ def main():
         out["mlp_closure"] = {
             "workload": label + " + learned heat-flux closure (64-64-64-64-16 tanh MLP, BF16 MFMA)",
             "start_time": end["t"], "runs": runs, "training": tr}
+    if not args.no_fluid_closure and cfg["kind"] == "2x3v":
+        out["fluid_closure"] = fluid_closure_report(args, params if not args.no_mlp else None)
     out["kernel_ms_per_step"] = {k: round(v[0] / r32["breakdown_steps"], 4) for k, v in r32["breakdown"].items()
                                  if v[1]}
     if not args.no_cpu:
