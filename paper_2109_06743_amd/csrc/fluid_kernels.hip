@@ -218,14 +218,37 @@ __device__ __forceinline__ void temperature_at(const double* __restrict__ U, int
     temperature6(V, A.m, T);
 }
 
+// Temperature-gradient closure of Eq. 5 as a source of the second moment:
+// S = -div Q = gchi n v_t lap T (gchi = chi / k0), lap by central second
+// differences, x periodic, y walls mirrored; S[cells][6] in PAIRS order.
+__global__ void closure_source3_kernel(const double* __restrict__ Us, FluidArgs A, double gchi,
+                                       double* __restrict__ S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= A.nx) return;
+    double Tc[6], T1[6], T2[6], lx[6];
+    temperature_at(Us, j, i, A, Tc);
+    temperature_at(Us, j, i + 1, A, T1);
+    temperature_at(Us, j, i - 1, A, T2);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) lx[k] = (T1[k] - 2.0 * Tc[k]) + T2[k];
+    temperature_at(Us, j + 1, i, A, T1);
+    temperature_at(Us, j - 1, i, A, T2);
+    const long long c = (long long)j * A.nx + i;
+    const double vt = sqrt((Tc[0] + Tc[3] + Tc[5]) / (3.0 * A.m));
+    const double w = gchi * (Us[c * 10] * vt);
+    const double ix2 = A.idx * A.idx, iy2 = A.idy * A.idy;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) S[c * 6 + k] = w * (lx[k] * ix2 + ((T1[k] - 2.0 * Tc[k]) + T2[k]) * iy2);
+}
+
 // U_out = a U_n + b (U_s + dt L(U_s)); U_out may alias U_n (each cell reads
-// only its own U_n entry) but not U_s.  gchi != 0 adds the temperature-
-// gradient closure of Eq. 5 as a source of the second moment:
-// -div Q = gchi n v_t lap T, gchi = chi / k0, lap by central differences.
+// only its own U_n entry) but not U_s.  Sg (or null): an extra source of the
+// second moment, [cells][6].
 __global__ void update3_kernel(const double* __restrict__ Us, const double* Un, double* Uout,
                                const double* __restrict__ Hx, const double* __restrict__ Hy,
                                const double* __restrict__ E, const double* __restrict__ B, double a, double b,
-                               double dt, FluidArgs A, double gchi) {
+                               double dt, FluidArgs A, const double* __restrict__ Sg) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= A.nx) return;
@@ -268,19 +291,9 @@ __global__ void update3_kernel(const double* __restrict__ Us, const double* Un, 
     const double* hyb = Hy + ((long long)j * A.nx + i) * 10;
 #pragma unroll
     for (int k = 0; k < 10; ++k) L[k] -= (hxr[k] - hxl[k]) * A.idx + (hyt[k] - hyb[k]) * A.idy;
-    if (gchi != 0.0) {
-        double Tc[6], Te[6], Tw[6], Tn[6], Ts[6];
-        temperature6(u, A.m, Tc);
-        temperature_at(Us, j, i + 1, A, Te);
-        temperature_at(Us, j, i - 1, A, Tw);
-        temperature_at(Us, j + 1, i, A, Tn);
-        temperature_at(Us, j - 1, i, A, Ts);
-        const double vt = sqrt((Tc[0] + Tc[3] + Tc[5]) / (3.0 * A.m));
-        const double w = gchi * (u[0] * vt);
-        const double ix2 = A.idx * A.idx, iy2 = A.idy * A.idy;
+    if (Sg) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-            L[4 + k] += w * (((Te[k] - 2.0 * Tc[k]) + Tw[k]) * ix2 + ((Tn[k] - 2.0 * Tc[k]) + Ts[k]) * iy2);
+        for (int k = 0; k < 6; ++k) L[4 + k] += Sg[c * 6 + k];
     }
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
@@ -390,7 +403,7 @@ hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom
 hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
-                                 hipStream_t st, double gchi) {
+                                 hipStream_t st, double gchi, double* Sg) {
     FluidArgs A{nx, ny, m, q, 1.0 / dx, 1.0 / dy};
     dim3 blk(64), gc((nx + 63) / 64, ny);
     const int nbx_row = (nx + kXTile - 1) / kXTile;
@@ -398,7 +411,13 @@ hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo,
     const int nbx = nbx_row * ny, nby = nby_col * ((ny + 1 + kYRows - 1) / kYRows);
     hipLaunchKernelGGL(faces3_kernel, dim3(nbx + nby), dim3(kFaceThreads), 0, st, Us, QA, QB, wa, wb, A, nbx_row,
                        nbx, nby_col, Hx, Hy);
-    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A, gchi);
+    const bool grad = gchi != 0.0;
+    if (grad) {
+        if (!Sg) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(closure_source3_kernel, gc, blk, 0, st, Us, A, gchi, Sg);
+    }
+    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A,
+                       (const double*)(grad ? Sg : nullptr));
     return hipGetLastError();
 }
 

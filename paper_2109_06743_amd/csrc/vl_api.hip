@@ -154,10 +154,11 @@ size_t mlp_step_doubles(const vl_config& c) {
 }
 
 // Fluid-only closure step: the step's field arrays, the fluid scratch, the
-// third moment (20 per cell) and the network's scratch (25 per cell + 2).
+// third moment (20 per cell), the Eq. 5 source (6 per cell) and the
+// network's scratch (25 per cell + 2).
 size_t fluid_closure_doubles(const vl_config& c) {
     const size_t cells = (size_t)c.nx * c.ny;
-    return yee_doubles(c) + 18 * cells + fluid_doubles(c) + 20 * cells + 25 * cells + 2;
+    return yee_doubles(c) + 18 * cells + fluid_doubles(c) + 20 * cells + 6 * cells + 25 * cells + 2;
 }
 
 size_t step_doubles(const vl_config& c) {
@@ -344,7 +345,8 @@ vl_status fluid_closure_step_impl(vl_ctx* ctx, const vl_fluid_state* S, int clos
     double* B_1 = E_1 + 3 * cells;
     double* fwork = B_1 + 3 * cells;
     double* qc = fwork + fluid_doubles(c);
-    double* mw = qc + 20 * cells;
+    double* sg = qc + 20 * cells;                         // Eq. 5 source of P, [cells][6]
+    double* mw = sg + 6 * cells;
     mw += ((uintptr_t)mw & 15u) ? 1 : 0;                 // network outputs are stored as 16-byte vectors
     float* y = (float*)mw;
     unsigned short* x = (unsigned short*)(mw + 8 * cells);
@@ -385,7 +387,7 @@ vl_status fluid_closure_step_impl(vl_ctx* ctx, const vl_fluid_state* S, int clos
             }
             VL_HIP(vl::launch_fluid_stage_3v(G[k].Us, U, G[k].Uo, qc, qc, 1.0, 0.0, G[k].E, G[k].B, G[k].a, G[k].b,
                                              dt, c.nx, c.ny, sp.q, sp.m, dx_of(c), dy_of(c), Hx, Hy, st,
-                                             closure == VL_FLUID_GRADIENT ? gchi : 0.0));
+                                             closure == VL_FLUID_GRADIENT ? gchi : 0.0, sg));
         }
     }
     Timed tm(ctx, VL_T_FIELDS, st);

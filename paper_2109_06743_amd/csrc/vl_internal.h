@@ -93,10 +93,13 @@ hipError_t launch_fluid_rk3_1v(double* U, const double* mom_t, const double* mom
 
 // One SSP-RK3 stage of the 3V fluid: Uo = a Un + b (Us + dt L(Us)), third
 // moment wa QA + wb QB (raw-moment layout, entries 10..19 of 20 per cell).
+// One RK stage of the ten-moment fluid.  gchi != 0 adds the Eq. 5
+// temperature-gradient closure gchi n v_t lap T as a source of P, computed
+// into Sg ([cells][6] scratch, required then).
 hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
-                                 hipStream_t st, double gchi = 0.0);
+                                 hipStream_t st, double gchi = 0.0, double* Sg = nullptr);
 // Qcal of fluid records U[cells][10] with zero heat flux, into qc[cells][20] (offsets 10..19).
 hipError_t launch_qcal_q0(const double* U, long long cells, double m, double* qc, hipStream_t st);
 
