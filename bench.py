@@ -36,6 +36,9 @@ def build_workload(name):
     if name == "gem":
         cfg, f, F = W.gem(nx=256, ny=128, nv=16, dt=0.003, fit=True, dtype=np.float32)
         label = "GEM 2X3V 256x128 x 16^3 x 2 species, mi/me=25, moment fitting"
+    elif name == "gem34":
+        cfg, f, F = W.gem(nx=128, ny=64, nv=34, dt=0.003, fit=True, dtype=np.float32)
+        label = "GEM 2X3V 128x64 x 34^3 x 2 species, mi/me=25, moment fitting"
     elif name == "tail":
         cfg, f, F = W.tail(nx=1024, ny=512, nv=12, dt=0.0012, fit=True, dtype=np.float32)
         label = "magnetotail 2X3V 1024x512 x 12^3 x 2 species, mi/me=100, Bg=0.1, moment fitting"
@@ -362,13 +365,14 @@ def fluid_closure_report(args, trained_params):
             "runs": runs}
 
 
-def cpu_baseline(seconds_cap=30.0):
+def cpu_baseline(seconds_cap=30.0, nv=16):
     """The FP64 numpy oracle's full step on a sample of the same workload: the
-    GEM set-up with the same 16^3 velocity grids and species on a 16 x 8
+    GEM set-up with the same nv^3 velocity grids and species on a small
     spatial slab (per-cell work identical to the full grid)."""
     from oracle import fields as OF, moments as OM, step as OS
     from paper_2109_06743_amd import workloads as W
-    cfg, f, F0 = W.gem(nx=16, ny=8, nv=16, dt=0.003, fit=True, dtype=np.float64)
+    snx, sny = (16, 8) if nv <= 16 else (4, 2)
+    cfg, f, F0 = W.gem(nx=snx, ny=sny, nv=nv, dt=0.003, fit=True, dtype=np.float64)
     F = OF.Yee(cfg["nx"], cfg["ny"])
     for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
         setattr(F, k, getattr(F0, k).copy())
@@ -391,7 +395,7 @@ def cpu_baseline(seconds_cap=30.0):
                 break
         dt = (time.perf_counter() - t0) / n
     return {"value": ncells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"GEM 16x8 x 16^3 x 2 species (fit on), {n} steps of the numpy FP64 oracle, "
+            "sample": f"GEM {snx}x{sny} x {nv}^3 x 2 species (fit on), {n} steps of the numpy FP64 oracle, "
                       f"{dt:.2f} s/step, single-threaded numpy"}
 
 
@@ -400,7 +404,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="gem", choices=["gem", "tail"])
+    ap.add_argument("--workload", default="gem", choices=["gem", "gem34", "tail"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
@@ -436,7 +440,7 @@ def main():
     r32["cells_per_launch"] = sum(x.size for x in f) / len(f)
     log(f"fp32: {r32['ms']:.3f} ms/step  warm-up breakdown {r32['breakdown']}  timed {r32['timing']}")
     r64 = None
-    if not args.no_fp64:
+    if not args.no_fp64 and args.workload != "gem34":     # 34^3 cubes are FP32 only
         r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", args.steps, args.warmup)
         log(f"fp64: {r64['ms']:.3f} ms/step")
     value = r32["ncells"] / (r32["ms"] * 1e-3)
@@ -485,7 +489,7 @@ def main():
                                  if v[1]}
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(nv=cfg["species"][0]["nv"][0] if args.workload == "gem34" else 16)
     print(json.dumps(out), flush=True)
 
 

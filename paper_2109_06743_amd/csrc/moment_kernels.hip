@@ -305,7 +305,7 @@ fit3_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* _
 // of a wave are contiguous and the only coordinate that varies along a thread's
 // elements is v_x, which is uniform across the block (table in the arguments).
 struct XTable {
-    double v[32], v2[32], v3[32];
+    double v[kBigCube], v2[kBigCube], v3[kBigCube];
 };
 
 // The 20 raw moments as weighted sums of the pencil sums S_k = sum_x f v_x^k
@@ -371,6 +371,44 @@ moments3_cube_kernel(const T* __restrict__ f, double* __restrict__ mom, long lon
     const double v = ReduceScatter<20, 32>::run(acc, lane, idx, cnt);
     const double dV = G.dv[0] * G.dv[1] * G.dv[2];
     if ((lane & 1) == 0 && cnt > 0) mom[cell * 20 + idx] = v * (idx < 4 ? dV : G.m * dV);
+}
+
+// Large cubic blocks (a cell's pencils do not fit one wave's registers): one
+// block per cell; thread t sums the v_x pencils at transverse positions
+// t, t + NTH, ... one pencil at a time, then a block reduction of the 20 sums.
+template <class T, int N, int NTH>
+__global__ void __launch_bounds__(NTH)
+moments3_big_kernel(const T* __restrict__ f, double* __restrict__ mom, VGrid G, XTable X) {
+    __shared__ double red[(NTH / 64) * 20];
+    __shared__ double fin_s[20];
+    const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
+    const T* src = f + cell * (N * N * N);
+    double acc[20];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) acc[q] = 0.0;
+    for (int t = threadIdx.x; t < N * N; t += NTH) {
+        T fv[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) fv[k] = src[t + k * N * N];
+        double Se[4] = {0.0, 0.0, 0.0, 0.0}, So[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double g = (double)fv[k];
+            double* S = (k & 1) ? So : Se;
+            S[0] += g;
+            S[1] = fma(g, X.v[k], S[1]);
+            S[2] = fma(g, X.v2[k], S[2]);
+            S[3] = fma(g, X.v3[k], S[3]);
+        }
+        const double S[4] = {Se[0] + So[0], Se[1] + So[1], Se[2] + So[2], Se[3] + So[3]};
+        double a[20];
+        pencil_moments(S, vc(G, 1, t / N), vc(G, 2, t % N), a);
+#pragma unroll
+        for (int q = 0; q < 20; ++q) acc[q] += a[q];
+    }
+    block_sum_rs<20>(acc, red, fin_s);
+    const double dV = G.dv[0] * G.dv[1] * G.dv[2];
+    if (threadIdx.x < 20) mom[cell * 20 + threadIdx.x] = fin_s[threadIdx.x] * (threadIdx.x < 4 ? dV : G.m * dV);
 }
 
 // Moment fitting of one cubic cell per block (see fit3_kernel for the steps).
@@ -478,6 +516,8 @@ __attribute__((amdgpu_waves_per_eu(FIT_WPE)))
 fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
                  unsigned* __restrict__ clip_part, VGrid G, XTable X, typename Bits<T>::U* __restrict__ max_out) {
     constexpr int NTH = 64 * NW;
+    // keeping the pass-1 exponentials in registers pays while they fit
+    constexpr bool kKeep = FIT_KEEP_G && NT * N <= 48;
     __shared__ double red[NW * 21];
     __shared__ double fin_s[21];
     const int tid = threadIdx.x;
@@ -508,9 +548,7 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
         // four interleaved partial sums per Maxwellian keep the FP64 adds
         // from forming one serial chain
         double sp[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-#if FIT_KEEP_G
-        T gv[NT][N], gf[NT][N];
-#endif
+        T gv[kKeep ? NT : 1][kKeep ? N : 1], gf[kKeep ? NT : 1][kKeep ? N : 1];
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             if (tid + NTH * j < N * N) {
@@ -518,10 +556,10 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
                 for (int k = 0; k < N; ++k) {
                     const T vx = (T)X.v[k];
                     const T a = qv[j].g(vx), b = qf[j].g(vx);
-#if FIT_KEEP_G
-                    gv[j][k] = a;
-                    gf[j][k] = b;
-#endif
+                    if constexpr (kKeep) {
+                        gv[j][k] = a;
+                        gf[j][k] = b;
+                    }
                     sp[k & 3][0] += (double)a;
                     sp[k & 3][1] += (double)b;
                 }
@@ -536,12 +574,13 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
             const bool act = tid + NTH * j < N * N;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-#if FIT_KEEP_G
-                const T x = fv[j][k] - A * gv[j][k] + Bc * gf[j][k];
-#else
-                const T vx = (T)X.v[k];
-                const T x = fv[j][k] - A * qv[j].g(vx) + Bc * qf[j].g(vx);
-#endif
+                T x;
+                if constexpr (kKeep) {
+                    x = fv[j][k] - A * gv[j][k] + Bc * gf[j][k];
+                } else {
+                    const T vx = (T)X.v[k];
+                    x = fv[j][k] - A * qv[j].g(vx) + Bc * qf[j].g(vx);
+                }
                 nclip += (act && x < T(0)) ? 1 : 0;
                 fv[j][k] = act ? fmax(x, T(0)) : T(0);
             }
@@ -684,7 +723,7 @@ static int threads_for(int work) {
 
 static XTable xtable(const VGridArgs& a) {
     XTable X{};
-    for (int k = 0; k < a.nv[0] && k < 32; ++k) {
+    for (int k = 0; k < a.nv[0] && k < kBigCube; ++k) {
         const double v = a.lo[0] + (k + 0.5) * a.dv[0];
         X.v[k] = v;
         X.v2[k] = v * v;
@@ -695,7 +734,7 @@ static XTable xtable(const VGridArgs& a) {
 
 static int cube_edge(const VGridArgs& a) {
     const bool cube = a.nv[0] == a.nv[1] && a.nv[1] == a.nv[2];
-    return (cube && (a.nv[0] == 8 || a.nv[0] == 12 || a.nv[0] == 16)) ? a.nv[0] : 0;
+    return (cube && (a.nv[0] == 8 || a.nv[0] == 12 || a.nv[0] == 16 || a.nv[0] == kBigCube)) ? a.nv[0] : 0;
 }
 
 template <class T>
@@ -708,6 +747,9 @@ hipError_t launch_moments3(const T* f, double* mom, long long cells, const VGrid
         if (N == 16) hipLaunchKernelGGL((moments3_cube_kernel<T, 16>), grid, blk, 0, st, f, mom, cells, G, X);
         if (N == 12) hipLaunchKernelGGL((moments3_cube_kernel<T, 12>), grid, blk, 0, st, f, mom, cells, G, X);
         if (N == 8) hipLaunchKernelGGL((moments3_cube_kernel<T, 8>), grid, blk, 0, st, f, mom, cells, G, X);
+        if (N == kBigCube)
+            hipLaunchKernelGGL((moments3_big_kernel<T, kBigCube, 256>), dim3((unsigned)cells), blk, 0, st, f, mom,
+                               G, X);
         return hipGetLastError();
     }
     const size_t shm = sizeof(T) * (size_t)a.nv[0] * a.nv[1] * (a.nv[2] | 1);
@@ -777,6 +819,9 @@ hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, 
             if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, FIT16_NW, FIT16_NT>), grid, dim3(64 * FIT16_NW), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, FIT12_NW, FIT12_NT>), grid, dim3(64 * FIT12_NW), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == kBigCube)   // 640 threads, two pencils each (1156 pencils)
+                hipLaunchKernelGGL((fit3_cube_kernel<T, kBigCube, 10, 2>), grid, dim3(640), 0, st, fin, fout, P,
+                                   mom_post, cp, G, X, mo);
         } else {
             if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, 4, 1>), grid, dim3(256), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, 3, 1>), grid, dim3(192), 0, st, fin, fout, P, mom_post, cp, G, X, mo);

@@ -562,15 +562,21 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
         EB[threadIdx.x] = E[cell * 3 + threadIdx.x];
         EB[3 + threadIdx.x] = B ? B[cell * 3 + threadIdx.x] : 0.0;
     }
-    // all loads of the block are issued before the first shared-memory store
+    // small blocks: all loads of the block are issued before the first
+    // shared-memory store; large blocks stream through registers in chunks
+    constexpr int CH = PER > 16 ? 4 : PER;
+    static_assert(PER % CH == 0, "chunks must tile the block");
     const T* src = fin + cell * NV;
-    T v[PER];
+#pragma unroll 1
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+        T v[CH];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) v[j] = src[threadIdx.x + j * NTH];
+        for (int j = 0; j < CH; ++j) v[j] = src[threadIdx.x + (c0 + j) * NTH];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int e = threadIdx.x + j * NTH;
-        blk[e + (e / N) * (PZ - N)] = v[j];
+        for (int j = 0; j < CH; ++j) {
+            const int e = threadIdx.x + (c0 + j) * NTH;
+            blk[e + (e / N) * (PZ - N)] = v[j];
+        }
     }
     __syncthreads();
     // each sweep reads the fields from shared memory after its barrier, which
@@ -588,15 +594,19 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
     __syncthreads();
     T* dst = fout + cell * NV;
     T mx = T(0);
+#pragma unroll 1
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+        T v[CH];
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int e = threadIdx.x + j * NTH;
-        v[j] = blk[e + (e / N) * (PZ - N)];
-    }
+        for (int j = 0; j < CH; ++j) {
+            const int e = threadIdx.x + (c0 + j) * NTH;
+            v[j] = blk[e + (e / N) * (PZ - N)];
+        }
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        dst[threadIdx.x + j * NTH] = v[j];
-        mx = fmax(mx, v[j]);
+        for (int j = 0; j < CH; ++j) {
+            dst[threadIdx.x + (c0 + j) * NTH] = v[j];
+            mx = fmax(mx, v[j]);
+        }
     }
     if (max_out) block_max_part(mx, max_out);
 }
@@ -745,6 +755,14 @@ hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E
     const bool cube = P.nvx == P.nvy && P.nvy == P.nvz;
     auto* mo = (typename Bits<T>::U*)(max_out ? part : nullptr);
     const dim3 grid((unsigned)cells);
+    if constexpr (sizeof(T) == 4) {
+        if (cube && P.nvx == kBigCube) {
+            // one cell per CU (its LDS); 578 threads = two pencils each per sweep
+            hipLaunchKernelGGL((pfc_v3_cube_kernel<T, kBigCube, 578>), grid, dim3(578), 0, st, fin, fout, E, B, P,
+                               (const T*)finf, mo);
+            return finish_max<T>(max_out, part, cells, st);
+        }
+    }
     if (cube && P.nvx == 16) {
         hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 16, 256>), grid, dim3(256), 0, st, fin, fout, E, B, P, (const T*)finf, mo);
     } else if (cube && P.nvx == 12) {

@@ -575,10 +575,13 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
         }
         if (nd == 1 && sp.nv[0] > 4096) return VL_ENOTSUP;
         if (nd == 3) {
-            for (int d = 0; d < 3; ++d)
+            // the 34^3 cube (FP32: the block fills one CU's LDS) has its own kernels
+            const bool big = sp.nv[0] == vl::kBigCube && sp.nv[1] == vl::kBigCube && sp.nv[2] == vl::kBigCube;
+            if (big && c.f_dtype != VL_F32) return VL_ENOTSUP;
+            for (int d = 0; d < 3 && !big; ++d)
                 if (sp.nv[d] > 32) return VL_ENOTSUP;
-            if ((long long)sp.nv[0] * sp.nv[1] * sp.nv[2] > 8192) return VL_ENOTSUP;
-            if (vl::v3_shared_bytes(sp.nv[0], sp.nv[1], sp.nv[2], elem) > 64 * 1024) return VL_ENOTSUP;
+            if (!big && (long long)sp.nv[0] * sp.nv[1] * sp.nv[2] > 8192) return VL_ENOTSUP;
+            if (!big && vl::v3_shared_bytes(sp.nv[0], sp.nv[1], sp.nv[2], elem) > 64 * 1024) return VL_ENOTSUP;
             // reflecting walls pair v_y with -v_y: the v_y grid must be symmetric about 0
             if (std::fabs(sp.v_lo[1] + sp.v_hi[1]) > 1e-12 * std::fabs(sp.v_hi[1])) return VL_EINVAL;
         }

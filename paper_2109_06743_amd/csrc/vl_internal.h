@@ -62,6 +62,9 @@ hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, dou
                            hipStream_t st);
 // Per-cell fitting parameters (cubic velocity blocks): kFitCellDoubles doubles
 // per spatial cell of device scratch.
+// Edge of the large cubic velocity grid with fixed-size kernels (FP32 only:
+// 34 x 34 x 35 floats = 161840 bytes of LDS per cell in the V operator).
+constexpr int kBigCube = 34;
 constexpr int kFitCellDoubles = 20;
 template <class T>
 hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, double* mom_post, void* counters,

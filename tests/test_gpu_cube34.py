@@ -1,0 +1,125 @@
+"""34^3 velocity grids (the paper's resolution in Sec. 3.2) on the GEM
+set-up: the V operator (one cell per CU, the block filling its LDS), the
+moments (one block per cell), the moment fit (two pencils per thread) and a
+full FP32 step against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL_MOM, TOL_STEP, TOL_SWEEP, host, rel_l2, storage_round
+from oracle import fields as OF
+from oracle import moments as OMo
+from oracle import step as OS
+from oracle import vlasov as OV
+from paper_2109_06743_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+N = 34
+
+
+def _grid(sp):
+    v, dv = [], []
+    for d in range(3):
+        c, h = OV.centres(sp["v_lo"][d], sp["v_hi"][d], sp["nv"][d])
+        v.append(c)
+        dv.append(h)
+    return v, dv
+
+
+@pytest.fixture(scope="module")
+def gem34():
+    from gpu_util import ensure_lib
+    ensure_lib()
+    return W.gem(nx=4, ny=2, nv=N, dt=0.003, fit=True, dtype=np.float64)
+
+
+def test_v_operator_34(gem34):
+    import torch
+    from paper_2109_06743_amd import vl
+    cfg, f, _ = gem34
+    ny, nx = cfg["ny"], cfg["nx"]
+    ctx = vl.Context(cfg, "f32")
+    rng = np.random.default_rng(3)
+    E = 0.1 * rng.normal(size=(ny, nx, 3))
+    B = rng.normal(size=(ny, nx, 3))
+    for s, sp in enumerate(cfg["species"]):
+        print(f"species {s}", flush=True)
+        v, dv = _grid(sp)
+        f32 = storage_round(f[s], "f32")
+        fin = torch.from_numpy(f32.astype(np.float32)).cuda()
+        fout = torch.empty_like(fin)
+        ctx.pfc_advect_v(s, fin, fout, torch.from_numpy(E.reshape(-1)).cuda(), torch.from_numpy(B.reshape(-1)).cuda(),
+                         cfg["dt"])
+        ctx.sync()
+        ref = OV.v_advect_3v(f32, E, B, sp["q"], sp["m"], v, dv, cfg["dt"], f_inf=float(f32.max()))
+        got = host(fout, ref.shape)
+        for j in range(ny):
+            for i in range(nx):
+                assert rel_l2(got[j, i], ref[j, i]) < 3 * TOL_SWEEP["f32"], (s, j, i)
+        assert abs(got.sum() - f32.sum()) <= 1e-6 * f32.sum()
+
+
+def test_moments_and_fit_34(gem34):
+    import torch
+    from paper_2109_06743_amd import vl
+    cfg, f, _ = gem34
+    ny, nx = cfg["ny"], cfg["nx"]
+    ctx = vl.Context(cfg, "f32")
+    for s, sp in enumerate(cfg["species"]):
+        v, dv = _grid(sp)
+        f32 = storage_round(f[s], "f32")
+        fin = torch.from_numpy(f32.astype(np.float32)).cuda()
+        mom = torch.zeros(nx * ny * 20, dtype=torch.float64, device="cuda")
+        ctx.moments(s, fin, mom)
+        ctx.sync()
+        m_ref = OMo.raw_moments_3v(f32, v, dv, sp["m"])
+        got = host(mom, m_ref.shape)
+        for a, b in [(0, 1), (1, 4), (4, 10), (10, 20)]:
+            den = max(np.linalg.norm(m_ref[..., a:b]), 1e-3 * np.abs(m_ref[..., 0]).max())
+            assert np.linalg.norm(got[..., a:b] - m_ref[..., a:b]) / den < TOL_MOM["f32"], (s, a)
+        # fluid state: shifted mean velocity, 5 % hotter
+        d = OMo.derived_3v(m_ref, sp["m"])
+        U = np.zeros((ny, nx, 10))
+        for j in range(ny):
+            for i in range(nx):
+                n, u, T = d["n"][j, i], d["u"][j, i], d["T"][j, i]
+                vt = np.sqrt(np.trace(T) / (3 * sp["m"]))
+                u2 = u + np.array([0.05, -0.03, 0.02]) * vt
+                P2 = n * 1.05 * T + sp["m"] * n * np.outer(u2, u2)
+                U[j, i] = [n, *(n * u2), P2[0, 0], P2[0, 1], P2[0, 2], P2[1, 1], P2[1, 2], P2[2, 2]]
+        fout = torch.empty_like(fin)
+        post = torch.zeros_like(mom)
+        ctx.moment_fit(s, fin, fout, mom, torch.from_numpy(U.reshape(-1).copy()).cuda(), post)
+        ctx.sync()
+        gotf = host(fout, f32.shape)
+        for j in range(ny):
+            for i in range(nx):
+                ref, _, _, _ = OMo.fit_cell_3v(f32[j, i], m_ref[j, i], U[j, i], sp["m"], v, dv)
+                assert rel_l2(gotf[j, i], ref) < 1e-5, (s, j, i)
+
+
+def test_step_34(gem34):
+    from paper_2109_06743_amd import vl
+    cfg, f, F0 = gem34
+    nx, ny = cfg["nx"], cfg["ny"]
+    F = OF.Yee(nx, ny)
+    for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        setattr(F, k, getattr(F0, k).copy())
+    f = [storage_round(x, "f32") for x in f]
+    moms, Us = [], []
+    for k, sp in enumerate(cfg["species"]):
+        v, dv = OS._grids(cfg, sp)
+        mm = OMo.raw_moments_3v(f[k], v, dv, sp["m"])
+        moms.append(mm)
+        Us.append(mm[..., :10].copy())
+    ctx = vl.Context(cfg, "f32")
+    st = vl.StepState(ctx, f, vl.yee_pack(F), U_list=Us, mom_post_list=moms)
+    ref = dict(f=f, U=[u.copy() for u in Us], mom_post=moms, F=F)
+    for k in range(2):
+        print(f"step {k}", flush=True)
+        ctx.step(st, cfg["dt"])
+        ref = OS.step_2x3v(ref, cfg, cfg["dt"])
+        ctx.sync()
+        for s in range(2):
+            got = host(st.f[s], ref["f"][s].shape)
+            assert rel_l2(got, ref["f"][s]) < TOL_STEP["f32"] * (k + 1), (k, s)
+            assert rel_l2(host(st.U[s], ref["U"][s].shape), ref["U"][s]) < 1e-5
