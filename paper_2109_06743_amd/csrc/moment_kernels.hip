@@ -345,7 +345,7 @@ moments3_cube_kernel(const T* __restrict__ f, double* __restrict__ mom, long lon
     for (int j = 0; j < NT; ++j) {
         const int t = lane + 64 * j;
 #pragma unroll
-        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? src[t + k * N * N] : T(0);
+        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? __builtin_nontemporal_load(src + t + k * N * N) : T(0);
     }
     double acc[20];
 #pragma unroll
@@ -389,7 +389,7 @@ moments3_big_kernel(const T* __restrict__ f, double* __restrict__ mom, VGrid G, 
     for (int t = threadIdx.x; t < N * N; t += NTH) {
         T fv[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) fv[k] = src[t + k * N * N];
+        for (int k = 0; k < N; ++k) fv[k] = __builtin_nontemporal_load(src + t + k * N * N);
         double Se[4] = {0.0, 0.0, 0.0, 0.0}, So[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -530,7 +530,7 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
     for (int j = 0; j < NT; ++j) {
         const int t = tid + NTH * j;
 #pragma unroll
-        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? src[t + k * N * N] : T(0);
+        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? __builtin_nontemporal_load(src + t + k * N * N) : T(0);
     }
     const FitCell& C = P[cell];
     const bool ok = C.ok != 0.0;
@@ -622,7 +622,7 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const T o = ok ? fv[j][k] * sc : fv[j][k];
-                dst[t + k * N * N] = o;
+                __builtin_nontemporal_store(o, dst + t + k * N * N);
                 mx = fmax(mx, o);
             }
         }

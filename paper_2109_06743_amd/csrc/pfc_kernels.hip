@@ -571,7 +571,7 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
     for (int c0 = 0; c0 < PER; c0 += CH) {
         T v[CH];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) v[j] = src[threadIdx.x + (c0 + j) * NTH];
+        for (int j = 0; j < CH; ++j) v[j] = __builtin_nontemporal_load(src + threadIdx.x + (c0 + j) * NTH);
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             const int e = threadIdx.x + (c0 + j) * NTH;
@@ -604,7 +604,7 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
         }
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            dst[threadIdx.x + (c0 + j) * NTH] = v[j];
+            __builtin_nontemporal_store(v[j], dst + threadIdx.x + (c0 + j) * NTH);
             mx = fmax(mx, v[j]);
         }
     }
