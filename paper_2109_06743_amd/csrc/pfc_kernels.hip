@@ -430,26 +430,52 @@ __device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F
     return fma(cA, A, fma(cB, B, a * w));
 }
 
-// Sub-cell sweep of one pencil whose lanes all shift one way: REV walks the
-// pencil from its far end (s < 0), so the downwind direction is always +m.
+// Sub-cell sweep of a pencil held in registers (updated in place) whose
+// wave's lanes all shift one way: REV walks it from its far end (s < 0), so
+// the downwind direction is always +m.
 template <class T, int N, bool REV>
-__device__ __forceinline__ void pencil_one_way(T* pb, int stride, T a, T c1, T c2, T F2) {
-    T w[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) w[m] = pb[(REV ? N - 1 - m : m) * stride];
-    T Dm = w[0];                 // D_m = g_m - g_{m-1}, zero ghost below
-    T Dp = w[1] - w[0];
+__device__ __forceinline__ void regs_one_way(T (&g)[N], T a, T c1, T c2, T F2) {
+    auto u = [&](int m) -> T& { return g[REV ? N - 1 - m : m]; };
+    T Dm = u(0);                 // D_m = g_m - g_{m-1}, zero ghost below
+    T Dp = u(1) - u(0);
     T Fprev = T(0);              // flux through the lower wall
 #pragma unroll
     for (int m = 0; m < N; ++m) {
         T F = T(0);              // flux through face m+1/2 (none through the upper wall)
+        const T w = u(m);
         if (m + 1 < N) {
-            F = sub_cell_flux(w[m], Dm, Dp, a, c1, c2, F2);
+            F = sub_cell_flux(w, Dm, Dp, a, c1, c2, F2);
             Dm = Dp;
-            Dp = (m + 2 < N ? w[m + 2] : T(0)) - w[m + 1];
+            Dp = (m + 2 < N ? u(m + 2) : T(0)) - u(m + 1);
         }
-        pb[(REV ? N - 1 - m : m) * stride] = fmax(w[m] + Fprev - F, T(0));
+        u(m) = fmax(w + Fprev - F, T(0));
         Fprev = F;
+    }
+}
+
+// The same for a wave holding both signs: storage order, the sign folded
+// into the coefficients and a per-lane select of the face flux.
+template <class T, int N>
+__device__ __forceinline__ void regs_mixed(T (&g)[N], bool pos, T a, T ac1, T ac2, T F2) {
+    const T cA = pos ? ac1 : -ac2;
+    const T cB = pos ? ac2 : -ac1;
+    // phi_m: partial flux of cell m in the lane's direction
+    T Dm = g[0];
+    T Dp = g[1] - g[0];
+    T phi_m = sub_cell_flux(g[0], Dm, Dp, a, cA, cB, F2);
+    T Fprev = T(0);
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        T Fnext = T(0), phi_n = T(0);
+        if (m + 1 < N) {
+            Dm = Dp;
+            Dp = (m + 2 < N ? g[m + 2] : T(0)) - g[m + 1];
+            phi_n = sub_cell_flux(g[m + 1], Dm, Dp, a, cA, cB, F2);
+            Fnext = pos ? phi_m : -phi_n;
+        }
+        g[m] = fmax(g[m] + Fprev - Fnext, T(0));
+        Fprev = Fnext;
+        phi_m = phi_n;
     }
 }
 
@@ -486,11 +512,36 @@ __device__ __attribute__((noinline)) void pencil_shifted(T* blk, int first, int 
     blk[q] = fmax(top + phi_prev, T(0));
 }
 
+// One PFC sweep of a pencil held in registers with displacement s (cells).
+// Shifts of a cell or more (any lane of the wave) go through the pencil's own
+// cells blk[base + m stride] of the shared block, which no other thread
+// touches meanwhile.
 template <class T, int N>
-__device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3Params& P, const double* EB, T F2) {
-    constexpr int PZ = N | 1;
-    // The displacement is linear in the pencil's two transverse indices:
-    // s = s0 + s1 i1 + s2 i2 (coefficients in FP64, then the storage type).
+__device__ __forceinline__ void sweep_pencil_regs(T (&g)[N], T s, T F2, T* blk, int base, int stride) {
+    const bool pos = s >= T(0);
+    const ShiftT<T> sh(fabs(s));
+    if (__all(sh.K == 0) && __all(pos)) {
+        regs_one_way<T, N, false>(g, sh.a, sh.ac1, sh.ac2, F2);
+    } else if (__all(sh.K == 0) && __all(!pos)) {
+        regs_one_way<T, N, true>(g, sh.a, sh.ac1, sh.ac2, F2);
+    } else if (__all(sh.K == 0)) {
+        regs_mixed<T, N>(g, pos, sh.a, sh.ac1, sh.ac2, F2);
+    } else {
+#pragma unroll
+        for (int m = 0; m < N; ++m) blk[base + m * stride] = g[m];
+        const int K = sh.K > N + 2 ? N + 2 : sh.K;
+        const int first = pos ? base : base + (N - 1) * stride;
+        pencil_shifted<T, N>(blk, first, pos ? stride : -stride, K, sh.a, sh.ac1, sh.ac2, F2);
+#pragma unroll
+        for (int m = 0; m < N; ++m) g[m] = blk[base + m * stride];
+    }
+}
+
+// Displacement coefficients of sweep d: s = s0 + s1 i1 + s2 i2 over the
+// pencil's two transverse indices (in FP64, then the storage type).
+template <class T>
+__device__ __forceinline__ void sweep_coeffs(int d, double sigma, const V3Params& P, const double* EB, T& s0, T& s1,
+                                             T& s2) {
     const double C = P.qm * sigma * P.inv_dv[d];
     const double c0 = P.lo[0] + 0.5 * P.dv[0], c1 = P.lo[1] + 0.5 * P.dv[1], c2 = P.lo[2] + 0.5 * P.dv[2];
     double d0, d1, d2;
@@ -501,7 +552,16 @@ __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3
     } else {                // pencil (ix, iy): a_z = (q/m)(Ez + vx By - vy Bx)
         d0 = C * (EB[2] + EB[4] * c0 - EB[3] * c1); d1 = C * EB[4] * P.dv[0]; d2 = -C * EB[3] * P.dv[1];
     }
-    const T s0 = (T)d0, s1 = (T)d1, s2 = (T)d2;
+    s0 = (T)d0;
+    s1 = (T)d1;
+    s2 = (T)d2;
+}
+
+template <class T, int N>
+__device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3Params& P, const double* EB, T F2) {
+    constexpr int PZ = N | 1;
+    T s0, s1, s2;
+    sweep_coeffs<T>(d, sigma, P, EB, s0, s1, s2);
     const int stride = d == 0 ? N * PZ : (d == 1 ? PZ : 1);
     for (int pen = threadIdx.x; pen < N * N; pen += blockDim.x) {
         const int i1 = pen / N, i2 = pen % N;
@@ -509,35 +569,19 @@ __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3
         const T s = fma(s1, (T)i1, fma(s2, (T)i2, s0));
         const bool pos = s >= T(0);
         const ShiftT<T> sh(fabs(s));
-        if (__all(sh.K == 0) && __all(pos)) {
-            pencil_one_way<T, N, false>(blk + base, stride, sh.a, sh.ac1, sh.ac2, F2);
-        } else if (__all(sh.K == 0) && __all(!pos)) {
-            pencil_one_way<T, N, true>(blk + base, stride, sh.a, sh.ac1, sh.ac2, F2);
-        } else if (__all(sh.K == 0)) {
+        if (__all(sh.K == 0)) {
             T* pb = blk + base;
-            T w[N];
+            T g[N];
 #pragma unroll
-            for (int m = 0; m < N; ++m) w[m] = pb[m * stride];
-            const T cA = pos ? sh.ac1 : -sh.ac2;
-            const T cB = pos ? sh.ac2 : -sh.ac1;
-            // phi_m: partial flux of cell m in the lane's direction
-            T Dm = w[0];
-            T Dp = w[1] - w[0];
-            T phi_m = sub_cell_flux(w[0], Dm, Dp, sh.a, cA, cB, F2);
-            T Fprev = T(0);
+            for (int m = 0; m < N; ++m) g[m] = pb[m * stride];
+            if (__all(pos))
+                regs_one_way<T, N, false>(g, sh.a, sh.ac1, sh.ac2, F2);
+            else if (__all(!pos))
+                regs_one_way<T, N, true>(g, sh.a, sh.ac1, sh.ac2, F2);
+            else
+                regs_mixed<T, N>(g, pos, sh.a, sh.ac1, sh.ac2, F2);
 #pragma unroll
-            for (int m = 0; m < N; ++m) {
-                T Fnext = T(0), phi_n = T(0);
-                if (m + 1 < N) {
-                    Dm = Dp;
-                    Dp = (m + 2 < N ? w[m + 2] : T(0)) - w[m + 1];
-                    phi_n = sub_cell_flux(w[m + 1], Dm, Dp, sh.a, cA, cB, F2);
-                    Fnext = pos ? phi_m : -phi_n;
-                }
-                pb[m * stride] = fmax(w[m] + Fprev - Fnext, T(0));
-                Fprev = Fnext;
-                phi_m = phi_n;
-            }
+            for (int m = 0; m < N; ++m) pb[m * stride] = g[m];
         } else {
             const int K = sh.K > N + 2 ? N + 2 : sh.K;
             const int first = pos ? base : base + (N - 1) * stride;
@@ -554,6 +598,8 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
     constexpr int NV = N * N * N;
     constexpr int PER = NV / NTH;            // values per thread (NTH divides N^3)
     static_assert(PER * NTH == NV, "thread count must divide the block");
+    // one v_x pencil per thread: the two v_x sweeps run in registers
+    constexpr bool kRegX = N * N <= NTH;
     __shared__ T blk[N * N * PZ];
     __shared__ double EB[6];
     const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
@@ -562,50 +608,96 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
         EB[threadIdx.x] = E[cell * 3 + threadIdx.x];
         EB[3 + threadIdx.x] = B ? B[cell * 3 + threadIdx.x] : 0.0;
     }
-    // small blocks: all loads of the block are issued before the first
-    // shared-memory store; large blocks stream through registers in chunks
-    constexpr int CH = PER > 16 ? 4 : PER;
-    static_assert(PER % CH == 0, "chunks must tile the block");
-    const T* src = fin + cell * NV;
-#pragma unroll 1
-    for (int c0 = 0; c0 < PER; c0 += CH) {
-        T v[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) v[j] = __builtin_nontemporal_load(src + threadIdx.x + (c0 + j) * NTH);
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int e = threadIdx.x + (c0 + j) * NTH;
-            blk[e + (e / N) * (PZ - N)] = v[j];
-        }
-    }
-    __syncthreads();
-    // each sweep reads the fields from shared memory after its barrier, which
-    // keeps the five sweeps' shift set-ups from being hoisted (and held live)
     const double half = 0.5 * P.tau;
-    sweep_cube<T, N>(blk, 0, half, P, EB, F2);
-    __syncthreads();
-    sweep_cube<T, N>(blk, 1, half, P, EB, F2);
-    __syncthreads();
-    sweep_cube<T, N>(blk, 2, P.tau, P, EB, F2);
-    __syncthreads();
-    sweep_cube<T, N>(blk, 1, half, P, EB, F2);
-    __syncthreads();
-    sweep_cube<T, N>(blk, 0, half, P, EB, F2);
-    __syncthreads();
+    const T* src = fin + cell * NV;
     T* dst = fout + cell * NV;
     T mx = T(0);
-#pragma unroll 1
-    for (int c0 = 0; c0 < PER; c0 += CH) {
-        T v[CH];
+    if constexpr (kRegX) {
+        // Thread t owns the v_x pencil at (iy, iz) = (t / N, t % N): it loads it
+        // (unit stride across the wave), sweeps it, and stores it into the block
+        // for the v_y, v_z, v_y sweeps; then reads it back for the last v_x
+        // sweep and writes it out.  The fields come straight from global
+        // memory for the first sweep, which runs before any barrier.
+        const int t = threadIdx.x;
+        const bool own = t < N * N;
+        const int xb = (t / N) * PZ + t % N;
+        constexpr int XS = N * PZ;
+        double eb[6];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int e = threadIdx.x + (c0 + j) * NTH;
-            v[j] = blk[e + (e / N) * (PZ - N)];
+        for (int k = 0; k < 3; ++k) {
+            eb[k] = E[cell * 3 + k];
+            eb[3 + k] = B ? B[cell * 3 + k] : 0.0;
         }
+        T xs0, xs1, xs2;
+        sweep_coeffs<T>(0, half, P, eb, xs0, xs1, xs2);
+        const T sx = fma(xs1, (T)(t / N), fma(xs2, (T)(t % N), xs0));
+        T g[N];
+        if (own) {
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            __builtin_nontemporal_store(v[j], dst + threadIdx.x + (c0 + j) * NTH);
-            mx = fmax(mx, v[j]);
+            for (int k = 0; k < N; ++k) g[k] = __builtin_nontemporal_load(src + t + k * N * N);
+            sweep_pencil_regs<T, N>(g, sx, F2, blk, xb, XS);
+#pragma unroll
+            for (int k = 0; k < N; ++k) blk[xb + k * XS] = g[k];
+        }
+        __syncthreads();
+        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 2, P.tau, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
+        __syncthreads();
+        if (own) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) g[k] = blk[xb + k * XS];
+            sweep_pencil_regs<T, N>(g, sx, F2, blk, xb, XS);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                __builtin_nontemporal_store(g[k], dst + t + k * N * N);
+                mx = fmax(mx, g[k]);
+            }
+        }
+    } else {
+        // small blocks never get here; large blocks stream through registers
+        // in chunks of four values per thread
+        constexpr int CH = PER > 16 ? 4 : PER;
+        static_assert(PER % CH == 0, "chunks must tile the block");
+#pragma unroll 1
+        for (int c0 = 0; c0 < PER; c0 += CH) {
+            T v[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) v[j] = __builtin_nontemporal_load(src + threadIdx.x + (c0 + j) * NTH);
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int e = threadIdx.x + (c0 + j) * NTH;
+                blk[e + (e / N) * (PZ - N)] = v[j];
+            }
+        }
+        __syncthreads();
+        // each sweep reads the fields from shared memory after its barrier, which
+        // keeps the five sweeps' shift set-ups from being hoisted (and held live)
+        sweep_cube<T, N>(blk, 0, half, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 2, P.tau, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 0, half, P, EB, F2);
+        __syncthreads();
+#pragma unroll 1
+        for (int c0 = 0; c0 < PER; c0 += CH) {
+            T v[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int e = threadIdx.x + (c0 + j) * NTH;
+                v[j] = blk[e + (e / N) * (PZ - N)];
+            }
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                __builtin_nontemporal_store(v[j], dst + threadIdx.x + (c0 + j) * NTH);
+                mx = fmax(mx, v[j]);
+            }
         }
     }
     if (max_out) block_max_part(mx, max_out);
