@@ -333,7 +333,7 @@ __device__ __forceinline__ void store20(double* dst, const double (&a)[20], doub
 // pencils at transverse positions t = l + 64 j (t = iy * N + iz), so the 20
 // sums are reduced inside one wave, with no block barrier.
 template <class T, int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 moments3_cube_kernel(const T* __restrict__ f, double* __restrict__ mom, long long cells, VGrid G, XTable X) {
     constexpr int NT = (N * N + 63) / 64;
     const int lane = threadIdx.x & 63;
