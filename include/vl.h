@@ -58,7 +58,7 @@ typedef enum {
 } vl_status;
 
 enum { VL_F32 = 0, VL_F64 = 1 };
-enum { VL_BC_REFLECT = 0 };
+enum { VL_BC_REFLECT = 0, VL_BC_PERIODIC = 1 };
 enum { VL_CLOSURE_KINETIC = 0, VL_CLOSURE_MLP = 1 };
 enum { VL_MAX_SPECIES = 2 };
 
@@ -75,7 +75,9 @@ typedef struct {
     int32_t nx, ny;       /* spatial cells; ny = 1 when dim_x = 1 */
     double x_lo, x_hi;    /* periodic x extent */
     double y_lo, y_hi;    /* y extent between walls (2X3V) */
-    int32_t bc_y;         /* VL_BC_REFLECT */
+    int32_t bc_y;         /* 2X3V y boundary: VL_BC_REFLECT (conducting walls, reflecting f;
+                             Sec. 3.3) or VL_BC_PERIODIC (Sec. 3.2); the learned closure
+                             needs VL_BC_REFLECT */
     int32_t nspecies;     /* 1 .. VL_MAX_SPECIES */
     vl_species sp[VL_MAX_SPECIES];
     int32_t f_dtype;      /* VL_F32 or VL_F64 */

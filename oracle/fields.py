@@ -72,10 +72,18 @@ def _odd_pad_y(a):
     return np.concatenate([-a[:1], a, -a[-1:]], axis=0)
 
 
-def _curl_e(F, dx, dy):
-    """(curl E)_x at Bx, (curl E)_y at By, (curl E)_z at Bz positions."""
-    Ez_p = _odd_pad_y(F.Ez)                          # rows -1 .. ny
-    Ex_p = _odd_pad_y(F.Ex)
+def _pad_y(a, bc_y):
+    """Ghost rows -1 and ny: odd at conducting walls, wrapped when periodic."""
+    if bc_y == "periodic":
+        return np.concatenate([a[-1:], a, a[:1]], axis=0)
+    return _odd_pad_y(a)
+
+
+def _curl_e(F, dx, dy, bc_y="reflect"):
+    """(curl E)_x at Bx, (curl E)_y at By, (curl E)_z at Bz positions.  With
+    periodic y the [ny+1] arrays' rows 0 and ny are the same points."""
+    Ez_p = _pad_y(F.Ez, bc_y)                        # rows -1 .. ny
+    Ex_p = _pad_y(F.Ex, bc_y)
     cx = (Ez_p[1:] - Ez_p[:-1]) / dy                 # dEz/dy at jh = 0..ny
     cy = -(np.roll(F.Ez, -1, axis=1) - F.Ez) / dx    # -dEz/dx at (i+1/2, j)
     dEy_dx = (np.roll(F.Ey, -1, axis=1) - F.Ey) / dx  # at (i+1/2, jh)
@@ -92,22 +100,26 @@ def _curl_b(F, dx, dy):
     return cx, cy, cz
 
 
-def current_on_yee(jc):
-    """Cell-centred current jc[ny, nx, 3] -> (jx at Ex, jy at Ey, jz at Ez)."""
+def current_on_yee(jc, bc_y="reflect"):
+    """Cell-centred current jc[ny, nx, 3] -> (jx at Ex, jy at Ey, jz at Ez);
+    j_y on the wall rows is 0 (reflecting), the mean across the seam
+    (periodic)."""
     jx = 0.5 * (jc[..., 0] + np.roll(jc[..., 0], -1, axis=1))
     ny, nx = jc.shape[:2]
     jy = np.zeros((ny + 1, nx))
     jy[1:ny] = 0.5 * (jc[:-1, :, 1] + jc[1:, :, 1])
+    if bc_y == "periodic":
+        jy[0] = jy[ny] = 0.5 * (jc[-1, :, 1] + jc[0, :, 1])
     jz = jc[..., 2].copy()
     return jx, jy, jz
 
 
-def maxwell_half_step(F, jc, dt, c, dx, dy):
+def maxwell_half_step(F, jc, dt, c, dx, dy, bc_y="reflect"):
     """One half step (length dt/2) of the FDTD solver with fixed current jc."""
     F = F.copy()
     h = 0.5 * dt
-    jx, jy, jz = current_on_yee(jc)
-    cx, cy, cz = _curl_e(F, dx, dy)
+    jx, jy, jz = current_on_yee(jc, bc_y)
+    cx, cy, cz = _curl_e(F, dx, dy, bc_y)
     F.Bx -= 0.5 * h * cx
     F.By -= 0.5 * h * cy
     F.Bz -= 0.5 * h * cz
@@ -115,7 +127,7 @@ def maxwell_half_step(F, jc, dt, c, dx, dy):
     F.Ex += h * c * c * (bx - jx)
     F.Ey += h * c * c * (by - jy)
     F.Ez += h * c * c * (bz - jz)
-    cx, cy, cz = _curl_e(F, dx, dy)
+    cx, cy, cz = _curl_e(F, dx, dy, bc_y)
     F.Bx -= 0.5 * h * cx
     F.By -= 0.5 * h * cy
     F.Bz -= 0.5 * h * cz

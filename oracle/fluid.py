@@ -24,7 +24,8 @@ Scheme (Sec. 2.1 names it; the paper prints no formula):
 Component orders: U = (n, nu_x, nu_y, nu_z, P_xx, P_xy, P_xz, P_yy, P_yz,
 P_zz); Q-calligraphic as in oracle.moments.TRIPLES.  1V: U = (n, nu, P).
 Boundaries: x periodic; y reflecting (ghost cells mirror the interior, with
-the sign flipped for components carrying an odd number of y indices).
+the sign flipped for components carrying an odd number of y indices) or
+periodic.
 """
 import numpy as np
 
@@ -127,11 +128,11 @@ def _pad(arr, axis, bc, parity):
     return np.concatenate([lo, arr, hi], axis=axis)
 
 
-def rhs_3v(U, Qc, E, B, q, m, dx, dy):
+def rhs_3v(U, Qc, E, B, q, m, dx, dy, bc_y="reflect"):
     """L(U) = -div H + S on U[ny, nx, 10] with Q-calligraphic Qc[ny, nx, 10]."""
     L = _source_3v(U, E, B, q, m)
     pu, pq = y_parity_u(), y_parity_q()
-    for axis, d, h, bc in ((1, 0, dx, "periodic"), (0, 1, dy, "reflect")):
+    for axis, d, h, bc in ((1, 0, dx, "periodic"), (0, 1, dy, bc_y)):
         Ug = _pad(U, axis, bc, pu)
         Qg = _pad(Qc, axis, bc, pq)
         n = U.shape[axis]
@@ -153,30 +154,30 @@ def rhs_3v(U, Qc, E, B, q, m, dx, dy):
     return L
 
 
-def rk3_3v(U, Q_t, Q_t1, fields_t, fields_t1, fields_th, q, m, dx, dy, dt):
+def rk3_3v(U, Q_t, Q_t1, fields_t, fields_t1, fields_th, q, m, dx, dy, dt, bc_y="reflect"):
     """One SSP-RK3 step; Q and (E, B) given at the stage times t, t+1, t+1/2."""
     Q_th = 0.5 * (Q_t + Q_t1)
-    U1 = U + dt * rhs_3v(U, Q_t, *fields_t, q, m, dx, dy)
-    U2 = 0.75 * U + 0.25 * (U1 + dt * rhs_3v(U1, Q_t1, *fields_t1, q, m, dx, dy))
-    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs_3v(U2, Q_th, *fields_th, q, m, dx, dy))
+    U1 = U + dt * rhs_3v(U, Q_t, *fields_t, q, m, dx, dy, bc_y)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * rhs_3v(U1, Q_t1, *fields_t1, q, m, dx, dy, bc_y))
+    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs_3v(U2, Q_th, *fields_th, q, m, dx, dy, bc_y))
 
 
-def rk3_3v_stagewise(U, qcal_of, fields_t, fields_t1, fields_th, q, m, dx, dy, dt):
+def rk3_3v_stagewise(U, qcal_of, fields_t, fields_t1, fields_th, q, m, dx, dy, dt, bc_y="reflect"):
     """SSP-RK3 with the third moment of each stage computed from that stage's
     state and fields by qcal_of(U_stage, B_stage) (a closure instead of the
     kinetic moments)."""
-    U1 = U + dt * rhs_3v(U, qcal_of(U, fields_t[1]), *fields_t, q, m, dx, dy)
-    U2 = 0.75 * U + 0.25 * (U1 + dt * rhs_3v(U1, qcal_of(U1, fields_t1[1]), *fields_t1, q, m, dx, dy))
-    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs_3v(U2, qcal_of(U2, fields_th[1]), *fields_th, q, m, dx, dy))
+    U1 = U + dt * rhs_3v(U, qcal_of(U, fields_t[1]), *fields_t, q, m, dx, dy, bc_y)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * rhs_3v(U1, qcal_of(U1, fields_t1[1]), *fields_t1, q, m, dx, dy, bc_y))
+    return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs_3v(U2, qcal_of(U2, fields_th[1]), *fields_th, q, m, dx, dy, bc_y))
 
 
-def rk3_3v_closure(U, qcal_of, source_of, fields_t, fields_t1, fields_th, q, m, dx, dy, dt):
+def rk3_3v_closure(U, qcal_of, source_of, fields_t, fields_t1, fields_th, q, m, dx, dy, dt, bc_y="reflect"):
     """SSP-RK3 in which every stage takes its third moment from
     qcal_of(U_stage, B_stage) and adds source_of(U_stage) ([ny, nx, 10], or
     None for no source) to L: the fluid model run with a heat-flux closure
     (Sec. 2.3) instead of the kinetic third moment."""
     def L(V, fl):
-        r = rhs_3v(V, qcal_of(V, fl[1]), *fl, q, m, dx, dy)
+        r = rhs_3v(V, qcal_of(V, fl[1]), *fl, q, m, dx, dy, bc_y)
         return r if source_of is None else r + source_of(V)
     U1 = U + dt * L(U, fields_t)
     U2 = 0.75 * U + 0.25 * (U1 + dt * L(U1, fields_t1))

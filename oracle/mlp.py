@@ -307,7 +307,7 @@ def divergence_heat_flux(Q10, dx, dy):
     return out
 
 
-def gradient_closure_divergence(U, m, q, dx, dy):
+def gradient_closure_divergence(U, m, q, dx, dy, bc_y="reflect"):
     """Eq. 5: div Q = -(chi/k0) n v_t lap T with k0 = 1/d_s, d_s = sqrt(m/(n0 q^2))
     for the reference density n0 = 1 (Sec. 2.1 normalisation, eps0 = 1/c^2),
     v_t = sqrt(tr(T)/(3m)); lap by central second differences (x periodic, y
@@ -316,7 +316,7 @@ def gradient_closure_divergence(U, m, q, dx, dy):
     vt = np.sqrt((T6[..., 0] + T6[..., 3] + T6[..., 5]) / (3.0 * m))
     d_s = math.sqrt(m / (q * q))
     _, pT = _y_parity_uT()
-    Tg = _pad_y(T6, pT)
+    Tg = _pad_y(T6, pT) if bc_y != "periodic" else np.concatenate([T6[-1:], T6, T6[:1]], axis=0)
     lap = ((np.roll(T6, -1, axis=1) - 2.0 * T6 + np.roll(T6, 1, axis=1)) / dx ** 2
            + (Tg[2:] - 2.0 * T6 + Tg[:-2]) / dy ** 2)
     return -(CHI * d_s) * (n * vt)[..., None] * lap

@@ -82,9 +82,10 @@ def step_2x3v(st, cfg, dt):
     dy = (cfg["y_hi"] - cfg["y_lo"]) / ny
     c = cfg["c"]
     species = cfg["species"]
+    bc = cfg.get("bc_y", "reflect")
     F_t = st["F"]
     j_t = sum(sp["q"] * st["mom_post"][k][..., 1:4] for k, sp in enumerate(species))
-    F = fields.maxwell_half_step(F_t, j_t, dt, c, dx, dy)
+    F = fields.maxwell_half_step(F_t, j_t, dt, c, dx, dy, bc)
     E_h, B_h = fields.cell_centred(F)
     E_0, B_0 = fields.cell_centred(F_t)
     fields_t1 = (2.0 * E_h - E_0, 2.0 * B_h - B_0)
@@ -93,14 +94,16 @@ def step_2x3v(st, cfg, dt):
     for k, sp in enumerate(species):
         q, m = sp["q"], sp["m"]
         v, dv = _grids(cfg, sp)
-        f = vlasov.x_advect_2x3v(st["f"][k], v[0], v[1], dx, dy, 0.5 * dt)
+        f = vlasov.x_advect_2x3v(st["f"][k], v[0], v[1], dx, dy, 0.5 * dt, bc_y=bc)
         f = vlasov.v_advect_3v(f, E_h, B_h, q, m, v, dv, dt)
-        f = vlasov.x_advect_2x3v(f, v[0], v[1], dx, dy, 0.5 * dt)
+        f = vlasov.x_advect_2x3v(f, v[0], v[1], dx, dy, 0.5 * dt, bc_y=bc)
         mom_pre = moments.raw_moments_3v(f, v, dv, m)
         U = st["U"][k]
         if cfg.get("fit"):
             use_net = False
             if cfg.get("closure") == "mlp":
+                if bc != "reflect":
+                    raise ValueError("the network closure is defined for reflecting y walls")
                 err = mlp.judge_error(mom_pre, m, k, st["mlp_params"], fields_t1[1])
                 fb = st["fallback"][k] if st.get("fallback") is not None else not (err <= cfg["closure_tol"])
                 out["closure_err"].append(err)
@@ -111,7 +114,7 @@ def step_2x3v(st, cfg, dt):
                                            (E_0, B_0), fields_t1, (E_h, B_h), q, m, dx, dy, dt)
             else:
                 U = fluid.rk3_3v(U, st["mom_post"][k][..., 10:], mom_pre[..., 10:],
-                                 (E_0, B_0), fields_t1, (E_h, B_h), q, m, dx, dy, dt)
+                                 (E_0, B_0), fields_t1, (E_h, B_h), q, m, dx, dy, dt, bc)
             f, U, cl, sk = moments.moment_fit_3v(f, mom_pre, U, m, v, dv)
             out["clipped"] += cl
             out["skipped"] += sk
@@ -123,7 +126,7 @@ def step_2x3v(st, cfg, dt):
         out["mom_pre"].append(mom_pre)
         out["mom_post"].append(mom_post)
     j_t1 = sum(sp["q"] * out["mom_post"][k][..., 1:4] for k, sp in enumerate(species))
-    out["F"] = fields.maxwell_half_step(F, j_t1, dt, c, dx, dy)
+    out["F"] = fields.maxwell_half_step(F, j_t1, dt, c, dx, dy, bc)
     out["E_half"], out["B_half"] = E_h, B_h
     return out
 
@@ -141,9 +144,10 @@ def fluid_step_2x3v(st, cfg, dt, closure, params=None):
     dy = (cfg["y_hi"] - cfg["y_lo"]) / ny
     c = cfg["c"]
     species = cfg["species"]
+    bc = cfg.get("bc_y", "reflect")
     F_t = st["F"]
     j_t = sum(sp["q"] * st["U"][k][..., 1:4] for k, sp in enumerate(species))
-    F = fields.maxwell_half_step(F_t, j_t, dt, c, dx, dy)
+    F = fields.maxwell_half_step(F_t, j_t, dt, c, dx, dy, bc)
     E_h, B_h = fields.cell_centred(F)
     E_0, B_0 = fields.cell_centred(F_t)
     fields_t1 = (2.0 * E_h - E_0, 2.0 * B_h - B_0)
@@ -156,18 +160,21 @@ def fluid_step_2x3v(st, cfg, dt, closure, params=None):
 
             def source_of(V, m=m, q=q):
                 S = np.zeros(V.shape)
-                S[..., 4:10] = -mlp.gradient_closure_divergence(V, m, q, dx, dy)
+                S[..., 4:10] = -mlp.gradient_closure_divergence(V, m, q, dx, dy, bc)
                 return S
         elif closure == "mlp":
+            if bc != "reflect":
+                raise ValueError("the network closure is defined for reflecting y walls")
+
             def qcal_of(V, Bs, m=m, k=k):
                 return mlp.closure_qcal(V, m, k, params, Bs)
             source_of = None
         else:
             raise ValueError(closure)
         out["U"].append(fluid.rk3_3v_closure(st["U"][k], qcal_of, source_of, (E_0, B_0), fields_t1, (E_h, B_h),
-                                             q, m, dx, dy, dt))
+                                             q, m, dx, dy, dt, bc))
     j_t1 = sum(sp["q"] * out["U"][k][..., 1:4] for k, sp in enumerate(species))
-    out["F"] = fields.maxwell_half_step(F, j_t1, dt, c, dx, dy)
+    out["F"] = fields.maxwell_half_step(F, j_t1, dt, c, dx, dy, bc)
     return out
 
 

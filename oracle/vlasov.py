@@ -68,9 +68,13 @@ def x_sweep_2x3v(f, vx, dx, tau, f_inf):
     return _sweep_axis(f, 1, s, "periodic", f_inf)
 
 
-def y_sweep_2x3v(f, vy, dy, tau, f_inf):
-    """Sweep along y (axis 0) between reflecting walls, pairing v_y with -v_y."""
+def y_sweep_2x3v(f, vy, dy, tau, f_inf, bc="reflect"):
+    """Sweep along y (axis 0): between reflecting walls, pairing v_y with -v_y,
+    or periodic (every v_y cell its own cyclic pencil)."""
     ny, nx, nvx, nvy, nvz = f.shape
+    if bc == "periodic":
+        s = np.broadcast_to((vy * tau / dy)[None, None, :, None], (nx, nvx, nvy, nvz))
+        return _sweep_axis(f, 0, s, "periodic", f_inf)
     assert np.allclose(vy, -vy[::-1]), "reflecting walls need a v_y grid symmetric about 0"
     out = np.empty_like(f)
     for jy in range(nvy - 1, (nvy - 1) // 2, -1):      # the v_y > 0 half (with its mirror)
@@ -86,11 +90,11 @@ def y_sweep_2x3v(f, vy, dy, tau, f_inf):
     return out
 
 
-def x_advect_2x3v(f, vx, vy, dx, dy, tau, f_inf=None):
+def x_advect_2x3v(f, vx, vy, dx, dy, tau, f_inf=None, bc_y="reflect"):
     """X(tau) in 2X3V: x-sweep then y-sweep, one f_inf for both."""
     f_inf = f.max() if f_inf is None else f_inf
     g = x_sweep_2x3v(f, vx, dx, tau, f_inf)
-    return y_sweep_2x3v(g, vy, dy, tau, f_inf)
+    return y_sweep_2x3v(g, vy, dy, tau, f_inf, bc_y)
 
 
 def v_advect_3v(f, E, B, q, m, v, dv, tau, f_inf=None):

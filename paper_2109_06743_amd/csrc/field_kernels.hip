@@ -54,6 +54,7 @@ hipError_t launch_poisson(const double* mom, int N, double L, double q, double* 
 struct YeeView {
     double *Ex, *Ey, *Ez, *Bx, *By, *Bz;
     int nx, ny;
+    int per;    // 1: periodic y (rows 0 and ny of the [ny+1] arrays are the same points)
 };
 
 __host__ __device__ inline YeeView yee_view(double* base, int nx, int ny) {
@@ -67,11 +68,18 @@ __host__ __device__ inline YeeView yee_view(double* base, int nx, int ny) {
     v.Bz = v.By + a;
     v.nx = nx;
     v.ny = ny;
+    v.per = 0;
     return v;
 }
 
-// integer-row component (Ex, Ez) at row j with odd ghosts beyond the walls
-__device__ __forceinline__ double odd_row(const double* a, int j, int i, int nx, int ny) {
+// integer-row component (Ex, Ez) at row j: odd ghosts beyond conducting
+// walls, wrapped rows when y is periodic
+__device__ __forceinline__ double odd_row(const double* a, int j, int i, int nx, int ny, int per) {
+    if (per) {
+        if (j < 0) j += ny;
+        if (j >= ny) j -= ny;
+        return a[(long long)j * nx + i];
+    }
     if (j < 0) return -a[(long long)(-1 - j) * nx + i];
     if (j >= ny) return -a[(long long)(2 * ny - 1 - j) * nx + i];
     return a[(long long)j * nx + i];
@@ -86,18 +94,19 @@ __global__ void yee_curl_e_kernel(YeeView F, double coef, double dx, double dy) 
     const int ip = (i + 1 == nx) ? 0 : i + 1;
     const long long h = (long long)jh * nx;
     // Bx at (i, jh-1/2): (curl E)_x = dEz/dy
-    const double dEz = (odd_row(F.Ez, jh, i, nx, ny) - odd_row(F.Ez, jh - 1, i, nx, ny)) / dy;
+    const double dEz = (odd_row(F.Ez, jh, i, nx, ny, F.per) - odd_row(F.Ez, jh - 1, i, nx, ny, F.per)) / dy;
     F.Bx[h + i] -= coef * dEz;
     // Bz at (i+1/2, jh-1/2): (curl E)_z = dEy/dx - dEx/dy
     const double dEy = (F.Ey[h + ip] - F.Ey[h + i]) / dx;
-    const double dEx = (odd_row(F.Ex, jh, i, nx, ny) - odd_row(F.Ex, jh - 1, i, nx, ny)) / dy;
+    const double dEx = (odd_row(F.Ex, jh, i, nx, ny, F.per) - odd_row(F.Ex, jh - 1, i, nx, ny, F.per)) / dy;
     F.Bz[h + i] -= coef * (dEy - dEx);
     // By at (i+1/2, j): (curl E)_y = -dEz/dx
     if (jh < ny) F.By[h + i] += coef * (F.Ez[h + ip] - F.Ez[h + i]) / dx;
 }
 
 // E += coef c^2 (curl B - j); j = sum_s q_s M1_s at cell centres averaged to
-// the E positions (j_y on a wall face is 0).
+// the E positions (j_y on a wall face is 0; periodic y: the mean across the
+// seam).
 struct Currents {
     const double* mom[2];   // per species: n u_x, n u_y, n u_z at offsets 1..3 of each cell's record
     double q[2];
@@ -122,6 +131,7 @@ __global__ void yee_curl_b_kernel(YeeView F, Currents J, double coef, double c2,
     // Ey at (i, jh-1/2): (curl B)_y = -dBz/dx
     double jy = 0.0;
     if (jh > 0 && jh < ny) jy = 0.5 * (jc(J, h - nx + i, 1) + jc(J, h + i, 1));
+    else if (F.per) jy = 0.5 * (jc(J, (long long)(ny - 1) * nx + i, 1) + jc(J, i, 1));   // across the seam
     F.Ey[h + i] += coef * c2 * (-(F.Bz[h + i] - F.Bz[h + im]) / dx - jy);
     if (jh < ny) {
         // Ex at (i+1/2, j): (curl B)_x = dBz/dy
@@ -158,8 +168,9 @@ __global__ void axpby_kernel(const double* __restrict__ x, const double* __restr
 }
 
 hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
-                               double dt, double c, double dx, double dy, hipStream_t st, int mstride) {
+                               double dt, double c, double dx, double dy, hipStream_t st, int mstride, int per) {
     YeeView F = yee_view(yee, nx, ny);
+    F.per = per;
     Currents J;
     J.ns = ns;
     J.stride = mstride;

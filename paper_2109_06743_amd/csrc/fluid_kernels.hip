@@ -74,6 +74,7 @@ struct FluidArgs {
     int nx, ny;
     double m, q;
     double idx, idy;      // 1/dx, 1/dy
+    int per;              // 1: periodic y, 0: reflecting walls
 };
 
 __device__ __forceinline__ double speed3(const double* U, int d, double m) {
@@ -101,8 +102,13 @@ static_assert(kYRows * kYCols == kXTile, "both tiles hold the same number of fac
 __device__ __forceinline__ double stage_comp(const double* U, const double* QA, const double* QB, double wa,
                                              double wb, int j, int i, int k, const FluidArgs& A) {
     bool mir = false;
-    if (j < 0) { j = -1 - j; mir = true; }
-    if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
+    if (A.per) {
+        while (j < 0) j += A.ny;
+        while (j >= A.ny) j -= A.ny;
+    } else {
+        if (j < 0) { j = -1 - j; mir = true; }
+        if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
+    }
     while (i < 0) i += A.nx;
     while (i >= A.nx) i -= A.nx;
     const long long c = (long long)j * A.nx + i;
@@ -207,8 +213,13 @@ __device__ __forceinline__ void temperature6(const double* V, double m, double* 
 __device__ __forceinline__ void temperature_at(const double* __restrict__ U, int j, int i, const FluidArgs& A,
                                                double* T) {
     bool mir = false;
-    if (j < 0) { j = -1 - j; mir = true; }
-    if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
+    if (A.per) {
+        if (j < 0) j += A.ny;
+        if (j >= A.ny) j -= A.ny;
+    } else {
+        if (j < 0) { j = -1 - j; mir = true; }
+        if (j >= A.ny) { j = 2 * A.ny - 1 - j; mir = true; }
+    }
     if (i < 0) i += A.nx;
     if (i >= A.nx) i -= A.nx;
     const long long c = (long long)j * A.nx + i;
@@ -378,7 +389,7 @@ __global__ void update1_kernel(const double* __restrict__ Us, const double* Un, 
 hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom_t1, const double* E_t,
                                const double* B_t, const double* E_t1, const double* B_t1, const double* E_th,
                                const double* B_th, double dt, int nx, int ny, double q, double m, double dx,
-                               double dy, double* work, hipStream_t st) {
+                               double dy, double* work, hipStream_t st, int per) {
     const long long cells = (long long)nx * ny;
     double* U1 = work;
     double* U2 = U1 + cells * 10;
@@ -394,7 +405,7 @@ hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom
     for (int k = 0; k < 3; ++k) {
         const hipError_t e = launch_fluid_stage_3v(S[k].Us, S[k].Un, S[k].Uo, S[k].QA, S[k].QB, S[k].wa, S[k].wb,
                                                    S[k].E, S[k].B, S[k].a, S[k].b, dt, nx, ny, q, m, dx, dy, Hx, Hy,
-                                                   st);
+                                                   st, 0.0, nullptr, per);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();
@@ -403,8 +414,8 @@ hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom
 hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
-                                 hipStream_t st, double gchi, double* Sg) {
-    FluidArgs A{nx, ny, m, q, 1.0 / dx, 1.0 / dy};
+                                 hipStream_t st, double gchi, double* Sg, int per) {
+    FluidArgs A{nx, ny, m, q, 1.0 / dx, 1.0 / dy, per};
     dim3 blk(64), gc((nx + 63) / 64, ny);
     const int nbx_row = (nx + kXTile - 1) / kXTile;
     const int nby_col = (nx + kYCols - 1) / kYCols;

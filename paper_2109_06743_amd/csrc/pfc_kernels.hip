@@ -109,9 +109,13 @@ pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int Nv, fl
 // ---------------------------------------------------------------------------
 // Fused X(tau) for 2X3V: the x sweep and then the y sweep with one f_inf, in
 // one pass over f.  A thread owns one (v_x, |v_y|, v_z) pair, C adjacent x
-// cells and a segment of S positions of the doubled reflecting y pencil
-// (positions 0..ny-1: rows of the +v_y half; ny..2ny-1: rows ny-1..0 of the
-// -v_y half).  It walks its segment, x-sweeping the C cells of each position
+// cells and a segment of S positions of its y pencils.  Reflecting walls: one
+// doubled pencil (positions 0..ny-1: rows of the +v_y half; ny..2ny-1: rows
+// ny-1..0 of the -v_y half).  Periodic y: two cyclic pencils of ny positions
+// (the +v_y half walked upward, the -v_y half downward); either way every
+// walk runs downwind.  Addresses are a 64-bit row base (the same for all
+// lanes at a position) plus a 32-bit offset within the row (nx * Nv < 2^31,
+// checked on the host).  It walks its segment, x-sweeping the C cells of each position
 // on the fly (a window of C+3 inputs in registers) and feeding the result to
 // the y update, f'(q) = P(q-K) + phi(q-K-1) - phi(q-K) with P the x-swept
 // pencil, so the intermediate array never reaches memory.  Per segment the x
@@ -122,14 +126,18 @@ template <class T, int C, int S>
 __global__ void __launch_bounds__(256)
 pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, int Nv, int nvx, int nvy, int nvz,
               float inv_nvz, float inv_half, double vx_lo, double dvx, double tau_dx, double vy_lo, double dvy,
-              double tau_dy, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
+              double tau_dy, int per, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
     const int half = (nvy + 1) / 2;
     const int npairs = nvx * half * nvz;
     const int L = 2 * ny;
-    const unsigned nst = (unsigned)(nx + C - 1) / C, nseg = (unsigned)(L + S - 1) / S;
+    const unsigned nsh = (unsigned)(ny + S - 1) / S;                  // periodic: segments per pencil
+    const unsigned nst = (unsigned)(nx + C - 1) / C, nseg = per ? 2 * nsh : (unsigned)(L + S - 1) / S;
     const unsigned wi = xcd_work_index(blockIdx.x, gridDim.x);
     const int c0 = (int)(wi % nst) * C;
-    const int i0 = (int)((wi / nst) % nseg) * S;
+    const unsigned kseg = (wi / nst) % nseg;
+    const int h0 = per ? (int)(kseg / nsh) : 0;                       // periodic: which pencil
+    const int i0 = per ? h0 * ny + (int)(kseg % nsh) * S : (int)kseg * S;
+    const int iend = per ? (h0 + 1) * ny : L;
     const int pid = (int)(wi / (nst * nseg)) * 256 + threadIdx.x;
     const T F2 = T(2) * *finf_p;
     T mx = T(0);
@@ -161,19 +169,28 @@ pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, i
                 if (col < 0) col = nx - 1;
             }
         }
-        // y: the doubled pencil moves by sy >= 0 cells
+        // y: every pencil moves by sy >= 0 cells in its walking order
         const double syd = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
         const ShiftT<T> shy(syd);
-        const int Ky = shy.K < L ? shy.K : shy.K % L;
-        auto base_of = [&](int j) -> unsigned {       // start of position j (any integer) of the doubled pencil
+        const int Ky = per ? shy.K % ny : (shy.K < L ? shy.K : shy.K % L);
+        // row (uniform across the wave) and offset in the row of position j
+        auto row_of_pos = [&](int j, unsigned& voff) -> int {
+            if (per) {
+                int r = (j - h0 * ny) % ny;
+                if (r < 0) r += ny;
+                voff = h0 ? vd : vu;
+                return h0 ? ny - 1 - r : r;
+            }
             j %= L;
             if (j < 0) j += L;
-            return j < ny ? (unsigned)j * rs + vu : (unsigned)(L - 1 - j) * rs + vd;
+            voff = j < ny ? vu : vd;
+            return j < ny ? j : L - 1 - j;
         };
         auto load = [&](int j, T (&W)[C + 3]) {
-            const unsigned b = base_of(j);
+            unsigned voff;
+            const T* rp = fin + (size_t)row_of_pos(j, voff) * rs + voff;
 #pragma unroll
-            for (int w = 0; w < C + 3; ++w) W[w] = fin[b + coff[w]];
+            for (int w = 0; w < C + 3; ++w) W[w] = rp[coff[w]];
         };
         auto xsweep = [&](const T (&W)[C + 3], T (&P)[C]) {
             T D = W[2] - W[1];
@@ -187,7 +204,7 @@ pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, i
                 D = Dn;
             }
         };
-        const int i1 = i0 + S < L ? i0 + S : L;
+        const int i1 = i0 + S < iend ? i0 + S : iend;
         T Wn[C + 3], Pa[C], Pb[C], Pc[C], phi_prev[C];
         load(i0 - 2, Wn);
         xsweep(Wn, Pa);
@@ -205,14 +222,15 @@ pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, i
             if (i + 1 < i1) load(i + 2, Wn);           // next position's inputs in flight
             T Pn[C];
             xsweep(Wc, Pn);                            // P(i+1)
-            const unsigned ob = base_of(i + Ky);
+            unsigned ovoff;
+            T* op = fout + (size_t)row_of_pos(i + Ky, ovoff) * rs + ovoff;
 #pragma unroll
             for (int r = 0; r < C; ++r) {
                 const T phi = pfc_phi_d(Pc[r], Pc[r] - Pb[r], Pn[r] - Pc[r], shy.a, shy.ac1, shy.ac2, F2);
                 const T o = fmax(Pc[r] + phi_prev[r] - phi, T(0));
                 const int col = posx ? c0 + r : c0 + C - 1 - r;
                 if (col < nx) {
-                    fout[ob + (unsigned)col * (unsigned)Nv] = o;
+                    op[(unsigned)col * (unsigned)Nv] = o;
                     mx = fmax(mx, o);
                 }
                 phi_prev[r] = phi;
@@ -797,25 +815,33 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
 template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
 constexpr int kXySeg = 64;
 template <class T>
-long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz) {
+long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz, int per) {
     const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
-    return ((npairs + 255) / 256) * ((2LL * ny + kXySeg - 1) / kXySeg) * ((nx + xy_cols<T>() - 1) / xy_cols<T>());
+    const long long nseg = per ? 2LL * ((ny + kXySeg - 1) / kXySeg) : (2LL * ny + kXySeg - 1) / kXySeg;
+    return ((npairs + 255) / 256) * nseg * ((nx + xy_cols<T>() - 1) / xy_cols<T>());
 }
 long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
-    const long long a = pfc_xy_blocks_t<float>(nx, ny, nvx, nvy, nvz), b = pfc_xy_blocks_t<double>(nx, ny, nvx, nvy, nvz);
-    return a > b ? a : b;
+    // the largest grid over both storage types and both y boundaries
+    long long m = 0;
+    for (int per = 0; per < 2; ++per) {
+        const long long a = pfc_xy_blocks_t<float>(nx, ny, nvx, nvy, nvz, per);
+        const long long b = pfc_xy_blocks_t<double>(nx, ny, nvx, nvy, nvz, per);
+        m = a > m ? a : m;
+        m = b > m ? b : m;
+    }
+    return m;
 }
 
 template <class T>
 hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vx_lo, double dvx,
-                         double tau_dx, double vy_lo, double dvy, double tau_dy, const void* finf, void* max_out,
-                         void* part, hipStream_t st) {
+                         double tau_dx, double vy_lo, double dvy, double tau_dy, int per, const void* finf,
+                         void* max_out, void* part, hipStream_t st) {
     const int Nv = nvx * nvy * nvz;
     const int half = (nvy + 1) / 2;
-    const long long blocks = pfc_xy_blocks_t<T>(nx, ny, nvx, nvy, nvz);
+    const long long blocks = pfc_xy_blocks_t<T>(nx, ny, nvx, nvy, nvz, per);
     hipLaunchKernelGGL((pfc_xy_kernel<T, xy_cols<T>(), kXySeg>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx,
                        ny, Nv, nvx, nvy, nvz, 1.0f / (float)nvz, 1.0f / (float)half, vx_lo, dvx, tau_dx, vy_lo, dvy,
-                       tau_dy, (const T*)finf, (typename Bits<T>::U*)(max_out ? part : nullptr));
+                       tau_dy, per, (const T*)finf, (typename Bits<T>::U*)(max_out ? part : nullptr));
     return finish_max<T>(max_out, part, blocks, st);
 }
 
@@ -897,7 +923,7 @@ hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st)
                                          const V3Params&, const void*, void*, void*, hipStream_t);         \
     template hipError_t launch_array_max<T>(const T*, long long, void*, void*, hipStream_t);                \
     template hipError_t launch_pfc_xy<T>(const T*, T*, int, int, int, int, int, double, double, double, double, \
-                                         double, double, const void*, void*, void*, hipStream_t);          \
+                                         double, double, int, const void*, void*, void*, hipStream_t);     \
     template hipError_t launch_max_finalize<T>(const void*, long long, void*, hipStream_t);
 VL_INST(float)
 VL_INST(double)

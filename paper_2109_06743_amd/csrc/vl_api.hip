@@ -134,6 +134,8 @@ vl_status check_species(vl_ctx* ctx, int32_t s) {
     return VL_OK;
 }
 
+int per_y(const vl_config& c) { return c.dim_x == 2 && c.bc_y == VL_BC_PERIODIC ? 1 : 0; }
+
 size_t yee_doubles(const vl_config& c) {
     return c.dim_x == 2 ? (size_t)c.nx * (3 * (size_t)c.ny + 3 * ((size_t)c.ny + 1)) : 0;
 }
@@ -183,8 +185,8 @@ vl_status advect_x_typed(vl_ctx* ctx, int s, const T* fin, T* fout, T* fwork, do
     (void)fwork;
     Timed tm(ctx, VL_T_PFC_X, st);
     VL_HIP((vl::launch_pfc_xy<T>(fin, fout, c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2], sp.v_lo[0], dv_of(sp, 0),
-                                 tau / dx_of(c), sp.v_lo[1], dv_of(sp, 1), tau / dy_of(c), finf, max_y, ctx->bpart,
-                                 st)));
+                                 tau / dx_of(c), sp.v_lo[1], dv_of(sp, 1), tau / dy_of(c),
+                                 c.bc_y == VL_BC_PERIODIC ? 1 : 0, finf, max_y, ctx->bpart, st)));
     return VL_OK;
 }
 
@@ -274,7 +276,7 @@ vl_status fluid_step_impl(vl_ctx* ctx, int s, double* U, const double* mom_t, co
     Timed tm(ctx, VL_T_FLUID, st);
     if (c.dim_v == 3)
         VL_HIP(vl::launch_fluid_rk3_3v(U, mom_t, mom_t1, E_t, B_t, E_t1, B_t1, E_th, B_th, dt, c.nx, c.ny, sp.q, sp.m,
-                                       dx_of(c), dy_of(c), work, st));
+                                       dx_of(c), dy_of(c), work, st, per_y(c)));
     else
         VL_HIP(vl::launch_fluid_rk3_1v(U, mom_t, mom_t1, E_t, E_t1, E_th, dt, c.nx, sp.q, sp.m, dx_of(c), work, st));
     return VL_OK;
@@ -356,7 +358,8 @@ vl_status fluid_closure_step_impl(vl_ctx* ctx, const vl_fluid_state* S, int clos
         Timed tm(ctx, VL_T_FIELDS, st);
         VL_HIP(hipMemcpyAsync(yee_t, S->fields, ny1 * sizeof(double), hipMemcpyDeviceToDevice, st));
         VL_HIP(vl::launch_cell_fields(yee_t, c.nx, c.ny, E_t, B_t, st));
-        VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, Uc, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 10));
+        VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, Uc, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 10,
+                                       per_y(c)));
         VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, st));
         VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 3 * cells, st));
         VL_HIP(vl::launch_axpby(B_h, B_t, 2.0, -1.0, B_1, 3 * cells, st));
@@ -387,11 +390,12 @@ vl_status fluid_closure_step_impl(vl_ctx* ctx, const vl_fluid_state* S, int clos
             }
             VL_HIP(vl::launch_fluid_stage_3v(G[k].Us, U, G[k].Uo, qc, qc, 1.0, 0.0, G[k].E, G[k].B, G[k].a, G[k].b,
                                              dt, c.nx, c.ny, sp.q, sp.m, dx_of(c), dy_of(c), Hx, Hy, st,
-                                             closure == VL_FLUID_GRADIENT ? gchi : 0.0, sg));
+                                             closure == VL_FLUID_GRADIENT ? gchi : 0.0, sg, per_y(c)));
         }
     }
     Timed tm(ctx, VL_T_FIELDS, st);
-    VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, Uc, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 10));
+    VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, Uc, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 10,
+                                   per_y(c)));
     return VL_OK;
 }
 
@@ -427,7 +431,8 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
                 VL_HIP(vl::launch_cell_fields(yee_t, c.nx, c.ny, E_t, B_t, st));
             }
             const double* mom_t[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
-            VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t, q, ns, dt, c.c, dx_of(c), dy_of(c), st));
+            VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 20,
+                                            per_y(c)));
             VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, st));
             if (c.fit) {
                 VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 3 * cells, st));
@@ -466,7 +471,8 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         }
         const double* mom_t1[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
         Timed tm(ctx, VL_T_FIELDS, st);
-        VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t1, q, ns, dt, c.c, dx_of(c), dy_of(c), st));
+        VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t1, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 20,
+                                        per_y(c)));
     } else {
         const int nx = c.nx;
         double* mom_half = S->work;
@@ -548,7 +554,9 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
     if (c.dim_x == 2 && c.ny < 2) return VL_EINVAL;   // the wall ghosts mirror two interior rows
     if (!(std::isfinite(c.x_lo) && std::isfinite(c.x_hi) && c.x_hi > c.x_lo)) return VL_EINVAL;
     if (c.dim_x == 2 && !(std::isfinite(c.y_lo) && std::isfinite(c.y_hi) && c.y_hi > c.y_lo)) return VL_EINVAL;
-    if (c.dim_x == 2 && c.bc_y != VL_BC_REFLECT) return VL_ENOTSUP;
+    if (c.dim_x == 2 && c.bc_y != VL_BC_REFLECT && c.bc_y != VL_BC_PERIODIC) return VL_EINVAL;
+    // the network closure's features mirror at the walls
+    if (c.dim_x == 2 && c.bc_y == VL_BC_PERIODIC && c.closure == VL_CLOSURE_MLP) return VL_ENOTSUP;
     if (c.nspecies < 1 || c.nspecies > VL_MAX_SPECIES) return VL_EINVAL;
     if (c.dim_x == 1 && c.nspecies != 1) return VL_ENOTSUP;
     if (c.f_dtype != VL_F32 && c.f_dtype != VL_F64) return VL_EINVAL;
@@ -574,6 +582,8 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
             }
         }
         if (nd == 1 && sp.nv[0] > 4096) return VL_ENOTSUP;
+        // the X operators address a row of f (nx velocity blocks) with 32-bit offsets
+        if ((long long)c.nx * sp.nv[0] * sp.nv[1] * sp.nv[2] >= (1LL << 31)) return VL_ENOTSUP;
         if (nd == 3) {
             // the 34^3 cube (FP32: the block fills one CU's LDS) has its own kernels
             const bool big = sp.nv[0] == vl::kBigCube && sp.nv[1] == vl::kBigCube && sp.nv[2] == vl::kBigCube;
@@ -714,7 +724,7 @@ vl_status vl_maxwell_half_step(vl_ctx* ctx, double* yee, const double* const* mo
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     const double q[2] = {c.sp[0].q, c.nspecies > 1 ? c.sp[1].q : 0.0};
     VL_HIP(vl::launch_maxwell_half(yee, c.nx, c.ny, mom, q, c.nspecies, dt, c.c, dx_of(c), dy_of(c),
-                                   (hipStream_t)stream));
+                                   (hipStream_t)stream, 20, per_y(c)));
     return VL_OK;
 }
 
@@ -775,6 +785,8 @@ vl_status vl_fluid_closure_step(vl_ctx* ctx, vl_fluid_state* S, int32_t closure,
         if (!S->U[s]) return fail(ctx, VL_EINVAL, "null U[%d]", s);
     if (c.nspecies > 1 && S->U[0] == S->U[1]) return fail(ctx, VL_EALIAS, "U[0] and U[1] alias");
     if (closure == VL_FLUID_MLP && !S->mlp_params) return fail(ctx, VL_EINVAL, "the network closure needs mlp_params");
+    if (closure == VL_FLUID_MLP && c.bc_y != VL_BC_REFLECT)
+        return fail(ctx, VL_ENOTSUP, "the network closure's features need reflecting y walls");
     vl_status r;
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     return fluid_closure_step_impl(ctx, S, closure, dt, (hipStream_t)stream);

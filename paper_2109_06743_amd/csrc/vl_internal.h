@@ -46,10 +46,11 @@ hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipS
 long long pfc_x_blocks(int rows, int nx, long long Nv);
 long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz);
 // Fused X(tau) of 2X3V (x then y sweep, one f_inf); fout must not alias fin.
+// per = 0: reflecting y walls, 1: periodic y.
 template <class T>
 hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vx_lo, double dvx,
-                         double tau_dx, double vy_lo, double dvy, double tau_dy, const void* finf, void* max_out,
-                         void* part, hipStream_t st);
+                         double tau_dx, double vy_lo, double dvy, double tau_dy, int per, const void* finf,
+                         void* max_out, void* part, hipStream_t st);
 constexpr long long kMaxArrayBlocks = 4096;
 template <class T>
 hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStream_t st);
@@ -79,7 +80,8 @@ hipError_t launch_poisson(const double* mom, int N, double L, double q, double* 
 // mom[s]: per-cell records of mstride doubles holding n u at offsets 1..3
 // (raw moments: 20; fluid state: 10).
 hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
-                               double dt, double c, double dx, double dy, hipStream_t st, int mstride = 20);
+                               double dt, double c, double dx, double dy, hipStream_t st, int mstride = 20,
+                               int per = 0);
 hipError_t launch_cell_fields(const double* yee, int nx, int ny, double* E, double* B, hipStream_t st);
 hipError_t launch_field_energy(const double* fields, int dim_x, int nx, int ny, double c, double dX, double* part,
                                double* out, hipStream_t st);
@@ -89,7 +91,7 @@ hipError_t launch_axpby(const double* x, const double* y, double a, double b, do
 hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom_t1, const double* E_t,
                                const double* B_t, const double* E_t1, const double* B_t1, const double* E_th,
                                const double* B_th, double dt, int nx, int ny, double q, double m, double dx,
-                               double dy, double* work, hipStream_t st);
+                               double dy, double* work, hipStream_t st, int per = 0);
 hipError_t launch_fluid_rk3_1v(double* U, const double* mom_t, const double* mom_t1, const double* E_t,
                                const double* E_t1, const double* E_th, double dt, int nx, double q, double m,
                                double dx, double* work, hipStream_t st);
@@ -102,7 +104,7 @@ hipError_t launch_fluid_rk3_1v(double* U, const double* mom_t, const double* mom
 hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo, const double* QA, const double* QB,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
-                                 hipStream_t st, double gchi = 0.0, double* Sg = nullptr);
+                                 hipStream_t st, double gchi = 0.0, double* Sg = nullptr, int per = 0);
 // Qcal of fluid records U[cells][10] with zero heat flux, into qc[cells][20] (offsets 10..19).
 hipError_t launch_qcal_q0(const double* U, long long cells, double m, double* qc, hipStream_t st);
 

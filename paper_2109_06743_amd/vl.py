@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvl.so")
 
 VL_F32, VL_F64 = 0, 1
+VL_BC_REFLECT, VL_BC_PERIODIC = 0, 1
 MAX_SPECIES = 2
 STATUS = {0: "VL_OK", 1: "VL_EINVAL", 2: "VL_EALIAS", 3: "VL_ENOTSUP", 4: "VL_EDEVICE", 5: "VL_EHIP",
           6: "VL_ENUMERIC"}
@@ -127,7 +128,7 @@ def make_config(cfg, f_dtype="f32"):
     c.fit = int(bool(cfg.get("fit", False)))
     c.closure = VL_CLOSURE_MLP if cfg.get("closure") == "mlp" else VL_CLOSURE_KINETIC
     c.closure_tol = float(cfg.get("closure_tol", 0.0))
-    c.bc_y = 0
+    c.bc_y = VL_BC_PERIODIC if cfg.get("bc_y") == "periodic" else VL_BC_REFLECT
     if cfg["kind"] == "1x1v":
         c.dim_x, c.dim_v = 1, 1
         c.nx, c.ny = cfg["nx"], 1

@@ -132,6 +132,97 @@ def gem_fluid(nx=256, ny=128, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5.
     return cfg, U, F
 
 
+def _maxwellian_drift(n, u, T, m, v):
+    """Analytic isotropic Maxwellian n (m/2piT)^{3/2} exp(-m |v-u|^2/(2T)) with a
+    drift u[..., 3]; n, T of shape [...]; returns [..., nvx, nvy, nvz]."""
+    vx, vy, vz = v
+    T = np.asarray(T, dtype=np.float64) * np.ones_like(n)
+    pre = n * (m / (2 * math.pi * T)) ** 1.5
+    g = [np.exp(-0.5 * m * (vd[None, :] - u[..., k].reshape(-1, 1)) ** 2 / T.reshape(-1, 1))
+         for k, vd in enumerate((vx, vy, vz))]
+    out = pre.reshape(-1, 1, 1, 1) * g[0][:, :, None, None] * g[1][:, None, :, None] * g[2][:, None, None, :]
+    return out.reshape(n.shape + (len(vx), len(vy), len(vz)))
+
+
+def _ot_setup(nx, ny, nv, mass_ratio, c, beta_i, du, dB, ve_max, vi_max, dt, steps, fit):
+    """Orszag-Tang configuration, per-species (n, u[3], T) at cell centres and Yee fields."""
+    me = 1.0 / mass_ratio
+    L = 0.5 * math.sqrt(me) * nx                   # two cells per electron inertial length (d_i = 1)
+    Ly = L * ny / nx
+    T = 0.5 * beta_i                               # beta_i = 2 n0 T_i / B0^2 with n0 = B0 = mu0 = 1; T_e = T_i
+    sp = [_species(-1.0, me, ve_max, nv), _species(1.0, 1.0, vi_max, nv)]
+    cfg = dict(kind="2x3v", nx=nx, ny=ny, x_lo=0.0, x_hi=L, y_lo=0.0, y_hi=Ly, c=c, species=sp, fit=fit, dt=dt,
+               steps=steps, bc_y="periodic", name=f"orszag-tang {nx}x{ny}x{nv}^3 mi/me={mass_ratio:g}")
+    dx, dy = L / nx, Ly / ny
+    xc = (np.arange(nx) + 0.5) * dx                # integer i
+    xf = (np.arange(nx) + 1.0) * dx                # i + 1/2
+    yc = (np.arange(ny) + 0.5) * dy                # integer j
+    yf = np.arange(ny + 1) * dy                    # j - 1/2 (rows 0 and ny are the same points)
+    k1 = 2 * math.pi / L
+    F = Yee0(nx, ny)
+    XC, YF = np.meshgrid(xc, yf)
+    F.Bx = -dB * np.sin(k1 * YF)
+    XF, YC = np.meshgrid(xf, yc)
+    F.By = dB * np.sin(2 * k1 * XF)
+    F.Bz = np.ones((ny + 1, nx))
+    F.Ex = -du * np.sin(k1 * XF)                   # E = -u x B with B_z = B0
+    F.Ey = -du * np.sin(k1 * YF)
+    # electron density from Gauss's law on the grid: div E = (n_i - n_e) / eps0, eps0 = 1/c^2
+    divE = (F.Ex - np.roll(F.Ex, 1, axis=1)) / dx + (F.Ey[1:] - F.Ey[:-1]) / dy
+    X, Y = np.meshgrid(xc, yc)
+    u = np.zeros((ny, nx, 3))
+    u[..., 0] = -du * np.sin(k1 * Y)
+    u[..., 1] = du * np.sin(k1 * X)
+    ue = u.copy()
+    ue[..., 2] = -k1 * dB * (2 * np.cos(2 * k1 * X) + np.cos(k1 * Y))   # the electrons carry j_z
+    ne = 1.0 - divE / (c * c)
+    ni = np.ones((ny, nx))
+    return cfg, ((ne, ue, T), (ni, u, T)), F
+
+
+def orszag_tang(n=512, nv=34, mass_ratio=100.0, c=18.174, beta_i=0.1, du=0.2, dB=0.2, ve_max=14.0, vi_max=1.5,
+                dt=0.0015, steps=20, fit=True, dtype=np.float32, ny=None):
+    """Orszag-Tang turbulence (Sec. 3.2): periodic box, B = (-dB sin 2pi y/L,
+    dB sin 4pi x/L, B0), u = (-du sin 2pi y/L, du sin 2pi x/L, u_z) with the
+    electrons carrying j_z, E = -u x B, T_i = T_e, beta_i = 0.1, m_i/m_e = 100,
+    c = 18.174 v_A, electrons on +-14 v_A, ions on +-1.5 v_A; n x ny cells
+    (ny = n: the square box)."""
+    ny = n if ny is None else ny
+    cfg, prof, F = _ot_setup(n, ny, nv, mass_ratio, c, beta_i, du, dB, ve_max, vi_max, dt, steps, fit)
+    f = []
+    for s, (ns, us, Ts) in zip(cfg["species"], prof):
+        v = [_centres(s["v_lo"][d], s["v_hi"][d], s["nv"][d]) for d in range(3)]
+        f.append(_maxwellian_drift(ns, us, Ts, s["m"], v).astype(dtype))
+    return cfg, f, F
+
+
+def orszag_tang_device(n=512, nv=34, dtype="f32", rows_per_chunk=16, **kw):
+    """The same set-up with f generated on the current GPU (torch tensors), a
+    few rows at a time: the full 512^2 x 34^3 grid is 41 GB per species."""
+    import torch
+    ny = kw.pop("ny", n)
+    cfg, prof, F = _ot_setup(n, ny, nv, kw.get("mass_ratio", 100.0), kw.get("c", 18.174), kw.get("beta_i", 0.1),
+                             kw.get("du", 0.2), kw.get("dB", 0.2), kw.get("ve_max", 14.0), kw.get("vi_max", 1.5),
+                             kw.get("dt", 0.0015), kw.get("steps", 20), kw.get("fit", True))
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    f = []
+    for s, (ns, us, Ts) in zip(cfg["species"], prof):
+        v = [torch.as_tensor(_centres(s["v_lo"][d], s["v_hi"][d], s["nv"][d]), device="cuda") for d in range(3)]
+        out = torch.empty((ny, n, nv, nv, nv), dtype=tdt, device="cuda")
+        m = s["m"]
+        for j0 in range(0, ny, rows_per_chunk):
+            j1 = min(j0 + rows_per_chunk, ny)
+            nn = torch.as_tensor(ns[j0:j1], device="cuda")
+            uu = torch.as_tensor(us[j0:j1], device="cuda")
+            pre = nn * (m / (2 * math.pi * Ts)) ** 1.5
+            g = [torch.exp(-0.5 * m * (v[k][None, None, :] - uu[..., k, None]) ** 2 / Ts) for k in range(3)]
+            blk = (pre[..., None, None, None] * g[0][..., :, None, None] * g[1][..., None, :, None]
+                   * g[2][..., None, None, :])
+            out[j0:j1] = blk.to(tdt)
+        f.append(out)
+    return cfg, f, F
+
+
 def tail(nx=1024, ny=512, nv=12, mass_ratio=100.0, c=30.0, lam=0.6, Ti_Te=3.0, Bg=0.1, noise=1e-4,
          ve_max=20.0, vi_max=5.0, dt=0.0012, steps=20, fit=True, seed=0, dtype=np.float32):
     """Magnetotail-like set-up (Sec. 4.1): Harris sheet carrying the current,

@@ -113,6 +113,19 @@ def test_cube34_is_fp32_only(lib):
     assert st == 3
 
 
+def test_periodic_y_and_the_network_closure(lib):
+    cfg, _, _ = workloads.orszag_tang(n=8, nv=4)
+    st, h = _create(cfg)
+    assert st == 0
+    lib.vl_destroy(h)
+    st, h = _create(dict(cfg, closure="mlp", closure_tol=0.5))
+    assert st == 3                                  # the network's features mirror at walls
+    c = vl.make_config(cfg)
+    c.bc_y = 7
+    h = ctypes.c_void_p()
+    assert lib.vl_create(ctypes.byref(c), ctypes.byref(h)) == 1
+
+
 def test_fluid_closure_step_rejects_bad_arguments(lib):
     cfg, _, _ = workloads.gem_fluid(nx=8, ny=4)
     st, h = _create(cfg)
