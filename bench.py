@@ -39,12 +39,21 @@ def build_workload(name):
     elif name == "gem34":
         cfg, f, F = W.gem(nx=128, ny=64, nv=34, dt=0.003, fit=True, dtype=np.float32)
         label = "GEM 2X3V 128x64 x 34^3 x 2 species, mi/me=25, moment fitting"
+    elif name == "ot":
+        # the paper's Orszag-Tang grid, 41 GB of f per species: generated on the GPU
+        cfg, f, F = W.orszag_tang_device(n=512, nv=34, dtype="f32")
+        label = "Orszag-Tang 2X3V 512x512 x 34^3 x 2 species, periodic, mi/me=100, moment fitting"
     elif name == "tail":
         cfg, f, F = W.tail(nx=1024, ny=512, nv=12, dt=0.0012, fit=True, dtype=np.float32)
         label = "magnetotail 2X3V 1024x512 x 12^3 x 2 species, mi/me=100, Bg=0.1, moment fitting"
     else:
         raise SystemExit(f"unknown workload {name}")
     return cfg, f, F, label
+
+
+def _nelem(x):
+    """Element count of a numpy array or a torch tensor."""
+    return x.numel() if hasattr(x, "numel") else x.size
 
 
 def total_energy(ctx, st):
@@ -365,14 +374,17 @@ def fluid_closure_report(args, trained_params):
             "runs": runs}
 
 
-def cpu_baseline(seconds_cap=30.0, nv=16):
+def cpu_baseline(seconds_cap=30.0, nv=16, ot=False):
     """The FP64 numpy oracle's full step on a sample of the same workload: the
-    GEM set-up with the same nv^3 velocity grids and species on a small
-    spatial slab (per-cell work identical to the full grid)."""
+    GEM (or Orszag-Tang) set-up with the same nv^3 velocity grids and species
+    on a small spatial slab (per-cell work identical to the full grid)."""
     from oracle import fields as OF, moments as OM, step as OS
     from paper_2109_06743_amd import workloads as W
     snx, sny = (16, 8) if nv <= 16 else (4, 2)
-    cfg, f, F0 = W.gem(nx=snx, ny=sny, nv=nv, dt=0.003, fit=True, dtype=np.float64)
+    if ot:
+        cfg, f, F0 = W.orszag_tang(n=snx, ny=sny, nv=nv, dtype=np.float64)
+    else:
+        cfg, f, F0 = W.gem(nx=snx, ny=sny, nv=nv, dt=0.003, fit=True, dtype=np.float64)
     F = OF.Yee(cfg["nx"], cfg["ny"])
     for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
         setattr(F, k, getattr(F0, k).copy())
@@ -395,7 +407,8 @@ def cpu_baseline(seconds_cap=30.0, nv=16):
                 break
         dt = (time.perf_counter() - t0) / n
     return {"value": ncells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"GEM {snx}x{sny} x {nv}^3 x 2 species (fit on), {n} steps of the numpy FP64 oracle, "
+            "sample": f"{'Orszag-Tang' if ot else 'GEM'} {snx}x{sny} x {nv}^3 x 2 species (fit on), {n} steps of "
+                      f"the numpy FP64 oracle, "
                       f"{dt:.2f} s/step, single-threaded numpy"}
 
 
@@ -404,7 +417,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="gem", choices=["gem", "gem34", "tail"])
+    ap.add_argument("--workload", default="gem", choices=["gem", "gem34", "ot", "tail"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
@@ -437,10 +450,10 @@ def main():
     cfg, f, F, label = build_workload(args.workload)
     log(f"workload {label}: built in {time.perf_counter() - t0:.1f} s")
     r32 = run_gpu(cfg, f, F, "f32", args.steps, args.warmup)
-    r32["cells_per_launch"] = sum(x.size for x in f) / len(f)
+    r32["cells_per_launch"] = sum(_nelem(x) for x in f) / len(f)
     log(f"fp32: {r32['ms']:.3f} ms/step  warm-up breakdown {r32['breakdown']}  timed {r32['timing']}")
     r64 = None
-    if not args.no_fp64 and args.workload != "gem34":     # 34^3 cubes are FP32 only
+    if not args.no_fp64 and args.workload not in ("gem34", "ot"):     # 34^3 cubes are FP32 only
         r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", args.steps, args.warmup)
         log(f"fp64: {r64['ms']:.3f} ms/step")
     value = r32["ncells"] / (r32["ms"] * 1e-3)
@@ -464,7 +477,7 @@ def main():
         out["energy_rel_drift"]["f64"] = r64["energy_rel_drift"]
         out["energy_rel_drift"]["f64_steps"] = r64["steps_run"]
         out["mass_rel_drift"]["f64"] = r64["mass_rel_drift"]
-    if not args.no_mlp and cfg["kind"] == "2x3v":
+    if not args.no_mlp and cfg["kind"] == "2x3v" and cfg.get("bc_y", "reflect") == "reflect":
         log("learned closure: generating data and training ...")
         params, tr, end = train_closure(cfg, f, F)
         log(f"  {tr}")
@@ -484,12 +497,13 @@ def main():
             "workload": label + " + learned heat-flux closure (64-64-64-64-16 tanh MLP, BF16 MFMA)",
             "start_time": end["t"], "runs": runs, "training": tr}
     if not args.no_fluid_closure and cfg["kind"] == "2x3v":
-        out["fluid_closure"] = fluid_closure_report(args, params if not args.no_mlp else None)
+        out["fluid_closure"] = fluid_closure_report(args, params if "mlp_closure" in out else None)
     out["kernel_ms_per_step"] = {k: round(v[0] / r32["breakdown_steps"], 4) for k, v in r32["breakdown"].items()
                                  if v[1]}
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(nv=cfg["species"][0]["nv"][0] if args.workload == "gem34" else 16)
+        out["cpu_baseline"] = cpu_baseline(nv=cfg["species"][0]["nv"][0] if args.workload in ("gem34", "ot") else 16,
+                                           ot=args.workload == "ot")
     print(json.dumps(out), flush=True)
 
 
