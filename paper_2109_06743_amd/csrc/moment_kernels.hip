@@ -494,8 +494,9 @@ fit3_params_kernel(const double* __restrict__ mom_pre, double* __restrict__ U, l
 
 // One block of NW waves per cell; thread t owns the v_x pencils at transverse
 // positions t + 64 NW j (j < NT).  Two passes over f held in registers: the
-// normalisation sums of the two Maxwellians (FP32 exponentials, FP64 sums),
-// then the exchange, clip, FP64 post-fit moments and the FP64 rescale.  The
+// normalisation sums of the two Maxwellians (exponentials and pencil sums in
+// the storage type, FP64 across pencils), then the exchange, clip (counted
+// per wave with a ballot), FP64 post-fit moments and the FP64 rescale.  The
 // block sums use the reduce-scatter (block_sum_rs).
 #ifndef FIT_KEEP_G
 #define FIT_KEEP_G 1
@@ -516,6 +517,8 @@ __attribute__((amdgpu_waves_per_eu(FIT_WPE)))
 fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
                  unsigned* __restrict__ clip_part, VGrid G, XTable X, typename Bits<T>::U* __restrict__ max_out) {
     constexpr int NTH = 64 * NW;
+    // every thread owns NT whole pencils (no idle positions to mask)
+    constexpr bool kFull = NT * NTH == N * N;
     // keeping the pass-1 exponentials in registers pays while they fit
     constexpr bool kKeep = FIT_KEEP_G && NT * N <= 48;
     __shared__ double red[NW * 21];
@@ -530,12 +533,20 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
     for (int j = 0; j < NT; ++j) {
         const int t = tid + NTH * j;
 #pragma unroll
-        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? __builtin_nontemporal_load(src + t + k * N * N) : T(0);
+        for (int k = 0; k < N; ++k)
+            fv[j][k] = (kFull || t < N * N) ? __builtin_nontemporal_load(src + t + k * N * N) : T(0);
     }
+    // v_x in the storage type: held in registers for the small blocks,
+    // converted at each use for the large ones (register pressure)
+    constexpr bool kVx = N <= 16;
+    T vxr[kVx ? N : 1];
+#pragma unroll
+    for (int k = 0; k < (kVx ? N : 1); ++k) vxr[k] = (T)X.v[k];
+    auto vx = [&](int k) -> T { return kVx ? vxr[k] : (T)X.v[k]; };
     const FitCell& C = P[cell];
     const bool ok = C.ok != 0.0;
     const double nV = C.nV;
-    int nclip = 0;
+    unsigned nclip = 0;     // clipped elements of this wave (the same in every lane)
     if (ok) {
         QuadX<T> qv[NT], qf[NT];
 #pragma unroll
@@ -545,44 +556,46 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
             qv[j].set(C.aV, C.uV, vy, vz);
             qf[j].set(C.aF, C.uF, vy, vz);
         }
-        // four interleaved partial sums per Maxwellian keep the FP64 adds
-        // from forming one serial chain
-        double sp[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        // pencil sums of the samples in the storage type (four interleaved
+        // chains; the samples carry that type's rounding already), added
+        // across pencils in FP64
+        double s[2] = {0.0, 0.0};
         T gv[kKeep ? NT : 1][kKeep ? N : 1], gf[kKeep ? NT : 1][kKeep ? N : 1];
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            if (tid + NTH * j < N * N) {
+            if (kFull || tid + NTH * j < N * N) {
+                T pa[4] = {T(0), T(0), T(0), T(0)}, pb[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
-                    const T vx = (T)X.v[k];
-                    const T a = qv[j].g(vx), b = qf[j].g(vx);
+                    const T a = qv[j].g(vx(k)), b = qf[j].g(vx(k));
                     if constexpr (kKeep) {
                         gv[j][k] = a;
                         gf[j][k] = b;
                     }
-                    sp[k & 3][0] += (double)a;
-                    sp[k & 3][1] += (double)b;
+                    pa[k & 3] += a;
+                    pb[k & 3] += b;
                 }
+                s[0] += (double)((pa[0] + pa[1]) + (pa[2] + pa[3]));
+                s[1] += (double)((pb[0] + pb[1]) + (pb[2] + pb[3]));
             }
         }
-        double s[2] = {(sp[0][0] + sp[1][0]) + (sp[2][0] + sp[3][0]), (sp[0][1] + sp[1][1]) + (sp[2][1] + sp[3][1])};
         block_sum_rs<2>(s, red, fin_s);
         const T A = (T)(nV / (fin_s[0] * dV));
         const T Bc = (T)(nV / (fin_s[1] * dV));
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const bool act = tid + NTH * j < N * N;
+            const bool act = kFull || tid + NTH * j < N * N;
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 T x;
                 if constexpr (kKeep) {
                     x = fv[j][k] - A * gv[j][k] + Bc * gf[j][k];
                 } else {
-                    const T vx = (T)X.v[k];
-                    x = fv[j][k] - A * qv[j].g(vx) + Bc * qf[j].g(vx);
+                    x = fv[j][k] - A * qv[j].g(vx(k)) + Bc * qf[j].g(vx(k));
                 }
-                nclip += (act && x < T(0)) ? 1 : 0;
-                fv[j][k] = act ? fmax(x, T(0)) : T(0);
+                const bool neg = x < T(0);
+                nclip += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(act && neg));
+                fv[j][k] = act ? (neg ? T(0) : x) : T(0);
             }
         }
     }
@@ -590,7 +603,7 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
     double acc[21];
 #pragma unroll
     for (int q = 0; q < 20; ++q) acc[q] = 0.0;
-    acc[20] = (double)nclip;
+    acc[20] = (tid & (kWave - 1)) == 0 ? (double)nclip : 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int t = tid + NTH * j;
@@ -613,15 +626,15 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
     }
     block_sum_rs<21>(acc, red, fin_s);
     const double scale = ok ? nV / (fin_s[0] * dV) : 1.0;
-    const T sc = (T)scale;
+    const T sc = (T)scale;     // 1 exactly when the cell is skipped
     T mx = T(0);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int t = tid + NTH * j;
-        if (t < N * N) {
+        if (kFull || t < N * N) {
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const T o = ok ? fv[j][k] * sc : fv[j][k];
+                const T o = fv[j][k] * sc;
                 __builtin_nontemporal_store(o, dst + t + k * N * N);
                 mx = fmax(mx, o);
             }

@@ -160,12 +160,12 @@ size_t mlp_step_doubles(const vl_config& c) {
 // network's scratch (25 per cell + 2).
 size_t fluid_closure_doubles(const vl_config& c) {
     const size_t cells = (size_t)c.nx * c.ny;
-    return yee_doubles(c) + 18 * cells + fluid_doubles(c) + 20 * cells + 6 * cells + 25 * cells + 2;
+    return 18 * cells + fluid_doubles(c) + 20 * cells + 6 * cells + 25 * cells + 2;
 }
 
 size_t step_doubles(const vl_config& c) {
     const size_t cells = (size_t)c.nx * c.ny;
-    if (c.dim_v == 3) return yee_doubles(c) + 18 * cells + fluid_doubles(c) + mlp_step_doubles(c);
+    if (c.dim_v == 3) return 18 * cells + fluid_doubles(c) + mlp_step_doubles(c);
     return 4 * (size_t)c.nx + 3 * (size_t)c.nx + fluid_doubles(c);
 }
 
@@ -337,9 +337,7 @@ vl_status fluid_closure_step_impl(vl_ctx* ctx, const vl_fluid_state* S, int clos
     const int ns = c.nspecies;
     const long long cells = ctx->cells;
     const double q[2] = {c.sp[0].q, ns > 1 ? c.sp[1].q : 0.0};
-    const size_t ny1 = yee_doubles(c);
-    double* yee_t = S->work;
-    double* E_t = yee_t + ny1;
+    double* E_t = S->work;
     double* B_t = E_t + 3 * cells;
     double* E_h = B_t + 3 * cells;
     double* B_h = E_h + 3 * cells;
@@ -356,13 +354,12 @@ vl_status fluid_closure_step_impl(vl_ctx* ctx, const vl_fluid_state* S, int clos
     const double* Uc[2] = {S->U[0], ns > 1 ? S->U[1] : nullptr};
     {
         Timed tm(ctx, VL_T_FIELDS, st);
-        VL_HIP(hipMemcpyAsync(yee_t, S->fields, ny1 * sizeof(double), hipMemcpyDeviceToDevice, st));
-        VL_HIP(vl::launch_cell_fields(yee_t, c.nx, c.ny, E_t, B_t, st));
+        VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_t, B_t, st));   // the fields at t
         VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, Uc, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 10,
                                        per_y(c)));
         VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, st));
-        VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 3 * cells, st));
-        VL_HIP(vl::launch_axpby(B_h, B_t, 2.0, -1.0, B_1, 3 * cells, st));
+        // E^1 = 2 E^{t+1/2} - E^t and the same for B (E and B arrays adjacent)
+        VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 6 * cells, st));
     }
     for (int s = 0; s < ns; ++s) {
         const vl_species& sp = c.sp[s];
@@ -413,9 +410,7 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
 
     if (c.dim_x == 2) {
         const long long cells = ctx->cells;
-        const size_t ny1 = yee_doubles(c);
-        double* yee_t = S->work;
-        double* E_t = yee_t + ny1;
+        double* E_t = S->work;
         double* B_t = E_t + 3 * cells;
         double* E_h = B_t + 3 * cells;
         double* B_h = E_h + 3 * cells;
@@ -427,16 +422,15 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         {
             Timed tm(ctx, VL_T_FIELDS, st);
             if (c.fit) {
-                VL_HIP(hipMemcpyAsync(yee_t, S->fields, ny1 * sizeof(double), hipMemcpyDeviceToDevice, st));
-                VL_HIP(vl::launch_cell_fields(yee_t, c.nx, c.ny, E_t, B_t, st));
+                VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_t, B_t, st));   // the fields at t
             }
             const double* mom_t[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
             VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 20,
                                             per_y(c)));
             VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, st));
             if (c.fit) {
-                VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 3 * cells, st));
-                VL_HIP(vl::launch_axpby(B_h, B_t, 2.0, -1.0, B_1, 3 * cells, st));
+                // E^1 = 2 E^{t+1/2} - E^t and the same for B (E and B arrays adjacent)
+                VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 6 * cells, st));
             }
         }
         for (int s = 0; s < ns; ++s) {
