@@ -106,6 +106,19 @@ pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int Nv, fl
     if (max_out) block_max_part(mx, max_out);
 }
 
+// Partial flux a w + cA A + cB B of a cell with value w and neighbour
+// differences Dm (below) and Dp (above), F2 = 2 f_inf: the limited slopes are
+// A = med3(Dp, -r2, 2w) and B = med3(Dm, -2w, r2) with r2 = F2 - 2w taken
+// without its clamp at zero (see the cubic velocity sweeps below).
+template <class T>
+__device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F2) {
+    const T x2 = w + w;
+    const T r2 = F2 - x2;
+    const T A = med3(Dp, -r2, x2);
+    const T B = med3(Dm, -x2, r2);
+    return fma(cA, A, fma(cB, B, a * w));
+}
+
 // ---------------------------------------------------------------------------
 // Fused X(tau) for 2X3V: the x sweep and then the y sweep with one f_inf, in
 // one pass over f.  A thread owns one (v_x, |v_y|, v_z) pair, C adjacent x
@@ -113,11 +126,12 @@ pfc_x_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int Nv, fl
 // doubled pencil (positions 0..ny-1: rows of the +v_y half; ny..2ny-1: rows
 // ny-1..0 of the -v_y half).  Periodic y: two cyclic pencils of ny positions
 // (the +v_y half walked upward, the -v_y half downward); either way every
-// walk runs downwind.  Addresses are a 64-bit row base (the same for all
-// lanes at a position) plus a 32-bit offset within the row (nx * Nv < 2^31,
-// checked on the host).  It walks its segment, x-sweeping the C cells of each position
-// on the fly (a window of C+3 inputs in registers) and feeding the result to
-// the y update, f'(q) = P(q-K) + phi(q-K-1) - phi(q-K) with P the x-swept
+// walk runs downwind.  Addresses are a 64-bit row base plus a 32-bit offset
+// within the row (a row is below 4 GiB, checked on the host); the row of a
+// load is the same in every lane.  It walks its segment, x-sweeping the C
+// cells of each position on the fly (a window of C+3 inputs in registers,
+// the windows of the next three positions in flight) and feeding the result
+// to the y update, f'(q) = P(q-K) + phi(q-K-1) - phi(q-K) with P the x-swept
 // pencil, so the intermediate array never reaches memory.  Per segment the x
 // sweep runs S+3 times for S outputs; the extra rows are re-read from cache.
 // Work order: x strip fastest, so neighbouring strips stream the same rows
@@ -155,89 +169,136 @@ pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, i
         const bool posx = sxd >= 0.0;
         const Shift<T> shx(fabs(sxd));
         const int Kx = shx.K < nx ? (int)shx.K : (int)(shx.K % nx);
-        // window columns, upwind to downwind, as element offsets within a row
-        unsigned coff[C + 3];
-        {
-            int col = posx ? c0 - Kx - 2 : c0 + Kx + C + 1;
-            while (col < 0) col += nx;
-            while (col >= nx) col -= nx;
-#pragma unroll
-            for (int w = 0; w < C + 3; ++w) {
-                coff[w] = (unsigned)col * (unsigned)Nv;
-                col += posx ? 1 : -1;
-                if (col == nx) col = 0;
-                if (col < 0) col = nx - 1;
-            }
-        }
         // y: every pencil moves by sy >= 0 cells in its walking order
         const double syd = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
         const ShiftT<T> shy(syd);
         const int Ky = per ? shy.K % ny : (shy.K < L ? shy.K : shy.K % L);
-        // row (uniform across the wave) and offset in the row of position j
-        auto row_of_pos = [&](int j, unsigned& voff) -> int {
+        // first (upwind) column of the x window
+        int wcol0 = posx ? c0 - Kx - 2 : c0 + Kx + C + 1;
+        while (wcol0 < 0) wcol0 += nx;
+        while (wcol0 >= nx) wcol0 -= nx;
+        // row of position j and whether it holds the -v_y velocity
+        auto row_of_pos = [&](int j, bool& dn) -> int {
             if (per) {
                 int r = (j - h0 * ny) % ny;
                 if (r < 0) r += ny;
-                voff = h0 ? vd : vu;
+                dn = h0 != 0;
                 return h0 ? ny - 1 - r : r;
             }
             j %= L;
             if (j < 0) j += L;
-            voff = j < ny ? vu : vd;
+            dn = j >= ny;
             return j < ny ? j : L - 1 - j;
         };
-        auto load = [&](int j, T (&W)[C + 3]) {
-            unsigned voff;
-            const T* rp = fin + (size_t)row_of_pos(j, voff) * rs + voff;
+        // A load is a wave-uniform row base plus a byte offset within the row
+        // (rows are below 4 GiB, checked on the host).  The offsets of the
+        // window for the half being walked are cached in boff and rebuilt
+        // where the walk crosses into the other half (at most twice a segment).
+        const size_t rowbytes = (size_t)rs * sizeof(T);
+        unsigned boff[C + 3];
+        int bhalf = -1;                               // half cached in boff (uniform)
+        auto load = [&](int j, T (&W)[C + 3]) {      // j is the same in every lane
+            bool dn;
+            const char* base = reinterpret_cast<const char*>(fin) + (size_t)row_of_pos(j, dn) * rowbytes;
+            if ((int)dn != bhalf) {
+                const unsigned v = dn ? vd : vu;
+                int col = wcol0;                      // window columns, upwind to downwind
 #pragma unroll
-            for (int w = 0; w < C + 3; ++w) W[w] = rp[coff[w]];
+                for (int w = 0; w < C + 3; ++w) {
+                    boff[w] = ((unsigned)col * (unsigned)Nv + v) * (unsigned)sizeof(T);
+                    col += posx ? 1 : -1;
+                    if (col == nx) col = 0;
+                    if (col < 0) col = nx - 1;
+                }
+                bhalf = (int)dn;
+            }
+#pragma unroll
+            for (int w = 0; w < C + 3; ++w) W[w] = *reinterpret_cast<const T*>(base + boff[w]);
         };
+        // partial flux without the clamp of r2 at zero: every sweep's input
+        // lies in [0, f_inf] up to rounding (as in the velocity sweeps)
         auto xsweep = [&](const T (&W)[C + 3], T (&P)[C]) {
             T D = W[2] - W[1];
-            T phi_prev = pfc_phi_d(W[1], W[1] - W[0], D, shx.a, shx.ac1, shx.ac2, F2);
+            T phi_prev = sub_cell_flux(W[1], W[1] - W[0], D, shx.a, shx.ac1, shx.ac2, F2);
 #pragma unroll
             for (int r = 0; r < C; ++r) {
                 const T Dn = W[r + 3] - W[r + 2];
-                const T phi_next = pfc_phi_d(W[r + 2], D, Dn, shx.a, shx.ac1, shx.ac2, F2);
+                const T phi_next = sub_cell_flux(W[r + 2], D, Dn, shx.a, shx.ac1, shx.ac2, F2);
                 P[r] = fmax(W[r + 2] + phi_prev - phi_next, T(0));
                 phi_prev = phi_next;
                 D = Dn;
             }
         };
+        const bool full = c0 + C <= nx;               // every column of the strip exists
         const int i1 = i0 + S < iend ? i0 + S : iend;
-        T Wn[C + 3], Pa[C], Pb[C], Pc[C], phi_prev[C];
-        load(i0 - 2, Wn);
-        xsweep(Wn, Pa);
-        load(i0 - 1, Wn);
-        xsweep(Wn, Pb);
-        load(i0, Wn);
-        xsweep(Wn, Pc);
-#pragma unroll
-        for (int r = 0; r < C; ++r) phi_prev[r] = pfc_phi_d(Pb[r], Pb[r] - Pa[r], Pc[r] - Pb[r], shy.a, shy.ac1, shy.ac2, F2);
-        load(i0 + 1, Wn);
-        for (int i = i0; i < i1; ++i) {
-            T Wc[C + 3];
-#pragma unroll
-            for (int w = 0; w < C + 3; ++w) Wc[w] = Wn[w];
-            if (i + 1 < i1) load(i + 2, Wn);           // next position's inputs in flight
-            T Pn[C];
-            xsweep(Wc, Pn);                            // P(i+1)
-            unsigned ovoff;
-            T* op = fout + (size_t)row_of_pos(i + Ky, ovoff) * rs + ovoff;
+        // y state per column: P at the current position, its difference to the
+        // previous one and the flux through the face below it
+        T Pc[C], Dm[C], phy[C];
+        {
+            T Wa[C + 3], Pa[C], Pb[C];
+            load(i0 - 2, Wa);
+            xsweep(Wa, Pa);
+            load(i0 - 1, Wa);
+            xsweep(Wa, Pb);
+            load(i0, Wa);
+            xsweep(Wa, Pc);
 #pragma unroll
             for (int r = 0; r < C; ++r) {
-                const T phi = pfc_phi_d(Pc[r], Pc[r] - Pb[r], Pn[r] - Pc[r], shy.a, shy.ac1, shy.ac2, F2);
-                const T o = fmax(Pc[r] + phi_prev[r] - phi, T(0));
-                const int col = posx ? c0 + r : c0 + C - 1 - r;
-                if (col < nx) {
-                    op[(unsigned)col * (unsigned)Nv] = o;
-                    mx = fmax(mx, o);
-                }
-                phi_prev[r] = phi;
-                Pb[r] = Pc[r];
-                Pc[r] = Pn[r];
+                Dm[r] = Pc[r] - Pb[r];
+                phy[r] = sub_cell_flux(Pb[r], Pb[r] - Pa[r], Dm[r], shy.a, shy.ac1, shy.ac2, F2);
             }
         }
+        // one position: the window Wc (position i+1) is x-swept and the y update
+        // of position i is stored; the window of i+4 is loaded into Wn meanwhile
+        // (three positions of loads stay in flight while one is computed)
+        auto step = [&](int i, const T (&Wc)[C + 3], T (&Wn)[C + 3]) {
+            if (i + 3 < i1) load(i + 4, Wn);
+            T Pn[C];
+            xsweep(Wc, Pn);
+            bool dn;
+            const int ro = row_of_pos(i + Ky, dn);
+            T* op = fout + (size_t)ro * rs + (dn ? vd : vu);
+            T o[C];
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                const T Dn = Pn[r] - Pc[r];
+                const T phi = sub_cell_flux(Pc[r], Dm[r], Dn, shy.a, shy.ac1, shy.ac2, F2);
+                o[r] = fmax(Pc[r] + phy[r] - phi, T(0));
+                phy[r] = phi;
+                Dm[r] = Dn;
+                Pc[r] = Pn[r];
+            }
+            if (full) {
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    op[(unsigned)(posx ? c0 + r : c0 + C - 1 - r) * (unsigned)Nv] = o[r];
+                    mx = max_nonneg(mx, o[r], F2);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    const int col = posx ? c0 + r : c0 + C - 1 - r;
+                    if (col < nx) {
+                        op[(unsigned)col * (unsigned)Nv] = o[r];
+                        mx = max_nonneg(mx, o[r], F2);
+                    }
+                }
+            }
+        };
+        T W0[C + 3], W1[C + 3], W2[C + 3], W3[C + 3];
+        load(i0 + 1, W0);
+        if (i0 + 1 < i1) load(i0 + 2, W1);
+        if (i0 + 2 < i1) load(i0 + 3, W2);
+        int i = i0;
+        for (; i + 3 < i1; i += 4) {                  // four positions: the windows rotate
+            step(i, W0, W3);
+            step(i + 1, W1, W0);
+            step(i + 2, W2, W1);
+            step(i + 3, W3, W2);
+        }
+        if (i < i1) step(i, W0, W3);
+        if (i + 1 < i1) step(i + 1, W1, W0);
+        if (i + 2 < i1) step(i + 2, W2, W1);
     }
     if (max_out) block_max_part(mx, max_out);
 }
@@ -439,14 +500,6 @@ pfc_v3_kernel(const T* fin, T* fout, const double* __restrict__ E, const double*
 // difference, seven operations for the partial flux and three for the update
 // per element.  A wave with both signs keeps the storage order and selects
 // per lane, one operation more.
-template <class T>
-__device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F2) {
-    const T x2 = w + w;
-    const T r2 = F2 - x2;
-    const T A = med3(Dp, -r2, x2);
-    const T B = med3(Dm, -x2, r2);
-    return fma(cA, A, fma(cB, B, a * w));
-}
 
 // Sub-cell sweep of a pencil held in registers (updated in place) whose
 // wave's lanes all shift one way: REV walks it from its far end (s < 0), so
@@ -813,7 +866,7 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
 // x cells per thread (FP32: 8 keeps 4 waves/SIMD; FP64 registers allow 4) and
 // doubled-pencil positions per segment
 template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
-constexpr int kXySeg = 64;
+constexpr int kXySeg = 128;
 template <class T>
 long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz, int per) {
     const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;

@@ -576,8 +576,9 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
             }
         }
         if (nd == 1 && sp.nv[0] > 4096) return VL_ENOTSUP;
-        // the X operators address a row of f (nx velocity blocks) with 32-bit offsets
-        if ((long long)c.nx * sp.nv[0] * sp.nv[1] * sp.nv[2] >= (1LL << 31)) return VL_ENOTSUP;
+        // the X operators address a row of f (nx velocity blocks) with 32-bit
+        // element and byte offsets
+        if ((long long)c.nx * sp.nv[0] * sp.nv[1] * sp.nv[2] * elem >= (1LL << 32)) return VL_ENOTSUP;
         if (nd == 3) {
             // the 34^3 cube (FP32: the block fills one CU's LDS) has its own kernels
             const bool big = sp.nv[0] == vl::kBigCube && sp.nv[1] == vl::kBigCube && sp.nv[2] == vl::kBigCube;

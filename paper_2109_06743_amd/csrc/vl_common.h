@@ -193,6 +193,19 @@ __device__ __forceinline__ T pfc_phi_d(T w, T dm, T dp, T a, T ac1, T ac2, T F2)
     return fma(ac1, lp, fma(ac2, lm, a * w));
 }
 
+// Larger of two values in [0, hi] (none NaN): one median-of-three in FP32,
+// without the quieting of the inputs that fmax carries.
+template <class T>
+__device__ __forceinline__ T max_nonneg(T a, T b, T hi);
+template <>
+__device__ __forceinline__ float max_nonneg<float>(float a, float b, float hi) {
+    return __builtin_amdgcn_fmed3f(a, b, hi);
+}
+template <>
+__device__ __forceinline__ double max_nonneg<double>(double a, double b, double) {
+    return fmax(a, b);
+}
+
 // Split a non-negative displacement of s cells into floor and fraction, with
 // the coefficients of the partial flux (computed in FP64, rounded to T).
 template <class T>

@@ -83,10 +83,12 @@ def test_integer_shift_is_bitwise_exact(dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("nx,ny,nv,tau", [(12, 6, 8, 0.5), (20, 9, 6, 1.7),
-                                          # x strips with a ragged last strip, several y segments
-                                          # of the doubled pencil (2*ny > 32) with a short last one,
-                                          # shifts of more than a cell in x and y
-                                          (37, 41, 6, 2.3), (8, 20, 8, 0.05)])
+                                          # x strips with a ragged last strip, shifts of more
+                                          # than a cell in x and y
+                                          (37, 41, 6, 2.3), (8, 20, 8, 0.05),
+                                          # two y segments of the doubled pencil (2*ny > 128),
+                                          # the last one short
+                                          (37, 75, 6, 2.3)])
 def test_x_sweep_2x3v(dtype, nx, ny, nv, tau):
     import torch
     cfg, _, _ = W.gem(nx=nx, ny=ny, nv=nv, dtype=np.float64)

@@ -1,6 +1,6 @@
 """Periodic y (the Orszag-Tang set-up, Sec. 3.2) against the oracle: the
-fused X operator on a ragged grid (x strips and 64-row segments of both
-cyclic pencils cut short), full steps with moment fitting, and the fluid
+fused X operator on a ragged grid (x strips, and 128-row segments of both
+cyclic pencils with a short last one), full steps with moment fitting, and the fluid
 model alone with the Eq. 5 closure."""
 import numpy as np
 import pytest
@@ -28,7 +28,7 @@ def test_x_operator_periodic(dtype):
     from gpu_util import ensure_lib
     from paper_2109_06743_amd import vl
     ensure_lib()
-    cfg, f, _ = W.orszag_tang(n=20, ny=70, nv=8, dtype=np.float64)
+    cfg, f, _ = W.orszag_tang(n=20, ny=140, nv=8, dtype=np.float64)
     nx, ny = cfg["nx"], cfg["ny"]
     dx = (cfg["x_hi"] - cfg["x_lo"]) / nx
     dy = (cfg["y_hi"] - cfg["y_lo"]) / ny

@@ -85,8 +85,8 @@ def _start_2x3v(cfg, f, F0, dtype):
 @pytest.mark.parametrize("fit", [False, True])
 @pytest.mark.parametrize("shape", [(8, 4, 8), (12, 6, 12), (40, 20, 8)])
 def test_step_2x3v(dtype, fit, shape):
-    """(40, 20, 8): several x strips and y segments of the fused X operator and
-    full plus partial tiles of fluid faces in both directions."""
+    """(40, 20, 8): several x strips of the fused X operator and full plus
+    partial tiles of fluid faces in both directions."""
     from paper_2109_06743_amd import vl
     nx, ny, nv = shape
     cfg, f, F0 = W.gem(nx=nx, ny=ny, nv=nv, dt=0.003, fit=fit, dtype=np.float64)
