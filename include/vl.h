@@ -96,7 +96,8 @@ typedef struct vl_ctx vl_ctx;
  * *cfg; device scratch (a few kilobytes, plus 160 bytes per spatial cell for
  * the 3V moment fitting on its first call) is allocated on first use on the
  * device current at that time and freed by vl_destroy.  Errors: VL_EINVAL (bad geometry, velocity
- * grid not symmetric in v_y for 2X3V), VL_ENOTSUP (unsupported combination). */
+ * grid not symmetric in v_y for 2X3V), VL_ENOTSUP (unsupported combination, or a row of f --
+ * nx velocity blocks -- of 4 GiB or more). */
 vl_status vl_create(const vl_config* cfg, vl_ctx** out);
 vl_status vl_destroy(vl_ctx* ctx);
 
