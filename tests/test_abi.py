@@ -141,3 +141,17 @@ def test_fluid_closure_step_rejects_bad_arguments(lib):
     assert lib.vl_fluid_closure_step(h, ctypes.byref(fs), 0, 0.1, None) == 1
     assert lib.vl_fluid_closure_step(h, None, 0, 0.1, None) == 1
     lib.vl_destroy(h)
+
+
+def test_create_rejects_rows_of_4_gib(lib):
+    """A row of f (nx velocity blocks) is addressed with 32-bit byte offsets."""
+    sp = [dict(q=-1.0, m=0.04, v_lo=[-1.0] * 3, v_hi=[1.0] * 3, nv=[16] * 3)]
+    cfg = dict(kind="2x3v", nx=131071, ny=2, x_lo=0.0, x_hi=1.0, y_lo=-1.0, y_hi=1.0, c=20.0, fit=True, species=sp)
+    st, h = _create(cfg, "f64")                      # 131071 * 4096 * 8 B < 4 GiB
+    assert st == 0
+    lib.vl_destroy(h)
+    assert _create(dict(cfg, nx=131072), "f64")[0] == 3
+    st, h = _create(dict(cfg, nx=262143), "f32")
+    assert st == 0
+    lib.vl_destroy(h)
+    assert _create(dict(cfg, nx=262144), "f32")[0] == 3
