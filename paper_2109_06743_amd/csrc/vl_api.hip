@@ -39,10 +39,6 @@ struct vl_ctx {
     void* bpart = nullptr;
     unsigned* bclip = nullptr;
     long long max_blocks = 0;
-    // second stream of the 2X3V step (field half step and fluid steps) and the
-    // events that order it against the caller's stream, created on first use
-    hipStream_t side = nullptr;
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     char err[512] = {0};
 };
 
@@ -129,22 +125,6 @@ vl_status ensure_device(vl_ctx* ctx) {
     ctx->dft = (double*)(ctx->slots + kSlots * VL_MAX_SPECIES);
     ctx->part = ctx->dft + 2 * (size_t)ctx->cfg.nx + 2;
     ctx->device = dev;
-    return VL_OK;
-}
-
-// The step's second stream (default priority) and its ordering events, on
-// the context's device.
-vl_status ensure_side(vl_ctx* ctx) {
-    if (ctx->side) return VL_OK;
-    hipStream_t sd = nullptr;
-    VL_HIP(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
-    for (hipEvent_t& e : ctx->ev) {
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            (void)hipStreamDestroy(sd);
-            return fail(ctx, VL_EDEVICE, "hipEventCreateWithFlags failed");
-        }
-    }
-    ctx->side = sd;
     return VL_OK;
 }
 
@@ -439,62 +419,35 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         double* fwork = B_1 + 3 * cells;
         double* mwork = fwork + fluid_doubles(c);
         mwork += ((uintptr_t)mwork & 15u) ? 1 : 0;         // network outputs are stored as 16-byte vectors
-        // With the kinetic closure the field half step and each species' fluid
-        // step run on a second stream: the fields overlap the first X(dt/2),
-        // a fluid step the next species' operators or the previous fit.  ev[0]:
-        // inputs ready; ev[1]: fields at t + 1/2; ev[2 + s]: moments of
-        // f^{t+1}; ev[4 + s]: fluid state at t + 1.
-        const bool fork = c.fit && c.closure != VL_CLOSURE_MLP;
-        hipStream_t fs = st;
-        if (fork) {
-            if ((r = ensure_side(ctx)) != VL_OK) return r;
-            fs = ctx->side;
-            VL_HIP(hipEventRecord(ctx->ev[0], st));
-            VL_HIP(hipStreamWaitEvent(fs, ctx->ev[0], 0));
-        }
         {
-            Timed tm(ctx, VL_T_FIELDS, fs);
+            Timed tm(ctx, VL_T_FIELDS, st);
             if (c.fit) {
-                VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_t, B_t, fs));   // the fields at t
+                VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_t, B_t, st));   // the fields at t
             }
             const double* mom_t[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
-            VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t, q, ns, dt, c.c, dx_of(c), dy_of(c), fs, 20,
+            VL_HIP(vl::launch_maxwell_half(S->fields, c.nx, c.ny, mom_t, q, ns, dt, c.c, dx_of(c), dy_of(c), st, 20,
                                             per_y(c)));
-            VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, fs));
+            VL_HIP(vl::launch_cell_fields(S->fields, c.nx, c.ny, E_h, B_h, st));
             if (c.fit) {
                 // E^1 = 2 E^{t+1/2} - E^t and the same for B (E and B arrays adjacent)
-                VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 6 * cells, fs));
+                VL_HIP(vl::launch_axpby(E_h, E_t, 2.0, -1.0, E_1, 6 * cells, st));
             }
         }
-        if (fork) VL_HIP(hipEventRecord(ctx->ev[1], fs));
-        // The kinetic operators over the species: X(dt/2) f -> tmp and V(dt)
-        // in place for every species, then per species X(dt/2) tmp -> f, the
-        // moments of f^{t+1} and the fluid step, then the fits.  On the second
-        // stream the first fluid step overlaps the next species' X(dt/2), the
-        // second one the first fit.
-        for (int s = 0; s < ns; ++s)
-            if ((r = advect_x_typed<T>(ctx, s, (T*)S->f[s], (T*)S->f_tmp[s], nullptr, 0.5 * dt, slot(ctx, 0, s),
-                                       nullptr, slot(ctx, 1, s), st)) != VL_OK)
-                return r;
-        if (fork) VL_HIP(hipStreamWaitEvent(st, ctx->ev[1], 0));
-        for (int s = 0; s < ns; ++s)
-            if ((r = advect_v_typed<T>(ctx, s, (T*)S->f_tmp[s], (T*)S->f_tmp[s], E_h, B_h, dt, slot(ctx, 1, s),
-                                       slot(ctx, 2, s), st)) != VL_OK)
-                return r;
         for (int s = 0; s < ns; ++s) {
             T* f = (T*)S->f[s];
-            if ((r = advect_x_typed<T>(ctx, s, (T*)S->f_tmp[s], f, nullptr, 0.5 * dt, slot(ctx, 2, s), nullptr,
+            T* tmp = (T*)S->f_tmp[s];
+            // X(dt/2): f -> tmp; V(dt): tmp in place; X(dt/2): tmp -> f
+            if ((r = advect_x_typed<T>(ctx, s, f, tmp, nullptr, 0.5 * dt, slot(ctx, 0, s), nullptr, slot(ctx, 1, s),
+                                       st)) != VL_OK)
+                return r;
+            if ((r = advect_v_typed<T>(ctx, s, tmp, tmp, E_h, B_h, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) !=
+                VL_OK)
+                return r;
+            if ((r = advect_x_typed<T>(ctx, s, tmp, f, nullptr, 0.5 * dt, slot(ctx, 2, s), nullptr,
                                        c.fit ? nullptr : slot(ctx, 0, s), st)) != VL_OK)
                 return r;
             if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
-            if (fork) {
-                VL_HIP(hipEventRecord(ctx->ev[2 + s], st));
-                VL_HIP(hipStreamWaitEvent(fs, ctx->ev[2 + s], 0));
-                if ((r = fluid_step_impl(ctx, s, S->U[s], S->mom_post[s], S->mom_pre[s], E_t, B_t, E_1, B_1, E_h, B_h,
-                                         dt, fwork, fs)) != VL_OK)
-                    return r;
-                VL_HIP(hipEventRecord(ctx->ev[4 + s], fs));
-            } else if (c.fit) {
+            if (c.fit) {
                 if (c.closure == VL_CLOSURE_MLP)
                     r = fluid_step_mlp(ctx, s, S, E_t, B_t, E_1, B_1, E_h, B_h, dt, fwork, mwork, st);
                 else
@@ -509,12 +462,6 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
                 VL_HIP(hipMemcpyAsync(S->mom_post[s], S->mom_pre[s], cells * 20 * sizeof(double),
                                       hipMemcpyDeviceToDevice, st));
             }
-        }
-        for (int s = 0; fork && s < ns; ++s) {
-            VL_HIP(hipStreamWaitEvent(st, ctx->ev[4 + s], 0));
-            if ((r = fit_typed<T>(ctx, s, (T*)S->f[s], (T*)S->f[s], S->mom_pre[s], S->U[s], S->mom_post[s],
-                                  S->counters, slot(ctx, 0, s), st)) != VL_OK)
-                return r;
         }
         const double* mom_t1[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
         Timed tm(ctx, VL_T_FIELDS, st);
@@ -678,12 +625,6 @@ vl_status vl_destroy(vl_ctx* ctx) {
     if (ctx->slots) (void)hipFree(ctx->slots);
     if (ctx->fit_scratch) (void)hipFree(ctx->fit_scratch);
     if (ctx->bpart) (void)hipFree(ctx->bpart);
-    if (ctx->side) {
-        (void)hipStreamSynchronize(ctx->side);
-        (void)hipStreamDestroy(ctx->side);
-    }
-    for (hipEvent_t e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
     delete ctx;
     return VL_OK;
 }
