@@ -123,10 +123,16 @@ __device__ __forceinline__ double stage_comp(const double* U, const double* QA, 
     return v;
 }
 
+// Species sp = blockIdx.y of the set.
 __global__ void __launch_bounds__(kFaceThreads)
-faces3_kernel(const double* __restrict__ U, const double* __restrict__ QA, const double* __restrict__ QB, double wa,
-              double wb, FluidArgs A, int nbx_row, int nbx, int nby_col, double* __restrict__ Hx,
-              double* __restrict__ Hy) {
+faces3_kernel(FluidSet S, double wa, double wb, FluidArgs A, int nbx_row, int nbx, int nby_col) {
+    const int sp = blockIdx.y;
+    const double* __restrict__ U = S.Us[sp];
+    const double* __restrict__ QA = S.QA[sp];
+    const double* __restrict__ QB = S.QB[sp];
+    double* __restrict__ Hx = S.Hx[sp];
+    double* __restrict__ Hy = S.Hy[sp];
+    A.m = S.m[sp];
     __shared__ double raw[kStageCells][20];
     __shared__ double lo[kRecCells][20], hi[kRecCells][20];   // point values at a cell's lower / upper face
     __shared__ double spd[2][kXTile];
@@ -232,11 +238,16 @@ __device__ __forceinline__ void temperature_at(const double* __restrict__ U, int
 // Temperature-gradient closure of Eq. 5 as a source of the second moment:
 // S = -div Q = gchi n v_t lap T (gchi = chi / k0), lap by central second
 // differences, x periodic, y walls mirrored; S[cells][6] in PAIRS order.
-__global__ void closure_source3_kernel(const double* __restrict__ Us, FluidArgs A, double gchi,
-                                       double* __restrict__ S) {
+// Species blockIdx.z of the set; species without the closure are skipped.
+__global__ void closure_source3_kernel(FluidSet Set, FluidArgs A) {
+    const int sp = blockIdx.z;
+    const double gchi = Set.gchi[sp];
+    const double* __restrict__ Us = Set.Us[sp];
+    double* __restrict__ S = Set.Sg[sp];
+    A.m = Set.m[sp];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
-    if (i >= A.nx) return;
+    if (i >= A.nx || gchi == 0.0) return;
     double Tc[6], T1[6], T2[6], lx[6];
     temperature_at(Us, j, i, A, Tc);
     temperature_at(Us, j, i + 1, A, T1);
@@ -254,12 +265,20 @@ __global__ void closure_source3_kernel(const double* __restrict__ Us, FluidArgs 
 }
 
 // U_out = a U_n + b (U_s + dt L(U_s)); U_out may alias U_n (each cell reads
-// only its own U_n entry) but not U_s.  Sg (or null): an extra source of the
-// second moment, [cells][6].
-__global__ void update3_kernel(const double* __restrict__ Us, const double* Un, double* Uout,
-                               const double* __restrict__ Hx, const double* __restrict__ Hy,
-                               const double* __restrict__ E, const double* __restrict__ B, double a, double b,
-                               double dt, FluidArgs A, const double* __restrict__ Sg) {
+// only its own U_n entry) but not U_s.  Where the species has the Eq. 5
+// closure, Sg is an extra source of the second moment, [cells][6].  Species
+// blockIdx.z of the set.
+__global__ void update3_kernel(FluidSet S, const double* __restrict__ E, const double* __restrict__ B, double a,
+                               double b, double dt, FluidArgs A) {
+    const int sp = blockIdx.z;
+    const double* __restrict__ Us = S.Us[sp];
+    const double* Un = S.Un[sp];
+    double* Uout = S.Uo[sp];
+    const double* __restrict__ Hx = S.Hx[sp];
+    const double* __restrict__ Hy = S.Hy[sp];
+    const double* __restrict__ Sg = S.gchi[sp] != 0.0 ? S.Sg[sp] : nullptr;
+    A.m = S.m[sp];
+    A.q = S.q[sp];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= A.nx) return;
@@ -385,29 +404,81 @@ __global__ void update1_kernel(const double* __restrict__ Us, const double* Un, 
 }
 
 // -------------------------------------------------------------- launchers --
-// One SSP-RK3 step.  work: U1, U2 (10 or 3 doubles per cell each), Hx, Hy.
+// One SSP-RK3 step of ns species (one launch per kernel for all of them).
+// work: per species U1, U2 (10 doubles per cell each), Hx (10 per cell), Hy
+// (10 per face of ny + 1 rows), fluid_rk3_3v_doubles(nx, ny) in all.
+hipError_t launch_fluid_rk3_3v_set(int ns, double* const* U, const double* const* mom_t, const double* const* mom_t1,
+                                   const double* E_t, const double* B_t, const double* E_t1, const double* B_t1,
+                                   const double* E_th, const double* B_th, double dt, int nx, int ny, const double* q,
+                                   const double* m, double dx, double dy, double* work, hipStream_t st, int per) {
+    if (ns < 1 || ns > 2) return hipErrorInvalidValue;
+    const long long cells = (long long)nx * ny;
+    FluidSet S[3] = {};
+    for (int s = 0; s < ns; ++s) {
+        double* w = work + (size_t)s * fluid_rk3_3v_doubles(nx, ny);
+        double* U1 = w;
+        double* U2 = U1 + cells * 10;
+        double* Hx = U2 + cells * 10;
+        double* Hy = Hx + cells * 10;
+        const double* Us[3] = {U[s], U1, U2};
+        double* Uo[3] = {U1, U2, U[s]};
+        const double* QA[3] = {mom_t[s], mom_t1[s], mom_t[s]};
+        const double* QB[3] = {mom_t[s], mom_t1[s], mom_t1[s]};
+        for (int k = 0; k < 3; ++k) {
+            S[k].Us[s] = Us[k];
+            S[k].Un[s] = U[s];
+            S[k].Uo[s] = Uo[k];
+            S[k].QA[s] = QA[k];
+            S[k].QB[s] = QB[k];
+            S[k].Hx[s] = Hx;
+            S[k].Hy[s] = Hy;
+            S[k].Sg[s] = nullptr;
+            S[k].m[s] = m[s];
+            S[k].q[s] = q[s];
+            S[k].gchi[s] = 0.0;
+        }
+    }
+    const double wa[3] = {1.0, 1.0, 0.5}, wb[3] = {0.0, 0.0, 0.5};
+    const double* E[3] = {E_t, E_t1, E_th};
+    const double* B[3] = {B_t, B_t1, B_th};
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int k = 0; k < 3; ++k) {
+        const hipError_t e = launch_fluid_stage_3v_set(S[k], ns, wa[k], wb[k], E[k], B[k], a[k], b[k], dt, nx, ny,
+                                                       dx, dy, st, per);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom_t1, const double* E_t,
                                const double* B_t, const double* E_t1, const double* B_t1, const double* E_th,
                                const double* B_th, double dt, int nx, int ny, double q, double m, double dx,
                                double dy, double* work, hipStream_t st, int per) {
-    const long long cells = (long long)nx * ny;
-    double* U1 = work;
-    double* U2 = U1 + cells * 10;
-    double* Hx = U2 + cells * 10;
-    double* Hy = Hx + cells * 10;
-    struct Stage { const double* Us; const double* Un; double* Uo; const double* QA; const double* QB; double wa, wb;
-                   const double* E; const double* B; double a, b; };
-    const Stage S[3] = {
-        {U, U, U1, mom_t, mom_t, 1.0, 0.0, E_t, B_t, 0.0, 1.0},
-        {U1, U, U2, mom_t1, mom_t1, 1.0, 0.0, E_t1, B_t1, 0.75, 0.25},
-        {U2, U, U, mom_t, mom_t1, 0.5, 0.5, E_th, B_th, 1.0 / 3.0, 2.0 / 3.0},
-    };
-    for (int k = 0; k < 3; ++k) {
-        const hipError_t e = launch_fluid_stage_3v(S[k].Us, S[k].Un, S[k].Uo, S[k].QA, S[k].QB, S[k].wa, S[k].wb,
-                                                   S[k].E, S[k].B, S[k].a, S[k].b, dt, nx, ny, q, m, dx, dy, Hx, Hy,
-                                                   st, 0.0, nullptr, per);
-        if (e != hipSuccess) return e;
+    double* Ul[1] = {U};
+    const double* mt[1] = {mom_t};
+    const double* mt1[1] = {mom_t1};
+    return launch_fluid_rk3_3v_set(1, Ul, mt, mt1, E_t, B_t, E_t1, B_t1, E_th, B_th, dt, nx, ny, &q, &m, dx, dy, work,
+                                   st, per);
+}
+
+hipError_t launch_fluid_stage_3v_set(const FluidSet& S, int ns, double wa, double wb, const double* E,
+                                     const double* B, double a, double b, double dt, int nx, int ny, double dx,
+                                     double dy, hipStream_t st, int per) {
+    if (ns < 1 || ns > 2) return hipErrorInvalidValue;
+    FluidArgs A{nx, ny, 0.0, 0.0, 1.0 / dx, 1.0 / dy, per};
+    dim3 blk(64), gc((nx + 63) / 64, ny, ns);
+    const int nbx_row = (nx + kXTile - 1) / kXTile;
+    const int nby_col = (nx + kYCols - 1) / kYCols;
+    const int nbx = nbx_row * ny, nby = nby_col * ((ny + 1 + kYRows - 1) / kYRows);
+    hipLaunchKernelGGL(faces3_kernel, dim3(nbx + nby, ns), dim3(kFaceThreads), 0, st, S, wa, wb, A, nbx_row, nbx,
+                       nby_col);
+    bool grad = false;
+    for (int s = 0; s < ns; ++s) {
+        if (S.gchi[s] != 0.0 && !S.Sg[s]) return hipErrorInvalidValue;
+        grad = grad || S.gchi[s] != 0.0;
     }
+    if (grad) hipLaunchKernelGGL(closure_source3_kernel, gc, blk, 0, st, S, A);
+    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, S, E, B, a, b, dt, A);
     return hipGetLastError();
 }
 
@@ -415,21 +486,19 @@ hipError_t launch_fluid_stage_3v(const double* Us, const double* Un, double* Uo,
                                  double wa, double wb, const double* E, const double* B, double a, double b, double dt,
                                  int nx, int ny, double q, double m, double dx, double dy, double* Hx, double* Hy,
                                  hipStream_t st, double gchi, double* Sg, int per) {
-    FluidArgs A{nx, ny, m, q, 1.0 / dx, 1.0 / dy, per};
-    dim3 blk(64), gc((nx + 63) / 64, ny);
-    const int nbx_row = (nx + kXTile - 1) / kXTile;
-    const int nby_col = (nx + kYCols - 1) / kYCols;
-    const int nbx = nbx_row * ny, nby = nby_col * ((ny + 1 + kYRows - 1) / kYRows);
-    hipLaunchKernelGGL(faces3_kernel, dim3(nbx + nby), dim3(kFaceThreads), 0, st, Us, QA, QB, wa, wb, A, nbx_row,
-                       nbx, nby_col, Hx, Hy);
-    const bool grad = gchi != 0.0;
-    if (grad) {
-        if (!Sg) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(closure_source3_kernel, gc, blk, 0, st, Us, A, gchi, Sg);
-    }
-    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, Us, Un, Uo, Hx, Hy, E, B, a, b, dt, A,
-                       (const double*)(grad ? Sg : nullptr));
-    return hipGetLastError();
+    FluidSet S{};
+    S.Us[0] = Us;
+    S.Un[0] = Un;
+    S.Uo[0] = Uo;
+    S.QA[0] = QA;
+    S.QB[0] = QB;
+    S.Hx[0] = Hx;
+    S.Hy[0] = Hy;
+    S.Sg[0] = Sg;
+    S.m[0] = m;
+    S.q[0] = q;
+    S.gchi[0] = gchi;
+    return launch_fluid_stage_3v_set(S, 1, wa, wb, E, B, a, b, dt, nx, ny, dx, dy, st, per);
 }
 
 hipError_t launch_qcal_q0(const double* U, long long cells, double m, double* qc, hipStream_t st) {

@@ -141,8 +141,7 @@ size_t yee_doubles(const vl_config& c) {
 }
 
 size_t fluid_doubles(const vl_config& c) {
-    const size_t cells = (size_t)c.nx * c.ny;
-    if (c.dim_v == 3) return 30 * cells + 10 * (size_t)c.nx * (c.ny + 1);
+    if (c.dim_v == 3) return vl::fluid_rk3_3v_doubles(c.nx, c.ny);
     return 9 * (size_t)c.nx;
 }
 
@@ -165,7 +164,8 @@ size_t fluid_closure_doubles(const vl_config& c) {
 
 size_t step_doubles(const vl_config& c) {
     const size_t cells = (size_t)c.nx * c.ny;
-    if (c.dim_v == 3) return 18 * cells + fluid_doubles(c) + mlp_step_doubles(c);
+    // the fluid steps of all species run together (a fluid scratch each)
+    if (c.dim_v == 3) return 18 * cells + (size_t)c.nspecies * fluid_doubles(c) + mlp_step_doubles(c);
     return 4 * (size_t)c.nx + 3 * (size_t)c.nx + fluid_doubles(c);
 }
 
@@ -417,7 +417,7 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         double* E_1 = B_h + 3 * cells;
         double* B_1 = E_1 + 3 * cells;
         double* fwork = B_1 + 3 * cells;
-        double* mwork = fwork + fluid_doubles(c);
+        double* mwork = fwork + (size_t)ns * fluid_doubles(c);
         mwork += ((uintptr_t)mwork & 15u) ? 1 : 0;         // network outputs are stored as 16-byte vectors
         {
             Timed tm(ctx, VL_T_FIELDS, st);
@@ -447,21 +447,31 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
                                        c.fit ? nullptr : slot(ctx, 0, s), st)) != VL_OK)
                 return r;
             if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
-            if (c.fit) {
-                if (c.closure == VL_CLOSURE_MLP)
-                    r = fluid_step_mlp(ctx, s, S, E_t, B_t, E_1, B_1, E_h, B_h, dt, fwork, mwork, st);
-                else
-                    r = fluid_step_impl(ctx, s, S->U[s], S->mom_post[s], S->mom_pre[s], E_t, B_t, E_1, B_1, E_h, B_h,
-                                        dt, fwork, st);
-                if (r != VL_OK) return r;
-                if ((r = fit_typed<T>(ctx, s, f, f, S->mom_pre[s], S->U[s], S->mom_post[s], S->counters,
-                                      slot(ctx, 0, s), st)) != VL_OK)
-                    return r;
-            } else {
+            if (!c.fit) {
                 Timed tm(ctx, VL_T_COPY, st);
                 VL_HIP(hipMemcpyAsync(S->mom_post[s], S->mom_pre[s], cells * 20 * sizeof(double),
                                       hipMemcpyDeviceToDevice, st));
             }
+        }
+        if (c.fit) {
+            // the fluid steps of all species (one launch per kernel with the
+            // kinetic closure), then the fits
+            if (c.closure == VL_CLOSURE_MLP) {
+                for (int s = 0; s < ns; ++s)
+                    if ((r = fluid_step_mlp(ctx, s, S, E_t, B_t, E_1, B_1, E_h, B_h, dt, fwork, mwork, st)) != VL_OK)
+                        return r;
+            } else {
+                Timed tm(ctx, VL_T_FLUID, st);
+                const double ms[2] = {c.sp[0].m, ns > 1 ? c.sp[1].m : 1.0};
+                const double* mt[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
+                const double* mt1[2] = {S->mom_pre[0], ns > 1 ? S->mom_pre[1] : nullptr};
+                VL_HIP(vl::launch_fluid_rk3_3v_set(ns, S->U, mt, mt1, E_t, B_t, E_1, B_1, E_h, B_h, dt, c.nx, c.ny, q,
+                                                   ms, dx_of(c), dy_of(c), fwork, st, per_y(c)));
+            }
+            for (int s = 0; s < ns; ++s)
+                if ((r = fit_typed<T>(ctx, s, (T*)S->f[s], (T*)S->f[s], S->mom_pre[s], S->U[s], S->mom_post[s],
+                                      S->counters, slot(ctx, 0, s), st)) != VL_OK)
+                    return r;
         }
         const double* mom_t1[2] = {S->mom_post[0], ns > 1 ? S->mom_post[1] : nullptr};
         Timed tm(ctx, VL_T_FIELDS, st);

@@ -88,6 +88,31 @@ hipError_t launch_field_energy(const double* fields, int dim_x, int nx, int ny, 
 hipError_t launch_axpby(const double* x, const double* y, double a, double b, double* out, long long n,
                         hipStream_t st);
 
+// Per-species operands of one fluid stage: up to two species per launch.
+struct FluidSet {
+    const double* Us[2];
+    const double* Un[2];
+    double* Uo[2];
+    const double* QA[2];
+    const double* QB[2];
+    double* Hx[2];
+    double* Hy[2];
+    double* Sg[2];        // Eq. 5 source scratch, [cells][6] (needed where gchi != 0)
+    double m[2], q[2], gchi[2];
+};
+
+// Scratch of one species' SSP-RK3 step of the 3V fluid (doubles).
+inline size_t fluid_rk3_3v_doubles(int nx, int ny) { return 30 * (size_t)nx * ny + 10 * (size_t)nx * (ny + 1); }
+
+// One SSP-RK3 step of ns (1 or 2) species, each kernel launched once for all
+// of them; work: ns * fluid_rk3_3v_doubles(nx, ny) doubles.
+hipError_t launch_fluid_rk3_3v_set(int ns, double* const* U, const double* const* mom_t, const double* const* mom_t1,
+                                   const double* E_t, const double* B_t, const double* E_t1, const double* B_t1,
+                                   const double* E_th, const double* B_th, double dt, int nx, int ny, const double* q,
+                                   const double* m, double dx, double dy, double* work, hipStream_t st, int per);
+hipError_t launch_fluid_stage_3v_set(const FluidSet& S, int ns, double wa, double wb, const double* E,
+                                     const double* B, double a, double b, double dt, int nx, int ny, double dx,
+                                     double dy, hipStream_t st, int per);
 hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom_t1, const double* E_t,
                                const double* B_t, const double* E_t1, const double* B_t1, const double* E_th,
                                const double* B_th, double dt, int nx, int ny, double q, double m, double dx,
