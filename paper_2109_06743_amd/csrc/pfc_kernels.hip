@@ -628,36 +628,47 @@ __device__ __forceinline__ void sweep_coeffs(int d, double sigma, const V3Params
     s2 = (T)d2;
 }
 
+// One pencil of the cubic block along d (d = 0: (iy, iz); 1: (ix, iz); 2:
+// (ix, iy)) with its shift split as pos / sh.
+template <class T, int N>
+__device__ __forceinline__ void sweep_cube_pencil(T* blk, int d, int pen, bool pos, const ShiftT<T>& sh, T F2) {
+    constexpr int PZ = N | 1;
+    const int stride = d == 0 ? N * PZ : (d == 1 ? PZ : 1);
+    const int i1 = pen / N, i2 = pen % N;
+    const int base = d == 0 ? i1 * PZ + i2 : (d == 1 ? i1 * N * PZ + i2 : (i1 * N + i2) * PZ);
+    if (__all(sh.K == 0)) {
+        T* pb = blk + base;
+        T g[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) g[m] = pb[m * stride];
+        if (__all(pos))
+            regs_one_way<T, N, false>(g, sh.a, sh.ac1, sh.ac2, F2);
+        else if (__all(!pos))
+            regs_one_way<T, N, true>(g, sh.a, sh.ac1, sh.ac2, F2);
+        else
+            regs_mixed<T, N>(g, pos, sh.a, sh.ac1, sh.ac2, F2);
+#pragma unroll
+        for (int m = 0; m < N; ++m) pb[m * stride] = g[m];
+    } else {
+        const int K = sh.K > N + 2 ? N + 2 : sh.K;
+        const int first = pos ? base : base + (N - 1) * stride;
+        pencil_shifted<T, N>(blk, first, pos ? stride : -stride, K, sh.a, sh.ac1, sh.ac2, F2);
+    }
+}
+
+// Shift of pencil pen of sweep d from the sweep's coefficients.
+template <class T, int N>
+__device__ __forceinline__ T cube_pencil_shift(int pen, T s0, T s1, T s2) {
+    return fma(s1, (T)(pen / N), fma(s2, (T)(pen % N), s0));
+}
+
 template <class T, int N>
 __device__ __forceinline__ void sweep_cube(T* blk, int d, double sigma, const V3Params& P, const double* EB, T F2) {
-    constexpr int PZ = N | 1;
     T s0, s1, s2;
     sweep_coeffs<T>(d, sigma, P, EB, s0, s1, s2);
-    const int stride = d == 0 ? N * PZ : (d == 1 ? PZ : 1);
     for (int pen = threadIdx.x; pen < N * N; pen += blockDim.x) {
-        const int i1 = pen / N, i2 = pen % N;
-        const int base = d == 0 ? i1 * PZ + i2 : (d == 1 ? i1 * N * PZ + i2 : (i1 * N + i2) * PZ);
-        const T s = fma(s1, (T)i1, fma(s2, (T)i2, s0));
-        const bool pos = s >= T(0);
-        const ShiftT<T> sh(fabs(s));
-        if (__all(sh.K == 0)) {
-            T* pb = blk + base;
-            T g[N];
-#pragma unroll
-            for (int m = 0; m < N; ++m) g[m] = pb[m * stride];
-            if (__all(pos))
-                regs_one_way<T, N, false>(g, sh.a, sh.ac1, sh.ac2, F2);
-            else if (__all(!pos))
-                regs_one_way<T, N, true>(g, sh.a, sh.ac1, sh.ac2, F2);
-            else
-                regs_mixed<T, N>(g, pos, sh.a, sh.ac1, sh.ac2, F2);
-#pragma unroll
-            for (int m = 0; m < N; ++m) pb[m * stride] = g[m];
-        } else {
-            const int K = sh.K > N + 2 ? N + 2 : sh.K;
-            const int first = pos ? base : base + (N - 1) * stride;
-            pencil_shifted<T, N>(blk, first, pos ? stride : -stride, K, sh.a, sh.ac1, sh.ac2, F2);
-        }
+        const T s = cube_pencil_shift<T, N>(pen, s0, s1, s2);
+        sweep_cube_pencil<T, N>(blk, d, pen, s >= T(0), ShiftT<T>(fabs(s)), F2);
     }
 }
 
@@ -711,12 +722,22 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
             for (int k = 0; k < N; ++k) blk[xb + k * XS] = g[k];
         }
         __syncthreads();
-        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
-        __syncthreads();
-        sweep_cube<T, N>(blk, 2, P.tau, P, EB, F2);
-        __syncthreads();
-        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
-        __syncthreads();
+        // one v_y and one v_z pencil per thread: their shifts are set up once,
+        // the v_y one serving both v_y sweeps
+        {
+            T c0, c1, c2;
+            sweep_coeffs<T>(1, half, P, EB, c0, c1, c2);
+            const T sy = cube_pencil_shift<T, N>(t, c0, c1, c2);
+            sweep_coeffs<T>(2, P.tau, P, EB, c0, c1, c2);
+            const T sz = cube_pencil_shift<T, N>(t, c0, c1, c2);
+            const ShiftT<T> shy(fabs(sy)), shz(fabs(sz));
+            if (own) sweep_cube_pencil<T, N>(blk, 1, t, sy >= T(0), shy, F2);
+            __syncthreads();
+            if (own) sweep_cube_pencil<T, N>(blk, 2, t, sz >= T(0), shz, F2);
+            __syncthreads();
+            if (own) sweep_cube_pencil<T, N>(blk, 1, t, sy >= T(0), shy, F2);
+            __syncthreads();
+        }
         if (own) {
 #pragma unroll
             for (int k = 0; k < N; ++k) g[k] = blk[xb + k * XS];

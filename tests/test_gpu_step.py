@@ -127,3 +127,20 @@ def test_step_conserves_mass_and_is_deterministic(dtype):
         runs.append([x.clone() for x in st.f] + [st.fields.clone()])
     for a, b in zip(*runs):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_step_2x3v_one_species(dtype):
+    """Electrons alone (the fluid kernels launched for a set of one species
+    inside the step), three steps with moment fitting against the oracle."""
+    from paper_2109_06743_amd import vl
+    cfg, f, F0 = W.gem(nx=12, ny=6, nv=8, dt=0.003, fit=True, dtype=np.float64)
+    cfg = dict(cfg, species=cfg["species"][:1])
+    ctx, st, ref = _start_2x3v(cfg, f[:1], F0, dtype)
+    for k in range(3):
+        ctx.step(st, cfg["dt"])
+        ref = OS.step_2x3v(ref, cfg, cfg["dt"])
+        ctx.sync()
+        got = host(st.f[0], ref["f"][0].shape)
+        assert rel_l2(got, ref["f"][0]) < TOL_STEP[dtype] * (k + 1), k
+        assert rel_l2(host(st.U[0], ref["U"][0].shape), ref["U"][0]) < (1e-5 if dtype == "f32" else 1e-12), k
