@@ -583,14 +583,14 @@ __device__ __attribute__((noinline)) void pencil_shifted(T* blk, int first, int 
     blk[q] = fmax(top + phi_prev, T(0));
 }
 
-// One PFC sweep of a pencil held in registers with displacement s (cells).
+// One PFC sweep of a pencil held in registers, its displacement split into
+// its sign pos and the shift sh (cells).
 // Shifts of a cell or more (any lane of the wave) go through the pencil's own
 // cells blk[base + m stride] of the shared block, which no other thread
 // touches meanwhile.
 template <class T, int N>
-__device__ __forceinline__ void sweep_pencil_regs(T (&g)[N], T s, T F2, T* blk, int base, int stride) {
-    const bool pos = s >= T(0);
-    const ShiftT<T> sh(fabs(s));
+__device__ __forceinline__ void sweep_pencil_regs(T (&g)[N], bool pos, const ShiftT<T>& sh, T F2, T* blk, int base,
+                                                  int stride) {
     if (__all(sh.K == 0) && __all(pos)) {
         regs_one_way<T, N, false>(g, sh.a, sh.ac1, sh.ac2, F2);
     } else if (__all(sh.K == 0) && __all(!pos)) {
@@ -713,11 +713,13 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
         T xs0, xs1, xs2;
         sweep_coeffs<T>(0, half, P, eb, xs0, xs1, xs2);
         const T sx = fma(xs1, (T)(t / N), fma(xs2, (T)(t % N), xs0));
+        const bool posx = sx >= T(0);
+        const ShiftT<T> shx(fabs(sx));         // both v_x sweeps
         T g[N];
         if (own) {
 #pragma unroll
             for (int k = 0; k < N; ++k) g[k] = __builtin_nontemporal_load(src + t + k * N * N);
-            sweep_pencil_regs<T, N>(g, sx, F2, blk, xb, XS);
+            sweep_pencil_regs<T, N>(g, posx, shx, F2, blk, xb, XS);
 #pragma unroll
             for (int k = 0; k < N; ++k) blk[xb + k * XS] = g[k];
         }
@@ -741,7 +743,7 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
         if (own) {
 #pragma unroll
             for (int k = 0; k < N; ++k) g[k] = blk[xb + k * XS];
-            sweep_pencil_regs<T, N>(g, sx, F2, blk, xb, XS);
+            sweep_pencil_regs<T, N>(g, posx, shx, F2, blk, xb, XS);
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 __builtin_nontemporal_store(g[k], dst + t + k * N * N);
