@@ -185,9 +185,17 @@ __device__ __forceinline__ bool local_nuT(const double* __restrict__ M, int stri
     return true;
 }
 
+// Species blockIdx.z of the set (species index s0 + blockIdx.z); its
+// features and scales are stored after those of the set's earlier species.
 __global__ void __launch_bounds__(64)
-mlp_features_kernel(const double* __restrict__ M, int stride, const double* __restrict__ B, int nx, int ny,
-                    double m, int species, unsigned short* __restrict__ x, double* __restrict__ scale) {
+mlp_features_kernel(MlpSet S, int s0, int stride, const double* __restrict__ B, int nx, int ny,
+                    unsigned short* __restrict__ x, double* __restrict__ scale) {
+    const int sp = blockIdx.z;
+    const double* __restrict__ M = S.M[sp];
+    const double m = S.m[sp];
+    const int species = s0 + sp;
+    x += (size_t)sp * nx * ny * kIn;
+    scale += (size_t)sp * nx * ny;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= nx) return;
@@ -471,10 +479,19 @@ __global__ void mlp_adam_kernel(float* __restrict__ P, float* __restrict__ m1, f
 // (scale * y) turned into Q-calligraphic = Q + sym(u P) - 2 m n uuu, written
 // at [c*20 + 10 + k] (the raw-moment layout the flux kernels read); or, when
 // *fallback is set, the kinetic wa*QA + wb*QB.
-__global__ void mlp_qcal_kernel(const double* __restrict__ U, const double* __restrict__ scale,
-                                const float* __restrict__ y, const int* __restrict__ fallback,
-                                const double* __restrict__ QA, const double* __restrict__ QB, double wa, double wb,
-                                long long cells, double m, double* __restrict__ qc) {
+// Species blockIdx.y of the set; scale, y and qc hold the set's species one
+// after the other.
+__global__ void mlp_qcal_kernel(MlpSet S, const double* __restrict__ scale, const float* __restrict__ y, double wa,
+                                double wb, long long cells, double* __restrict__ qc) {
+    const int sp = blockIdx.y;
+    const double* __restrict__ U = S.U[sp];
+    const int* __restrict__ fallback = S.fallback[sp];
+    const double* __restrict__ QA = S.QA[sp];
+    const double* __restrict__ QB = S.QB[sp];
+    const double m = S.m[sp];
+    scale += (size_t)sp * cells;
+    y += (size_t)sp * cells * kOutPad;
+    qc += (size_t)sp * cells * 20;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
     if (fallback && *fallback) {
@@ -503,8 +520,14 @@ __global__ void mlp_qcal_kernel(const double* __restrict__ U, const double* __re
 // Judge: sums over cells of |q_net - q_kin|^2 and |q_kin|^2 (q_i = Q_ijj),
 // per block in a fixed order.
 __global__ void __launch_bounds__(256)
-mlp_judge_partial_kernel(const double* __restrict__ M, const double* __restrict__ scale,
-                         const float* __restrict__ y, long long cells, double m, double* __restrict__ part) {
+mlp_judge_partial_kernel(MlpSet S, const double* __restrict__ scale, const float* __restrict__ y, long long cells,
+                         double* __restrict__ part) {
+    const int sp = blockIdx.y;
+    const double* __restrict__ M = S.M[sp];
+    const double m = S.m[sp];
+    scale += (size_t)sp * cells;
+    y += (size_t)sp * cells * kOutPad;
+    part += (size_t)sp * 2 * gridDim.x;
     __shared__ double red[2 * 4];
     double e2 = 0.0, k2 = 0.0;
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cells;
@@ -531,9 +554,13 @@ mlp_judge_partial_kernel(const double* __restrict__ M, const double* __restrict_
     }
 }
 
-__global__ void mlp_judge_finish_kernel(const double* __restrict__ part, int nblocks, double tol,
-                                        int* __restrict__ fallback, double* __restrict__ err) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block per species of the set.
+__global__ void mlp_judge_finish_kernel(MlpSet S, const double* __restrict__ part, int nblocks, double tol) {
+    if (threadIdx.x != 0) return;
+    const int sp = blockIdx.x;
+    int* __restrict__ fallback = S.fallback[sp];
+    double* __restrict__ err = S.err[sp];
+    part += (size_t)sp * 2 * nblocks;
     double e2 = 0.0, k2 = 0.0;
     for (int b = 0; b < nblocks; ++b) {
         e2 += part[2 * b];
@@ -547,11 +574,20 @@ __global__ void mlp_judge_finish_kernel(const double* __restrict__ part, int nbl
 // --------------------------------------------------------------- launchers --
 constexpr int kJudgeBlocks = 256;
 
+hipError_t launch_mlp_features_set(const MlpSet& S, int ns, int s0, int stride, const double* B, int nx, int ny,
+                                   unsigned short* x, double* scale, hipStream_t st) {
+    if (ns < 1 || ns > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_features_kernel, dim3((nx + 63) / 64, ny, ns), dim3(64), 0, st, S, s0, stride, B, nx, ny,
+                       x, scale);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_features(const double* M, int stride, const double* B, int nx, int ny, double m, int species,
                                unsigned short* x, double* scale, hipStream_t st) {
-    hipLaunchKernelGGL(mlp_features_kernel, dim3((nx + 63) / 64, ny), dim3(64), 0, st, M, stride, B, nx, ny, m,
-                       species, x, scale);
-    return hipGetLastError();
+    MlpSet S{};
+    S.M[0] = M;
+    S.m[0] = m;
+    return launch_mlp_features_set(S, 1, species, stride, B, nx, ny, x, scale, st);
 }
 
 hipError_t launch_mlp_targets(const double* M, long long cells, double m, float* y, hipStream_t st) {
@@ -595,21 +631,44 @@ hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, lo
     return hipGetLastError();
 }
 
+hipError_t launch_mlp_qcal_set(const MlpSet& S, int ns, const double* scale, const float* y, double wa, double wb,
+                               long long cells, double* qc, hipStream_t st) {
+    if (ns < 1 || ns > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_qcal_kernel, dim3((unsigned)((cells + 255) / 256), ns), dim3(256), 0, st, S, scale, y, wa,
+                       wb, cells, qc);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_qcal(const double* U, const double* scale, const float* y, const int* fallback,
                            const double* QA, const double* QB, double wa, double wb, long long cells, double m,
                            double* qc, hipStream_t st) {
-    hipLaunchKernelGGL(mlp_qcal_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, U, scale, y,
-                       fallback, QA, QB, wa, wb, cells, m, qc);
-    return hipGetLastError();
+    MlpSet S{};
+    S.U[0] = U;
+    S.fallback[0] = const_cast<int*>(fallback);
+    S.QA[0] = QA;
+    S.QB[0] = QB;
+    S.m[0] = m;
+    return launch_mlp_qcal_set(S, 1, scale, y, wa, wb, cells, qc, st);
 }
 
 size_t mlp_judge_part_doubles() { return 2 * kJudgeBlocks; }
 
+hipError_t launch_mlp_judge_set(const MlpSet& S, int ns, const double* scale, const float* y, long long cells,
+                                double tol, double* part, hipStream_t st) {
+    if (ns < 1 || ns > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_judge_partial_kernel, dim3(kJudgeBlocks, ns), dim3(256), 0, st, S, scale, y, cells, part);
+    hipLaunchKernelGGL(mlp_judge_finish_kernel, dim3(ns), dim3(64), 0, st, S, part, kJudgeBlocks, tol);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_judge(const double* M, const double* scale, const float* y, long long cells, double m,
                             double tol, double* part, int* fallback, double* err, hipStream_t st) {
-    hipLaunchKernelGGL(mlp_judge_partial_kernel, dim3(kJudgeBlocks), dim3(256), 0, st, M, scale, y, cells, m, part);
-    hipLaunchKernelGGL(mlp_judge_finish_kernel, dim3(1), dim3(64), 0, st, part, kJudgeBlocks, tol, fallback, err);
-    return hipGetLastError();
+    MlpSet S{};
+    S.M[0] = M;
+    S.m[0] = m;
+    S.fallback[0] = fallback;
+    S.err[0] = err;
+    return launch_mlp_judge_set(S, 1, scale, y, cells, tol, part, st);
 }
 
 }  // namespace vl

@@ -151,7 +151,7 @@ size_t fluid_doubles(const vl_config& c) {
 size_t mlp_step_doubles(const vl_config& c) {
     if (c.closure != VL_CLOSURE_MLP) return 0;
     const size_t cells = (size_t)c.nx * c.ny;
-    return 45 * cells + vl::mlp_judge_part_doubles() + 2;
+    return (size_t)c.nspecies * (45 * cells + vl::mlp_judge_part_doubles()) + 2;   // every species at once
 }
 
 // Fluid-only closure step: the step's field arrays, the fluid scratch, the
@@ -282,46 +282,72 @@ vl_status fluid_step_impl(vl_ctx* ctx, int s, double* U, const double* mom_t, co
     return VL_OK;
 }
 
-// Fluid RK3 of species s with the learned third moment (2X3V): judge the
-// network on mom_t1 (moments of f^{t+1}), then run the three stages, each
-// with the network's Q-calligraphic of that stage's state, or the kinetic
-// one where the judge set the fallback flag.
-vl_status fluid_step_mlp(vl_ctx* ctx, int s, const vl_state* S, const double* E_t, const double* B_t,
-                         const double* E_t1, const double* B_t1, const double* E_th, const double* B_th, double dt,
-                         double* fwork, double* mwork, hipStream_t st) {
+// Fluid RK3 of all species with the learned third moment (2X3V): judge the
+// network on the moments of f^{t+1}, then run the three stages, each with
+// the network's Q-calligraphic of that stage's state, or the kinetic one for
+// a species whose judge set the fallback flag.  Each kernel is launched once
+// for all species; their features, outputs and third moments are stored one
+// species after the other in mwork.
+vl_status fluid_step_mlp_all(vl_ctx* ctx, const vl_state* S, const double* E_t, const double* B_t,
+                             const double* E_t1, const double* B_t1, const double* E_th, const double* B_th,
+                             double dt, double* fwork, double* mwork, hipStream_t st) {
     const vl_config& c = ctx->cfg;
-    const vl_species& sp = c.sp[s];
+    const int ns = c.nspecies;
     const long long cells = ctx->cells;
     float* y = (float*)mwork;                           // 16-byte aligned (the caller aligns mwork)
-    unsigned short* x = (unsigned short*)(mwork + 8 * cells);
-    double* scale = mwork + 24 * cells;
-    double* qc = mwork + 25 * cells;
-    double* part = mwork + 45 * cells;
-    const double* mom_t = S->mom_post[s];
-    const double* mom_t1 = S->mom_pre[s];
-    int* fb = S->closure_fallback + s;
+    unsigned short* x = (unsigned short*)(mwork + 8 * ns * cells);
+    double* scale = mwork + 24 * ns * cells;
+    double* qc = mwork + 25 * ns * cells;
+    double* part = mwork + 45 * ns * cells;
     Timed tm(ctx, VL_T_FLUID, st);
-    VL_HIP(vl::launch_mlp_features(mom_t1, 20, B_t1, c.nx, c.ny, sp.m, s, x, scale, st));
-    VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, cells, y, st));
-    VL_HIP(vl::launch_mlp_judge(mom_t1, scale, y, cells, sp.m, c.closure_tol, part, fb, S->closure_err + s, st));
-    double* U = S->U[s];
-    double* U1 = fwork;
-    double* U2 = U1 + cells * 10;
-    double* Hx = U2 + cells * 10;
-    double* Hy = Hx + cells * 10;
-    struct Stage { const double* Us; const double* Un; double* Uo; const double* QA; const double* QB; double wa, wb;
-                   const double* E; const double* B; double a, b; };
-    const Stage G[3] = {
-        {U, U, U1, mom_t, mom_t, 1.0, 0.0, E_t, B_t, 0.0, 1.0},
-        {U1, U, U2, mom_t1, mom_t1, 1.0, 0.0, E_t1, B_t1, 0.75, 0.25},
-        {U2, U, U, mom_t, mom_t1, 0.5, 0.5, E_th, B_th, 1.0 / 3.0, 2.0 / 3.0},
-    };
+    vl::MlpSet J{};
+    for (int s = 0; s < ns; ++s) {
+        J.M[s] = S->mom_pre[s];
+        J.m[s] = c.sp[s].m;
+        J.fallback[s] = S->closure_fallback + s;
+        J.err[s] = S->closure_err + s;
+    }
+    VL_HIP(vl::launch_mlp_features_set(J, ns, 0, 20, B_t1, c.nx, c.ny, x, scale, st));
+    VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, ns * cells, y, st));
+    VL_HIP(vl::launch_mlp_judge_set(J, ns, scale, y, cells, c.closure_tol, part, st));
+    const double wa[3] = {1.0, 1.0, 0.5}, wb[3] = {0.0, 0.0, 0.5};
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
+    const double* E[3] = {E_t, E_t1, E_th};
+    const double* B[3] = {B_t, B_t1, B_th};
     for (int k = 0; k < 3; ++k) {
-        VL_HIP(vl::launch_mlp_features(G[k].Us, 10, G[k].B, c.nx, c.ny, sp.m, s, x, scale, st));
-        VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, cells, y, st));
-        VL_HIP(vl::launch_mlp_qcal(G[k].Us, scale, y, fb, G[k].QA, G[k].QB, G[k].wa, G[k].wb, cells, sp.m, qc, st));
-        VL_HIP(vl::launch_fluid_stage_3v(G[k].Us, G[k].Un, G[k].Uo, qc, qc, 1.0, 0.0, G[k].E, G[k].B, G[k].a, G[k].b,
-                                         dt, c.nx, c.ny, sp.q, sp.m, dx_of(c), dy_of(c), Hx, Hy, st));
+        vl::MlpSet F{};
+        vl::FluidSet G{};
+        for (int s = 0; s < ns; ++s) {
+            double* U = S->U[s];
+            double* U1 = fwork + (size_t)s * fluid_doubles(c);
+            double* U2 = U1 + cells * 10;
+            const double* Us[3] = {U, U1, U2};
+            double* Uo[3] = {U1, U2, U};
+            const double* QA[3] = {S->mom_post[s], S->mom_pre[s], S->mom_post[s]};
+            const double* QB[3] = {S->mom_post[s], S->mom_pre[s], S->mom_pre[s]};
+            F.M[s] = Us[k];
+            F.U[s] = Us[k];
+            F.QA[s] = QA[k];
+            F.QB[s] = QB[k];
+            F.fallback[s] = S->closure_fallback + s;
+            F.m[s] = c.sp[s].m;
+            G.Us[s] = Us[k];
+            G.Un[s] = U;
+            G.Uo[s] = Uo[k];
+            G.QA[s] = qc + (size_t)s * 20 * cells;
+            G.QB[s] = G.QA[s];
+            G.Hx[s] = U2 + cells * 10;
+            G.Hy[s] = G.Hx[s] + cells * 10;
+            G.Sg[s] = nullptr;
+            G.m[s] = c.sp[s].m;
+            G.q[s] = c.sp[s].q;
+            G.gchi[s] = 0.0;
+        }
+        VL_HIP(vl::launch_mlp_features_set(F, ns, 0, 10, B[k], c.nx, c.ny, x, scale, st));
+        VL_HIP(vl::launch_mlp_forward(S->mlp_params, x, ns * cells, y, st));
+        VL_HIP(vl::launch_mlp_qcal_set(F, ns, scale, y, wa[k], wb[k], cells, qc, st));
+        VL_HIP(vl::launch_fluid_stage_3v_set(G, ns, 1.0, 0.0, E[k], B[k], a[k], b[k], dt, c.nx, c.ny, dx_of(c),
+                                             dy_of(c), st, per_y(c)));
     }
     return VL_OK;
 }
@@ -457,9 +483,8 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
             // the fluid steps of all species (one launch per kernel with the
             // kinetic closure), then the fits
             if (c.closure == VL_CLOSURE_MLP) {
-                for (int s = 0; s < ns; ++s)
-                    if ((r = fluid_step_mlp(ctx, s, S, E_t, B_t, E_1, B_1, E_h, B_h, dt, fwork, mwork, st)) != VL_OK)
-                        return r;
+                if ((r = fluid_step_mlp_all(ctx, S, E_t, B_t, E_1, B_1, E_h, B_h, dt, fwork, mwork, st)) != VL_OK)
+                    return r;
             } else {
                 Timed tm(ctx, VL_T_FLUID, st);
                 const double ms[2] = {c.sp[0].m, ns > 1 ? c.sp[1].m : 1.0};

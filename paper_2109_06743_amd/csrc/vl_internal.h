@@ -135,6 +135,24 @@ hipError_t launch_qcal_q0(const double* U, long long cells, double m, double* qc
 
 // learned heat-flux closure (mlp_kernels.hip)
 constexpr int kMlpParams = 13520;
+// Per-species operands of the network kernels for up to two species per
+// launch; the features, scales, outputs and third moments of the set's
+// species are stored one after the other (cells of species 0, then 1).
+struct MlpSet {
+    const double* M[2];     // features and judge: moment (stride 20) or fluid (stride 10) records
+    const double* U[2];     // qcal: the stage's fluid state
+    const double* QA[2];    // qcal: kinetic third moments for the fallback
+    const double* QB[2];
+    int* fallback[2];       // judge output / qcal input (or null)
+    double* err[2];         // judge output
+    double m[2];
+};
+hipError_t launch_mlp_features_set(const MlpSet& S, int ns, int s0, int stride, const double* B, int nx, int ny,
+                                   unsigned short* x, double* scale, hipStream_t st);
+hipError_t launch_mlp_qcal_set(const MlpSet& S, int ns, const double* scale, const float* y, double wa, double wb,
+                               long long cells, double* qc, hipStream_t st);
+hipError_t launch_mlp_judge_set(const MlpSet& S, int ns, const double* scale, const float* y, long long cells,
+                                double tol, double* part, hipStream_t st);
 hipError_t launch_mlp_features(const double* M, int stride, const double* B, int nx, int ny, double m, int species,
                                unsigned short* x, double* scale, hipStream_t st);
 hipError_t launch_mlp_targets(const double* M, long long cells, double m, float* y, hipStream_t st);
