@@ -808,11 +808,6 @@ array_max_kernel(const T* __restrict__ f, long long n, typename Bits<T>::U* __re
     block_max_part(mx, out);
 }
 
-__global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // Maximum of the per-block partial maxima part[0..n) into *slot (bits of
 // non-negative values order like the values).  One block; 16-byte loads,
 // eight in flight per thread; fixed order.
@@ -983,11 +978,6 @@ hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipS
     hipLaunchKernelGGL((array_max_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, f, n,
                        (typename Bits<T>::U*)part);
     return finish_max<T>(out, part, blocks, st);
-}
-
-hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st) {
-    hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 63) / 64), dim3(64), 0, st, (unsigned long long*)p, n, v);
-    return hipGetLastError();
 }
 
 #define VL_INST(T)                                                                                         \

@@ -54,7 +54,6 @@ hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy
 constexpr long long kMaxArrayBlocks = 4096;
 template <class T>
 hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStream_t st);
-hipError_t launch_fill_u64(void* p, int n, unsigned long long v, hipStream_t st);
 
 template <class T>
 hipError_t launch_moments3(const T* f, double* mom, long long cells, const VGridArgs& a, hipStream_t st);
