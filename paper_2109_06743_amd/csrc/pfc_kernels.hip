@@ -680,8 +680,9 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
     constexpr int NV = N * N * N;
     constexpr int PER = NV / NTH;            // values per thread (NTH divides N^3)
     static_assert(PER * NTH == NV, "thread count must divide the block");
-    // one v_x pencil per thread: the two v_x sweeps run in registers
+    // one v_x pencil per thread, or two: the two v_x sweeps run in registers
     constexpr bool kRegX = N * N <= NTH;
+    constexpr bool kRegX2 = !kRegX && N * N <= 2 * NTH;
     __shared__ T blk[N * N * PZ];
     __shared__ double EB[6];
     const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
@@ -750,9 +751,62 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
                 mx = fmax(mx, g[k]);
             }
         }
+    } else if constexpr (kRegX2) {
+        // Thread t owns the v_x pencils t and t + NTH (those below N^2): each is
+        // loaded from global memory, swept in registers and stored into the
+        // block; after the v_y, v_z, v_y sweeps in the block each is read back,
+        // swept again and written out.  One pencil is in registers at a time.
+        const int t = threadIdx.x;
+        constexpr int XS = N * PZ;
+        double eb[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            eb[k] = E[cell * 3 + k];
+            eb[3 + k] = B ? B[cell * 3 + k] : 0.0;
+        }
+        T xs0, xs1, xs2;
+        sweep_coeffs<T>(0, half, P, eb, xs0, xs1, xs2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int p = t + j * NTH;
+            if (p < N * N) {
+                const int xb = (p / N) * PZ + p % N;
+                const T sx = cube_pencil_shift<T, N>(p, xs0, xs1, xs2);
+                T g[N];
+#pragma unroll
+                for (int k = 0; k < N; ++k) g[k] = __builtin_nontemporal_load(src + p + k * N * N);
+                sweep_pencil_regs<T, N>(g, sx >= T(0), ShiftT<T>(fabs(sx)), F2, blk, xb, XS);
+#pragma unroll
+                for (int k = 0; k < N; ++k) blk[xb + k * XS] = g[k];
+            }
+        }
+        __syncthreads();
+        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 2, P.tau, P, EB, F2);
+        __syncthreads();
+        sweep_cube<T, N>(blk, 1, half, P, EB, F2);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int p = t + j * NTH;
+            if (p < N * N) {
+                const int xb = (p / N) * PZ + p % N;
+                const T sx = cube_pencil_shift<T, N>(p, xs0, xs1, xs2);
+                T g[N];
+#pragma unroll
+                for (int k = 0; k < N; ++k) g[k] = blk[xb + k * XS];
+                sweep_pencil_regs<T, N>(g, sx >= T(0), ShiftT<T>(fabs(sx)), F2, blk, xb, XS);
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    __builtin_nontemporal_store(g[k], dst + p + k * N * N);
+                    mx = fmax(mx, g[k]);
+                }
+            }
+        }
     } else {
-        // small blocks never get here; large blocks stream through registers
-        // in chunks of four values per thread
+        // large blocks stream through registers in chunks of four values per
+        // thread
         constexpr int CH = PER > 16 ? 4 : PER;
         static_assert(PER % CH == 0, "chunks must tile the block");
 #pragma unroll 1
