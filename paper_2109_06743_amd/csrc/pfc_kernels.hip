@@ -122,7 +122,8 @@ __device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F
 // ---------------------------------------------------------------------------
 // Fused X(tau) for 2X3V: the x sweep and then the y sweep with one f_inf, in
 // one pass over f.  A thread owns one (v_x, |v_y|, v_z) pair, C adjacent x
-// cells and a segment of S positions of its y pencils.  Reflecting walls: one
+// cells and a segment of S positions of its y pencils (S chosen at launch,
+// xy_segment).  Reflecting walls: one
 // doubled pencil (positions 0..ny-1: rows of the +v_y half; ny..2ny-1: rows
 // ny-1..0 of the -v_y half).  Periodic y: two cyclic pencils of ny positions
 // (the +v_y half walked upward, the -v_y half downward); either way every
@@ -136,9 +137,9 @@ __device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F
 // sweep runs S+3 times for S outputs; the extra rows are re-read from cache.
 // Work order: x strip fastest, so neighbouring strips stream the same rows
 // at the same time.
-template <class T, int C, int S>
+template <class T, int C>
 __global__ void __launch_bounds__(256)
-pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int nx, int ny, int Nv, int nvx, int nvy, int nvz,
+pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int S, int nx, int ny, int Nv, int nvx, int nvy, int nvz,
               float inv_nvz, float inv_half, double vx_lo, double dvx, double tau_dx, double vy_lo, double dvy,
               double tau_dy, int per, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
     const int half = (nvy + 1) / 2;
@@ -935,14 +936,39 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
     return finish_max<T>(max_out, part, blocks, st);
 }
 
-// x cells per thread (FP32: 8 keeps 4 waves/SIMD; FP64 registers allow 4) and
-// doubled-pencil positions per segment
+// x cells per thread (FP32: 8; FP64 registers allow 4)
 template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
-constexpr int kXySeg = 128;
+
+// Positions per segment of the fused X operator: 128, or, where that leaves
+// the GPU with fewer blocks than fit on it at once (three per CU), the
+// shortest segments (at least 16 positions) whose blocks still all fit, so
+// one round of blocks covers the launch with more of them walking.
+static int xy_segment(int nx, int ny, long long npairs, int per, int cols) {
+    static int cus = 0;
+    if (cus <= 0) {
+        int d = 0;
+        if (hipGetDevice(&d) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    const long long npb = ((npairs + 255) / 256) * ((nx + cols - 1) / cols) * (per ? 2 : 1);
+    const int L = per ? ny : 2 * ny;              // positions of one pencil
+    const long long resident = 3LL * cus;
+    int best = L < 128 ? L : 128;
+    for (int k = (L + best - 1) / best + 1; k <= L / 16; ++k) {
+        const int S = (L + k - 1) / k;
+        if (npb * ((L + S - 1) / S) > resident) break;
+        best = S;
+    }
+    return best;
+}
+
 template <class T>
-long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz, int per) {
+long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz, int per, int* seg = nullptr) {
     const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
-    const long long nseg = per ? 2LL * ((ny + kXySeg - 1) / kXySeg) : (2LL * ny + kXySeg - 1) / kXySeg;
+    const int S = xy_segment(nx, ny, npairs, per, xy_cols<T>());
+    if (seg) *seg = S;
+    const long long nseg = per ? 2LL * ((ny + S - 1) / S) : (2LL * ny + S - 1) / S;
     return ((npairs + 255) / 256) * nseg * ((nx + xy_cols<T>() - 1) / xy_cols<T>());
 }
 long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
@@ -963,8 +989,9 @@ hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy
                          void* max_out, void* part, hipStream_t st) {
     const int Nv = nvx * nvy * nvz;
     const int half = (nvy + 1) / 2;
-    const long long blocks = pfc_xy_blocks_t<T>(nx, ny, nvx, nvy, nvz, per);
-    hipLaunchKernelGGL((pfc_xy_kernel<T, xy_cols<T>(), kXySeg>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, nx,
+    int S = 0;
+    const long long blocks = pfc_xy_blocks_t<T>(nx, ny, nvx, nvy, nvz, per, &S);
+    hipLaunchKernelGGL((pfc_xy_kernel<T, xy_cols<T>()>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, S, nx,
                        ny, Nv, nvx, nvy, nvz, 1.0f / (float)nvz, 1.0f / (float)half, vx_lo, dvx, tau_dx, vy_lo, dvy,
                        tau_dy, per, (const T*)finf, (typename Bits<T>::U*)(max_out ? part : nullptr));
     return finish_max<T>(max_out, part, blocks, st);
