@@ -242,13 +242,12 @@ def train_closure(cfg, f, F, gen_steps=300, start=60, every=15, epochs=16, batch
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     losses = []
     a.record()
+    Xt, Yt = X[:n_train], Y[:n_train]
     for ep in range(epochs):
         lr_ep = lr * 0.5 ** (ep // 4)                    # halved every four epochs
         perm = torch.randperm(n_train, device="cuda", generator=gen)
-        for b0 in range(0, n_train - batch + 1, batch):
-            idx = perm[b0:b0 + batch]
-            step += 1
-            ctx.mlp_train_step(P, m1, m2, step, lr_ep, X[idx], Y[idx], work, gl)
+        # one call per epoch: the batches perm[k*batch:(k+1)*batch] are gathered in the gradient kernel
+        step += ctx.mlp_train_epoch(P, m1, m2, step + 1, lr_ep, Xt, Yt, perm, batch, work, gl)
         losses.append(gl[-1].item())
     b.record()
     torch.cuda.synchronize()

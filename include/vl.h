@@ -290,6 +290,18 @@ vl_status vl_mlp_gradient(vl_ctx* ctx, const float* params, const uint16_t* x, c
 vl_status vl_mlp_train_step(vl_ctx* ctx, float* params, float* adam_m, float* adam_v, int64_t step, double lr,
                             const uint16_t* x, const float* y, int64_t n, float* work, float* grad_loss,
                             vl_stream stream);
+/* nsteps Adam steps as vl_mlp_train_step, step k (0-based) on the batch of
+ * rows idx[k*batch .. (k+1)*batch) of x ([nrows][64] BF16) and y ([nrows][16]
+ * FP32): the rows are gathered inside the gradient kernel, and the steps run
+ * with the 1-based Adam steps step0 .. step0 + nsteps - 1.  idx: device int64
+ * array of nsteps*batch entries; an entry outside [0, nrows) counts as a
+ * padding row (no features, no loss) but still in the batch's mean.  work:
+ * vl_mlp_work_size(batch) floats.  grad_loss ends with the last step's
+ * gradient and loss.  Same results as nsteps calls of vl_mlp_train_step on the
+ * gathered batches. */
+vl_status vl_mlp_train_epoch(vl_ctx* ctx, float* params, float* adam_m, float* adam_v, int64_t step0, double lr,
+                             const uint16_t* x, const float* y, int64_t nrows, const int64_t* idx, int64_t batch,
+                             int64_t nsteps, float* work, float* grad_loss, vl_stream stream);
 
 /* Diagnostics: total mass of species s (sum f dV dX, FP64) and the
  * kinetic+thermal energy sum tr(P)/2 dX (3V) or P/2 dX (1V) from a raw

@@ -94,13 +94,24 @@ struct Tile {
     f32x4 y;
 };
 
+// Source row of batch row r: idx[r] (rows outside [0, nrows) count as
+// padding, -1) or r itself; -1 past the batch.
+__device__ __forceinline__ long long source_row(long long r, long long n, const long long* __restrict__ idx,
+                                                long long nrows) {
+    if (r >= n) return -1;
+    if (!idx) return r;
+    const long long q = idx[r];
+    return (q >= 0 && q < nrows) ? q : -1;
+}
+
 __device__ __forceinline__ void forward_tile(const unsigned short* __restrict__ x, long long n, long long tile,
-                                             const NetLds& N, bool keep_fp32, Tile& T) {
+                                             const NetLds& N, bool keep_fp32, Tile& T,
+                                             const long long* __restrict__ idx = nullptr, long long nrows = 0) {
     const int lane = threadIdx.x & 63, s = lane & 15, g = lane >> 4;
-    const long long row = tile * 16 + s;
+    const long long row = source_row(tile * 16 + s, n, idx, nrows);
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb) {
-        if (row < n) {
+        if (row >= 0) {
             const uint2 v = *reinterpret_cast<const uint2*>(x + row * kIn + 16 * kb + 4 * g);
             T.hb[0][kb] = *reinterpret_cast<const bf16x4*>(&v);
         } else {
@@ -330,7 +341,8 @@ mlp_forward_kernel(const float* __restrict__ P, const unsigned short* __restrict
 // done in a fixed order).
 __global__ void __launch_bounds__(256)
 mlp_grad_kernel(const float* __restrict__ P, const unsigned short* __restrict__ x, const float* __restrict__ t,
-                long long n, long long tiles_per_block, float inv_norm, float* __restrict__ part) {
+                long long n, long long tiles_per_block, float inv_norm, float* __restrict__ part,
+                const long long* __restrict__ idx, long long nrows) {
     __shared__ NetLds N;
     __shared__ NetLdsT NT;
     __shared__ unsigned short stage_all[4][5][16 * kLds];
@@ -352,10 +364,10 @@ mlp_grad_kernel(const float* __restrict__ P, const unsigned short* __restrict__ 
     float lsum = 0.f;
     for (long long tile = t0; tile < t1; ++tile) {
         Tile T;
-        forward_tile(x, n, tile, N, true, T);
-        const long long row = tile * 16 + s;
+        forward_tile(x, n, tile, N, true, T, idx, nrows);
+        const long long row = source_row(tile * 16 + s, n, idx, nrows);
         f32x4 dy = {0.f, 0.f, 0.f, 0.f};
-        if (row < n) {
+        if (row >= 0) {
             const f32x4 tt = *reinterpret_cast<const f32x4*>(t + row * 16 + 4 * g);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -612,12 +624,13 @@ size_t mlp_grad_blocks(long long n) {
 size_t mlp_part_floats(long long n) { return mlp_grad_blocks(n) * (size_t)kPartStride; }
 
 hipError_t launch_mlp_gradient(const float* P, const unsigned short* x, const float* t, long long n, float* part,
-                               float* grad, hipStream_t st) {
+                               float* grad, hipStream_t st, const long long* idx, long long nrows) {
     const long long tiles = (n + 15) / 16;
     const long long blocks = (long long)mlp_grad_blocks(n);
     const long long tpb = (tiles + blocks - 1) / blocks;
     const float inv_norm = (float)(1.0 / ((double)n * kOut));
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, P, x, t, n, tpb, inv_norm, part);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, P, x, t, n, tpb, inv_norm, part,
+                       idx, nrows);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kNParam + 1 + 255) / 256), dim3(256), 0, st, part, (int)blocks, grad);
     return hipGetLastError();
 }

@@ -887,6 +887,26 @@ vl_status vl_mlp_train_step(vl_ctx* ctx, float* params, float* adam_m, float* ad
     return VL_OK;
 }
 
+vl_status vl_mlp_train_epoch(vl_ctx* ctx, float* params, float* adam_m, float* adam_v, int64_t step0, double lr,
+                             const uint16_t* x, const float* y, int64_t nrows, const int64_t* idx, int64_t batch,
+                             int64_t nsteps, float* work, float* grad_loss, vl_stream stream) {
+    if (!ctx) return VL_EINVAL;
+    if (!params || !adam_m || !adam_v || !x || !y || !idx || !work || !grad_loss)
+        return fail(ctx, VL_EINVAL, "null argument");
+    if (nrows < 1 || batch < 1 || nsteps < 1 || step0 < 1) return fail(ctx, VL_EINVAL, "nrows, batch, nsteps, step0 must be >= 1");
+    if (((uintptr_t)x & 7u) || ((uintptr_t)y & 15u)) return fail(ctx, VL_EINVAL, "x must be 8-, y 16-byte aligned");
+    if (!finite_pos(lr)) return fail(ctx, VL_EINVAL, "lr must be finite and > 0");
+    vl_status r;
+    if ((r = ensure_device(ctx)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    const long long* ix = (const long long*)idx;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        VL_HIP(vl::launch_mlp_gradient(params, x, y, batch, work, grad_loss, st, ix + k * batch, nrows));
+        VL_HIP(vl::launch_mlp_adam(params, adam_m, adam_v, grad_loss, step0 + k, lr, st));
+    }
+    return VL_OK;
+}
+
 vl_status vl_mass_energy(vl_ctx* ctx, int32_t s, const void* f, const double* mom, double* out, vl_stream stream) {
     vl_status r = check_species(ctx, s);
     if (r != VL_OK) return r;

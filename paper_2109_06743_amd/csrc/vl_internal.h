@@ -159,7 +159,8 @@ hipError_t launch_mlp_forward(const float* P, const unsigned short* x, long long
 size_t mlp_grad_blocks(long long n);
 size_t mlp_part_floats(long long n);
 hipError_t launch_mlp_gradient(const float* P, const unsigned short* x, const float* t, long long n, float* part,
-                               float* grad, hipStream_t st);
+                               float* grad, hipStream_t st,
+                               const long long* idx = nullptr, long long nrows = 0);
 hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, long long step, double lr,
                            hipStream_t st);
 hipError_t launch_mlp_qcal(const double* U, const double* scale, const float* y, const int* fallback,

@@ -22,7 +22,7 @@ EXPORTS = ["vl_create", "vl_destroy", "vl_pfc_advect_x", "vl_pfc_advect_v", "vl_
            "vl_fluid_step", "vl_step_work_size", "vl_step", "vl_mass_energy", "vl_sync", "vl_status_str",
            "vl_last_error", "vl_version", "vl_timing_enable", "vl_timing_read", "vl_mlp_features",
            "vl_mlp_targets", "vl_mlp_forward", "vl_mlp_work_size", "vl_mlp_gradient", "vl_mlp_train_step",
-           "vl_field_energy", "vl_fluid_closure_work_size", "vl_fluid_closure_step"]
+           "vl_mlp_train_epoch", "vl_field_energy", "vl_fluid_closure_work_size", "vl_fluid_closure_step"]
 VL_CLOSURE_KINETIC, VL_CLOSURE_MLP = 0, 1
 VL_FLUID_GRADIENT, VL_FLUID_MLP = 0, 1
 MLP_IN, MLP_OUT, MLP_OUT_PAD, MLP_NPARAM = 64, 10, 16, 13520
@@ -109,6 +109,8 @@ def load():
         "vl_mlp_work_size": ([ctypes.c_int64], sz),
         "vl_mlp_gradient": ([vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp], i32),
         "vl_mlp_train_step": ([vp, vp, vp, vp, ctypes.c_int64, d, vp, vp, ctypes.c_int64, vp, vp, vp], i32),
+        "vl_mlp_train_epoch": ([vp, vp, vp, vp, ctypes.c_int64, d, vp, vp, ctypes.c_int64, vp, ctypes.c_int64,
+                                ctypes.c_int64, vp, vp, vp], i32),
         "vl_status_str": ([i32], ctypes.c_char_p),
         "vl_last_error": ([vp], ctypes.c_char_p),
         "vl_version": ([], ctypes.c_char_p),
@@ -279,6 +281,14 @@ class Context:
         self._check(self.lib.vl_mlp_train_step(self.h, _ptr(params), _ptr(m1), _ptr(m2), int(step), float(lr),
                                                _ptr(x), _ptr(y), int(n), _ptr(work), _ptr(grad_loss),
                                                _stream(stream)))
+
+    def mlp_train_epoch(self, params, m1, m2, step0, lr, x, y, idx, batch, work, grad_loss, stream=None):
+        """len(idx) // batch Adam steps on the rows idx of x and y (idx: int64 device tensor)."""
+        nsteps = idx.shape[0] // batch
+        self._check(self.lib.vl_mlp_train_epoch(self.h, _ptr(params), _ptr(m1), _ptr(m2), int(step0), float(lr),
+                                                _ptr(x), _ptr(y), int(x.shape[0]), _ptr(idx), int(batch),
+                                                int(nsteps), _ptr(work), _ptr(grad_loss), _stream(stream)))
+        return nsteps
 
     def timing_enable(self, on=True):
         """on: True/False for every category, or an iterable of category names."""

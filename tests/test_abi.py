@@ -155,3 +155,18 @@ def test_create_rejects_rows_of_4_gib(lib):
     assert st == 0
     lib.vl_destroy(h)
     assert _create(dict(cfg, nx=262144), "f32")[0] == 3
+
+
+def test_mlp_train_epoch_rejects_bad_arguments(lib):
+    cfg, _ = workloads.landau(nx=16, nv=16)
+    st, h = _create(cfg)
+    p = ctypes.c_void_p(0x1000)                 # never dereferenced: validation fails first
+    y = ctypes.c_void_p(0x2000)
+    f = lib.vl_mlp_train_epoch
+    assert f(h, None, p, p, 1, 1e-3, p, y, 10, p, 4, 2, p, p, None) == 1          # null params
+    assert f(h, p, p, p, 1, 1e-3, p, y, 10, None, 4, 2, p, p, None) == 1          # null indices
+    assert f(h, p, p, p, 1, 1e-3, p, y, 10, p, 4, 0, p, p, None) == 1             # no steps
+    assert f(h, p, p, p, 0, 1e-3, p, y, 10, p, 4, 2, p, p, None) == 1             # Adam steps count from 1
+    assert f(h, p, p, p, 1, float("nan"), p, y, 10, p, 4, 2, p, p, None) == 1     # learning rate
+    assert f(h, p, p, p, 1, 1e-3, ctypes.c_void_p(0x1001), y, 10, p, 4, 2, p, p, None) == 1   # x alignment
+    lib.vl_destroy(h)

@@ -186,6 +186,60 @@ def test_adam_step_matches_oracle_and_training_descends():
     assert np.all(d["W4"][10:] == 0.0) and np.all(d["b4"][10:] == 0.0)
 
 
+def test_train_epoch_equals_train_steps_on_gathered_batches():
+    """vl_mlp_train_epoch gathers the batch rows inside the gradient kernel:
+    its parameters after four steps equal those of four vl_mlp_train_step
+    calls on the gathered batches (same kernels, same order: bitwise), and an
+    index outside the rows counts as a padding row."""
+    import torch
+    from paper_2109_06743_amd import vl
+    ctx = vl.Context(dict(W.gem(nx=4, ny=2, nv=8)[0]), "f32")
+    n, batch, nsteps = 3000, 512, 4
+    xv, xb = _random_x(n, 11)
+    rng = np.random.default_rng(12)
+    t = np.zeros((n, 16), dtype=np.float32)
+    t[:, :10] = np.tanh(xv @ rng.normal(scale=0.15, size=(10, 64)).T)
+    X = _t(xb.view(np.int16), torch.int16).reshape(n, 64)
+    T = _t(t, torch.float32)
+    idx = torch.as_tensor(rng.permutation(n)[:nsteps * batch].astype(np.int64)).cuda()
+    work = torch.zeros(ctx.mlp_work_size(batch), dtype=torch.float32, device="cuda")
+    runs = []
+    for mode in ("steps", "epoch"):
+        P = _t(W.mlp_init(3), torch.float32)
+        m1, m2 = torch.zeros_like(P), torch.zeros_like(P)
+        gl = torch.zeros(OM.N_PARAM + 1, dtype=torch.float32, device="cuda")
+        if mode == "steps":
+            for k in range(nsteps):
+                sel = idx[k * batch:(k + 1) * batch]
+                ctx.mlp_train_step(P, m1, m2, 1 + k, 1e-3, X[sel].contiguous(), T[sel].contiguous(), work, gl)
+        else:
+            assert ctx.mlp_train_epoch(P, m1, m2, 1, 1e-3, X, T, idx, batch, work, gl) == nsteps
+        ctx.sync()
+        runs.append((host(P), host(gl)))
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    # an out-of-range index is a padding row: no loss and no gradient of its own; a batch of
+    # padding only gives exactly zero, one padding row leaves the gradient of the other rows scaled
+    # by (batch - 1) / batch for the mean (up to the BF16 rounding of the scaled errors)
+    P = _t(W.mlp_init(3), torch.float32)
+    gl_0 = torch.full((OM.N_PARAM + 1,), 7.0, dtype=torch.float32, device="cuda")
+    pad = torch.full((batch,), -1, dtype=torch.int64, device="cuda")
+    pad[::2] = n + 3
+    ctx.mlp_train_epoch(P.clone(), torch.zeros_like(P), torch.zeros_like(P), 1, 1e-3, X, T, pad, batch, work, gl_0)
+    sel = idx[:batch].clone()
+    sel[5] = n + 7
+    gl_a = torch.zeros(OM.N_PARAM + 1, dtype=torch.float32, device="cuda")
+    ctx.mlp_train_epoch(P.clone(), torch.zeros_like(P), torch.zeros_like(P), 1, 1e-3, X, T, sel, batch, work, gl_a)
+    keep = torch.cat([sel[:5], sel[6:]])
+    gl_b = torch.zeros(OM.N_PARAM + 1, dtype=torch.float32, device="cuda")
+    ctx.mlp_gradient(P, X[keep].contiguous(), T[keep].contiguous(), work, gl_b)
+    ctx.sync()
+    assert not host(gl_0).any()
+    ga, gb = host(gl_a), host(gl_b) * ((batch - 1) / batch)
+    assert rel_l2(ga[:-1], gb[:-1]) < 2e-2
+    assert abs(ga[-1] - gb[-1]) <= 1e-5 * gb[-1]
+
+
 # ------------------------------------------------------ closure in a step --
 def _start(cfg, f, F0, dtype, params):
     from paper_2109_06743_amd import vl
