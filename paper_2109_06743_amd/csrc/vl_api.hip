@@ -882,8 +882,7 @@ vl_status vl_mlp_train_step(vl_ctx* ctx, float* params, float* adam_m, float* ad
     vl_status r;
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     hipStream_t st = (hipStream_t)stream;
-    VL_HIP(vl::launch_mlp_gradient(params, x, y, n, work, grad_loss, st));
-    VL_HIP(vl::launch_mlp_adam(params, adam_m, adam_v, grad_loss, step, lr, st));
+    VL_HIP(vl::launch_mlp_train_step(params, adam_m, adam_v, step, lr, x, y, n, work, grad_loss, st));
     return VL_OK;
 }
 
@@ -900,10 +899,9 @@ vl_status vl_mlp_train_epoch(vl_ctx* ctx, float* params, float* adam_m, float* a
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     const long long* ix = (const long long*)idx;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        VL_HIP(vl::launch_mlp_gradient(params, x, y, batch, work, grad_loss, st, ix + k * batch, nrows));
-        VL_HIP(vl::launch_mlp_adam(params, adam_m, adam_v, grad_loss, step0 + k, lr, st));
-    }
+    for (int64_t k = 0; k < nsteps; ++k)
+        VL_HIP(vl::launch_mlp_train_step(params, adam_m, adam_v, step0 + k, lr, x, y, batch, work, grad_loss, st,
+                                         ix + k * batch, nrows));
     return VL_OK;
 }
 

@@ -161,8 +161,11 @@ size_t mlp_part_floats(long long n);
 hipError_t launch_mlp_gradient(const float* P, const unsigned short* x, const float* t, long long n, float* part,
                                float* grad, hipStream_t st,
                                const long long* idx = nullptr, long long nrows = 0);
-hipError_t launch_mlp_adam(float* P, float* m1, float* m2, const float* grad, long long step, double lr,
-                           hipStream_t st);
+// gradient (as launch_mlp_gradient) and the Adam update of step `step`, fused
+// into the gradient sum
+hipError_t launch_mlp_train_step(float* P, float* m1, float* m2, long long step, double lr,
+                                 const unsigned short* x, const float* t, long long n, float* part, float* grad,
+                                 hipStream_t st, const long long* idx = nullptr, long long nrows = 0);
 hipError_t launch_mlp_qcal(const double* U, const double* scale, const float* y, const int* fallback,
                            const double* QA, const double* QB, double wa, double wb, long long cells, double m,
                            double* qc, hipStream_t st);
