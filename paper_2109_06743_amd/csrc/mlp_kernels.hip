@@ -548,28 +548,29 @@ __device__ __forceinline__ void adam_update(const AdamArgs& A, int p, float gr) 
 }
 
 // Sum of the block partials: grad[0..13519], loss at [13520].  Block i
-// covers entries 64i..64i+63; wave q adds partials q, q+4, q+8, ... in four
-// interleaved running sums (so that many loads are in flight), and the four
-// waves' totals are added in wave order: a fixed order, the same on every
-// call.  With A.P set, the Adam update of the same entries follows.
+// covers entries 64i..64i+63; wave q adds partials q, q+4, q+8, ..., sixteen
+// loads in flight at a time, into four running sums, and the four waves'
+// totals are added in wave order: a fixed order, the same on every call.
+// With A.P set, the Adam update of the same entries follows.
 __global__ void __launch_bounds__(256)
 mlp_reduce_kernel(const float* __restrict__ part, int nblocks, float* __restrict__ grad, AdamArgs A) {
     __shared__ float red[4][64];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
     if (p <= kNParam) {
         const float* __restrict__ src = part + p;
         int b = q;
-        for (; b + 12 < nblocks; b += 16) {
-            a0 += src[(long long)b * kPartStride];
-            a1 += src[(long long)(b + 4) * kPartStride];
-            a2 += src[(long long)(b + 8) * kPartStride];
-            a3 += src[(long long)(b + 12) * kPartStride];
+        for (; b + 60 < nblocks; b += 64) {
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = src[(long long)(b + 4 * k) * kPartStride];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc[k & 3] += v[k];
         }
-        for (; b < nblocks; b += 4) a0 += src[(long long)b * kPartStride];
+        for (; b < nblocks; b += 4) acc[0] += src[(long long)b * kPartStride];
     }
-    red[q][lane] = (a0 + a1) + (a2 + a3);
+    red[q][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
     if (q != 0 || p > kNParam) return;
     const float gr = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);

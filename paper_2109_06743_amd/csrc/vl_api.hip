@@ -71,8 +71,11 @@ hipEvent_t take_event(vl_ctx* c) {
         c->pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence at the record (the host never reads
+    // memory through these events), which also keeps the records from
+    // stretching the gaps between the timed kernel and its neighbours
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
