@@ -120,6 +120,36 @@ def test_forward_matches_oracle(n):
     assert np.abs(yg[:, 10:] - yr[:, 10:]).max() < 1e-6      # padding rows: zero weights, bias b4[10:]
 
 
+def test_parameters_off_16_byte_alignment_give_the_same_results():
+    """The kernels stage the network into LDS with 16-byte loads when the
+    parameter array allows it and element by element otherwise: both paths
+    give bitwise the same outputs and gradients."""
+    import torch
+    from paper_2109_06743_amd import vl
+    ctx = vl.Context(dict(W.gem(nx=4, ny=2, nv=8)[0]), "f32")
+    p = _params(3)
+    n = 1000
+    xv, xb = _random_x(n, 4)
+    x = _t(xb.view(np.int16), torch.int16).reshape(n, 64)
+    t = _t(np.random.default_rng(5).normal(size=(n, 16)).astype(np.float32), torch.float32)
+    pa = _t(p, torch.float32)
+    buf = torch.zeros(p.size + 1, dtype=torch.float32, device="cuda")
+    pm = buf[1:]                                   # 4 bytes past a 16-byte boundary
+    pm.copy_(pa)
+    assert pa.data_ptr() % 16 == 0 and pm.data_ptr() % 16 == 4
+    out = []
+    for P in (pa, pm):
+        y = torch.zeros(n * 16, dtype=torch.float32, device="cuda")
+        ctx.mlp_forward(P, x, y)
+        work = torch.zeros(ctx.mlp_work_size(n), dtype=torch.float32, device="cuda")
+        gl = torch.zeros(vl.MLP_NPARAM + 1, dtype=torch.float32, device="cuda")
+        ctx.mlp_gradient(P, x, t, work, gl)
+        ctx.sync()
+        out.append((host(y), host(gl)))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
 @pytest.mark.parametrize("n", [7, 777, 5000])
 def test_gradient_matches_oracle(n):
     import torch
