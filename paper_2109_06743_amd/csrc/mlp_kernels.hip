@@ -250,84 +250,111 @@ __device__ __forceinline__ bool local_nuT(const double* __restrict__ M, int stri
 
 // Species blockIdx.z of the set (species index s0 + blockIdx.z); its
 // features and scales are stored after those of the set's earlier species.
-__global__ void __launch_bounds__(64)
+// A 256-thread block covers 4 rows x 64 columns of cells: n, u, T of its
+// 6 x 66 stencil cells are formed once each into LDS (rather than nine times,
+// once per neighbour), each thread then forms its cell's features from
+// there, and the 256 feature rows (128 B each) leave through LDS, so that
+// every wave store writes 256 contiguous bytes.
+constexpr int kFeatCols = 64, kFeatRows = 4;
+union FeatLds {
+    double nut[kFeatRows + 2][kFeatCols + 2][11];   // n, u, T (padded against bank conflicts)
+    unsigned out[kFeatRows * kFeatCols][33];         // packed BF16 feature rows (padded)
+};
+
+__global__ void __launch_bounds__(256)
 mlp_features_kernel(MlpSet S, int s0, int stride, const double* __restrict__ B, int nx, int ny,
                     unsigned short* __restrict__ x, double* __restrict__ scale) {
+    __shared__ FeatLds L;
     const int sp = blockIdx.z;
     const double* __restrict__ M = S.M[sp];
     const double m = S.m[sp];
     const int species = s0 + sp;
     x += (size_t)sp * nx * ny * kIn;
     scale += (size_t)sp * nx * ny;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    if (i >= nx) return;
-    const long long c = (long long)j * nx + i;
-    double n0, u0[3], T0[6];
-    local_nuT(M, stride, c, m, false, n0, u0, T0);
-    const double Tref = (T0[0] + T0[3] + T0[5]) / 3.0;
-    const bool ok = n0 > 1e-12 && Tref > 0.0;
+    const int i0 = blockIdx.x * kFeatCols, j0 = blockIdx.y * kFeatRows;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < (kFeatRows + 2) * (kFeatCols + 2); q += blockDim.x) {
+        const int rr = q / (kFeatCols + 2), cc = q % (kFeatCols + 2);
+        double* d = L.nut[rr][cc];
+        int jj = j0 - 1 + rr;
+        if (jj > ny) {             // below the mirror of row ny-1: feeds no cell
+#pragma unroll
+            for (int k = 0; k < 10; ++k) d[k] = 0.0;
+            continue;
+        }
+        bool mir = false;
+        if (jj < 0) { jj = -1 - jj; mir = true; }
+        if (jj >= ny) { jj = 2 * ny - 1 - jj; mir = true; }
+        const int ii = ((i0 - 1 + cc) % nx + nx) % nx;
+        double nn, uu[3], TT[6];
+        local_nuT(M, stride, (long long)jj * nx + ii, m, mir, nn, uu, TT);
+        d[0] = nn;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[1 + k] = uu[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d[4 + k] = TT[k];
+    }
+    __syncthreads();
+    const int r = tid / kFeatCols, cl = tid % kFeatCols;
+    const int i = i0 + cl, j = j0 + r;
+    const bool valid = i < nx && j < ny;
     float f[64];    // features are rounded to FP32 (then BF16) anyway
 #pragma unroll
     for (int k = 0; k < 64; ++k) f[k] = 0.f;
     double sc = 0.0;
-    if (ok) {
-        const double vt = sqrt(Tref / m);
-        const double ivt = 1.0 / vt, iT = 1.0 / Tref, in0 = 1.0 / n0;
-        sc = n0 * m * vt * vt * vt;
-        // phi[dj][di][k]: stencil fields
-        double phi[3][3][10];
+    if (valid) {
+        const double* C = L.nut[r + 1][cl + 1];
+        const double n0 = C[0];
+        const double u0[3] = {C[1], C[2], C[3]};
+        double T0[6];
 #pragma unroll
-        for (int dj = -1; dj <= 1; ++dj) {
+        for (int k = 0; k < 6; ++k) T0[k] = C[4 + k];
+        const double Tref = (T0[0] + T0[3] + T0[5]) / 3.0;
+        if (n0 > 1e-12 && Tref > 0.0) {
+            const double vt = sqrt(Tref / m);
+            const double ivt = 1.0 / vt, iT = 1.0 / Tref, in0 = 1.0 / n0;
+            sc = n0 * m * vt * vt * vt;
+            f[0] = (float)(u0[0] * ivt);
+            f[1] = (float)(u0[1] * ivt);
+            f[2] = (float)(u0[2] * ivt);
 #pragma unroll
-            for (int di = -1; di <= 1; ++di) {
-                int jj = j + dj;
-                bool mir = false;
-                if (jj < 0) { jj = -1 - jj; mir = true; }
-                if (jj >= ny) { jj = 2 * ny - 1 - jj; mir = true; }
-                const int ii = (i + di + nx) % nx;
-                double nn, uu[3], TT[6];
-                local_nuT(M, stride, (long long)jj * nx + ii, m, mir, nn, uu, TT);
-                double* p = phi[dj + 1][di + 1];
-                p[0] = nn * in0;
-                p[1] = uu[0] * ivt;
-                p[2] = uu[1] * ivt;
-                p[3] = uu[2] * ivt;
+            for (int k = 0; k < 6; ++k) f[3 + k] = (float)(T0[k] * iT);
+            // stencil fields n/n_c, u/v_t, T/T_ref at offset (dj, di)
 #pragma unroll
-                for (int k = 0; k < 6; ++k) p[4 + k] = TT[k] * iT;
+            for (int k = 0; k < 10; ++k) {
+                const double sk = k == 0 ? in0 : (k < 4 ? ivt : iT);
+                auto P = [&](int dj, int di) { return L.nut[r + 1 + dj][cl + 1 + di][k] * sk; };
+                const double c0 = P(0, 0);
+                f[9 + 5 * k + 0] = (float)((P(0, 1) - P(0, -1)) / 2.0);
+                f[9 + 5 * k + 1] = (float)((P(1, 0) - P(-1, 0)) / 2.0);
+                f[9 + 5 * k + 2] = (float)(P(0, 1) - 2.0 * c0 + P(0, -1));
+                f[9 + 5 * k + 3] = (float)(P(1, 0) - 2.0 * c0 + P(-1, 0));
+                f[9 + 5 * k + 4] = (float)((P(1, 1) - P(-1, 1) - P(1, -1) + P(-1, -1)) / 4.0);
             }
-        }
-        f[0] = (float)(u0[0] * ivt);
-        f[1] = (float)(u0[1] * ivt);
-        f[2] = (float)(u0[2] * ivt);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) f[3 + k] = (float)(T0[k] * iT);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            f[9 + 5 * k + 0] = (float)((phi[1][2][k] - phi[1][0][k]) / 2.0);
-            f[9 + 5 * k + 1] = (float)((phi[2][1][k] - phi[0][1][k]) / 2.0);
-            f[9 + 5 * k + 2] = (float)(phi[1][2][k] - 2.0 * phi[1][1][k] + phi[1][0][k]);
-            f[9 + 5 * k + 3] = (float)(phi[2][1][k] - 2.0 * phi[1][1][k] + phi[0][1][k]);
-            f[9 + 5 * k + 4] = (float)((phi[2][2][k] - phi[0][2][k] - phi[2][0][k] + phi[0][0][k]) / 4.0);
-        }
-        f[59 + species] = 1.f;
-        if (B) {     // direction of the cell-centred magnetic field
-            const double bx = B[c * 3], by = B[c * 3 + 1], bz = B[c * 3 + 2];
-            const double bn = sqrt(bx * bx + by * by + bz * bz);
-            if (bn > 1e-12) {
-                f[61] = (float)(bx / bn);
-                f[62] = (float)(by / bn);
-                f[63] = (float)(bz / bn);
+            f[59 + species] = 1.f;
+            if (B) {     // direction of the cell-centred magnetic field
+                const long long c = (long long)j * nx + i;
+                const double bx = B[c * 3], by = B[c * 3 + 1], bz = B[c * 3 + 2];
+                const double bn = sqrt(bx * bx + by * by + bz * bz);
+                if (bn > 1e-12) {
+                    f[61] = (float)(bx / bn);
+                    f[62] = (float)(by / bn);
+                    f[63] = (float)(bz / bn);
+                }
             }
         }
     }
-    unsigned short* o = x + c * kIn;
+    __syncthreads();     // every read of the stencil values is done: the union now holds the output
 #pragma unroll
-    for (int k = 0; k < 64; k += 2) {
-        const unsigned lo = bf16_of(f[k]), hi = bf16_of(f[k + 1]);
-        *reinterpret_cast<unsigned*>(o + k) = lo | (hi << 16);
+    for (int k = 0; k < 32; ++k) L.out[tid][k] = bf16_of(f[2 * k]) | ((unsigned)bf16_of(f[2 * k + 1]) << 16);
+    __syncthreads();
+    for (int q = tid; q < kFeatRows * kFeatCols * 32; q += blockDim.x) {
+        const int rr = q >> 5, part = q & 31;
+        const int ii = i0 + rr % kFeatCols, jj = j0 + rr / kFeatCols;
+        if (ii < nx && jj < ny)
+            reinterpret_cast<unsigned*>(x + ((long long)jj * nx + ii) * kIn)[part] = L.out[rr][part];
     }
-    scale[c] = sc;
+    if (valid) scale[(long long)j * nx + i] = sc;
 }
 
 // Heat-flux tensor of one cell from its raw moments (TRIPLES order).
@@ -681,8 +708,8 @@ constexpr int kJudgeBlocks = 256;
 hipError_t launch_mlp_features_set(const MlpSet& S, int ns, int s0, int stride, const double* B, int nx, int ny,
                                    unsigned short* x, double* scale, hipStream_t st) {
     if (ns < 1 || ns > 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mlp_features_kernel, dim3((nx + 63) / 64, ny, ns), dim3(64), 0, st, S, s0, stride, B, nx, ny,
-                       x, scale);
+    hipLaunchKernelGGL(mlp_features_kernel, dim3((nx + kFeatCols - 1) / kFeatCols, (ny + kFeatRows - 1) / kFeatRows, ns),
+                       dim3(kFeatRows * kFeatCols), 0, st, S, s0, stride, B, nx, ny, x, scale);
     return hipGetLastError();
 }
 

@@ -53,10 +53,15 @@ def _perturbed_gem_moments(nx, ny, nv, seed):
     return cfg, moms
 
 
-def test_features_and_targets_match_oracle():
+@pytest.mark.parametrize("nx,ny", [(13, 7), (150, 9)])
+def test_features_and_targets_match_oracle(nx, ny):
+    """13 x 7: one tile of the features kernel (64 columns x 4 rows) with
+    ragged rows and columns; 150 x 9: three tiles per row and three rows of
+    tiles, ragged at both ends, with the x wrap and the y mirror crossing
+    tile edges."""
     import torch
     from paper_2109_06743_amd import vl
-    nx, ny, nv = 13, 7, 8
+    nv = 8
     cfg, moms = _perturbed_gem_moments(nx, ny, nv, 3)
     ctx = vl.Context(cfg, "f32")
     cells = nx * ny
