@@ -142,9 +142,13 @@ faces3_kernel(FluidSet S, double wa, double wb, FluidArgs A, int nbx_row, int nb
     const int col0 = yface ? (b % nby_col) * kYCols : (b % nbx_row) * kXTile;
     const int nstage = yface ? kStageCells : kXTile + 3;
     const int nrec = yface ? kRecCells : kXTile + 1;
+    // Thread t < 240 handles component k = t % 20 of cells t / 20, + 12, + 24, ...
+    // in the staging and reconstruction loops (no index division per element).
+    constexpr int kCellsPerPass = kFaceThreads / 20;
+    const int kc = (int)threadIdx.x % 20, c0 = (int)threadIdx.x / 20;
     // staged cell l: x tile (row0, col0 - 1 + l); y tile (row0 - 2 + l / kYCols, col0 + l % kYCols)
-    for (int t = threadIdx.x; t < nstage * 20; t += kFaceThreads) {
-        const int l = t / 20, k = t % 20;
+    for (int l = c0 < kCellsPerPass ? c0 : nstage; l < nstage; l += kCellsPerPass) {
+        const int k = kc;
         const int j = yface ? row0 - 2 + l / kYCols : row0;
         const int i = yface ? col0 + l % kYCols : col0 - 1 + l;
         // y tiles: rows past ny + 1 and columns past nx feed no valid face
@@ -154,8 +158,8 @@ faces3_kernel(FluidSet S, double wa, double wb, FluidArgs A, int nbx_row, int nb
     __syncthreads();
     // reconstructed cell r: x tile (row0, col0 + r); y tile (row0 - 1 + r / kYCols, col0 + r % kYCols)
     const int sstep = yface ? kYCols : 1;
-    for (int t = threadIdx.x; t < nrec * 20; t += kFaceThreads) {
-        const int r = t / 20, k = t % 20;
+    for (int r = c0 < kCellsPerPass ? c0 : nrec; r < nrec; r += kCellsPerPass) {
+        const int k = kc;
         double l, h;
         cweno(raw[r][k], raw[r + sstep][k], raw[r + 2 * sstep][k], l, h);
         lo[r][k] = l;
@@ -179,24 +183,27 @@ faces3_kernel(FluidSet S, double wa, double wb, FluidArgs A, int nbx_row, int nb
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < kXTile * 10; t += kFaceThreads) {
-        const int f = t / 10, k = t % 10;
+    // thread t < 250: flux component k = t % 10 of faces t / 10 and t / 10 + 25
+    const int k = (int)threadIdx.x % 10;
+    // flux component k: n -> nu_d, nu_i -> P_id / m, P_ab -> Qcal_abd
+    int src;
+    double sc = 1.0;
+    if (k == 0) {
+        src = 1 + d;
+    } else if (k < 4) {
+        src = 4 + p_index(k - 1, d);
+        sc = 1.0 / A.m;
+    } else {
+        const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+        src = 10 + q_index(ia[k - 4], ib[k - 4], d);
+    }
+    constexpr int kFacesPerPass = kFaceThreads / 10;
+    for (int f = (int)threadIdx.x < 10 * kFacesPerPass ? (int)threadIdx.x / 10 : kXTile; f < kXTile;
+         f += kFacesPerPass) {
         if (!face_ok(f)) continue;
         const double* Lm = hi[f];
         const double* Lp = lo[f + sstep];
         const double a = fmax(spd[0][f], spd[1][f]);
-        // flux component k: n -> nu_d, nu_i -> P_id / m, P_ab -> Qcal_abd
-        int src;
-        double sc = 1.0;
-        if (k == 0) {
-            src = 1 + d;
-        } else if (k < 4) {
-            src = 4 + p_index(k - 1, d);
-            sc = 1.0 / A.m;
-        } else {
-            const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
-            src = 10 + q_index(ia[k - 4], ib[k - 4], d);
-        }
         const double Fm = Lm[src] * sc, Fp = Lp[src] * sc;
         long long h;
         if (yface) h = (long long)(row0 + f / kYCols) * A.nx + col0 + f % kYCols;
