@@ -221,15 +221,17 @@ def test_adam_step_matches_oracle_and_training_descends():
     assert np.all(d["W4"][10:] == 0.0) and np.all(d["b4"][10:] == 0.0)
 
 
-def test_train_epoch_equals_train_steps_on_gathered_batches():
+@pytest.mark.parametrize("n,batch,nsteps", [(3000, 512, 4), (12000, 5000, 2)])
+def test_train_epoch_equals_train_steps_on_gathered_batches(n, batch, nsteps):
     """vl_mlp_train_epoch gathers the batch rows inside the gradient kernel:
-    its parameters after four steps equal those of four vl_mlp_train_step
+    its parameters after the steps equal those of as many vl_mlp_train_step
     calls on the gathered batches (same kernels, same order: bitwise), and an
-    index outside the rows counts as a padding row."""
+    index outside the rows counts as a padding row.  Batches of 512 rows give
+    one 16-row tile per gradient block; 5000 rows give two per block (the
+    next tile's rows are prefetched) and a half tile at the end."""
     import torch
     from paper_2109_06743_amd import vl
     ctx = vl.Context(dict(W.gem(nx=4, ny=2, nv=8)[0]), "f32")
-    n, batch, nsteps = 3000, 512, 4
     xv, xb = _random_x(n, 11)
     rng = np.random.default_rng(12)
     t = np.zeros((n, 16), dtype=np.float32)
