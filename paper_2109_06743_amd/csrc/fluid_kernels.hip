@@ -468,6 +468,15 @@ hipError_t launch_fluid_rk3_3v(double* U, const double* mom_t, const double* mom
                                    st, per);
 }
 
+// The update kernel reads each cell's 10-double records with 8-byte lane
+// accesses 80 bytes apart, so a wave's ten loads share the same lines; with
+// many waves per CU those lines are evicted between the loads and fetched
+// again.  Dynamic LDS that the kernel does not use caps it at four one-wave
+// blocks per CU (one wave per SIMD): 2048 x 1024 cells x 2 species, 7.35 ->
+// 6.89 ms per fluid-only step (two waves per SIMD: 7.08, five: 7.86).  The
+// faces kernel goes the other way (capped at four blocks per CU: 9.03 ms).
+constexpr unsigned kUpdateLdsCap = 40960;
+
 hipError_t launch_fluid_stage_3v_set(const FluidSet& S, int ns, double wa, double wb, const double* E,
                                      const double* B, double a, double b, double dt, int nx, int ny, double dx,
                                      double dy, hipStream_t st, int per) {
@@ -485,7 +494,7 @@ hipError_t launch_fluid_stage_3v_set(const FluidSet& S, int ns, double wa, doubl
         grad = grad || S.gchi[s] != 0.0;
     }
     if (grad) hipLaunchKernelGGL(closure_source3_kernel, gc, blk, 0, st, S, A);
-    hipLaunchKernelGGL(update3_kernel, gc, blk, 0, st, S, E, B, a, b, dt, A);
+    hipLaunchKernelGGL(update3_kernel, gc, blk, kUpdateLdsCap, st, S, E, B, a, b, dt, A);
     return hipGetLastError();
 }
 
