@@ -167,6 +167,14 @@ __global__ void axpby_kernel(const double* __restrict__ x, const double* __restr
     if (i < n) out[i] = a * x[i] + b * y[i];
 }
 
+// The B-curl kernel reads the current from the species' moment records (8-byte
+// lanes 80 or 160 bytes apart, several records per lane): dynamic LDS that it
+// does not use caps it at eight one-wave blocks per CU (two waves per SIMD),
+// so fewer waves evict the lines those loads share.  2048 x 1024 cells: the
+// three half-step kernels 0.74 -> 0.50 ms per fluid-only step (one wave per
+// SIMD 0.63, three 0.49, four 0.66).
+constexpr unsigned kCurlBLdsCap = 20480;
+
 hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const* mom, const double* q, int ns,
                                double dt, double c, double dx, double dy, hipStream_t st, int mstride, int per) {
     YeeView F = yee_view(yee, nx, ny);
@@ -181,7 +189,7 @@ hipError_t launch_maxwell_half(double* yee, int nx, int ny, const double* const*
     const double h = 0.5 * dt;
     dim3 blk(64), grid((nx + 63) / 64, ny + 1);
     hipLaunchKernelGGL(yee_curl_e_kernel, grid, blk, 0, st, F, 0.5 * h, dx, dy);
-    hipLaunchKernelGGL(yee_curl_b_kernel, grid, blk, 0, st, F, J, h, c * c, dx, dy);
+    hipLaunchKernelGGL(yee_curl_b_kernel, grid, blk, kCurlBLdsCap, st, F, J, h, c * c, dx, dy);
     hipLaunchKernelGGL(yee_curl_e_kernel, grid, blk, 0, st, F, 0.5 * h, dx, dy);
     return hipGetLastError();
 }
