@@ -686,17 +686,26 @@ mlp_judge_partial_kernel(MlpSet S, const double* __restrict__ scale, const float
 }
 
 // One block per species of the set.
-__global__ void mlp_judge_finish_kernel(MlpSet S, const double* __restrict__ part, int nblocks, double tol) {
-    if (threadIdx.x != 0) return;
-    const int sp = blockIdx.x;
+// One wave per species: lane l adds partials l, l + 64, ... (the loads of
+// all lanes in flight together), then a butterfly over the wave: a fixed
+// order of additions on every call.
+__global__ void __launch_bounds__(64)
+mlp_judge_finish_kernel(MlpSet S, const double* __restrict__ part, int nblocks, double tol) {
+    const int sp = blockIdx.x, lane = threadIdx.x;
     int* __restrict__ fallback = S.fallback[sp];
     double* __restrict__ err = S.err[sp];
     part += (size_t)sp * 2 * nblocks;
     double e2 = 0.0, k2 = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = lane; b < nblocks; b += 64) {
         e2 += part[2 * b];
         k2 += part[2 * b + 1];
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e2 += __shfl_xor(e2, o, 64);
+        k2 += __shfl_xor(k2, o, 64);
+    }
+    if (lane != 0) return;
     const double r = sqrt(e2) / fmax(sqrt(k2), 1e-300);
     *err = r;
     *fallback = !(r <= tol);
