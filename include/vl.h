@@ -105,11 +105,10 @@ vl_status vl_destroy(vl_ctx* ctx);
  * Sec. 2.1): x-sweep by v_x tau/dx cells (periodic), then in 2X3V a y-sweep
  * by v_y tau/dy cells between reflecting walls, both with the PFC limiter
  * bound max(f_in).  In 2X3V the two sweeps run fused in one pass (the
- * x-swept array is never stored).  f_in is not modified.  f_work is not
- * used (may be NULL; kept for source compatibility).  f_out must not alias
- * f_in (VL_EALIAS). */
-vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, void* f_work,
-                          double tau, vl_stream stream);
+ * x-swept array is never stored).  f_in is not modified.  f_out must not
+ * alias f_in (VL_EALIAS). */
+vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, double tau,
+                          vl_stream stream);
 
 /* Acceleration V(tau) of species s (Eq. 1, (q/m)(E + v x B) . grad_v f) with
  * zero-flux velocity boundaries (Sec. 2.1).  E, B are cell-centred FP64

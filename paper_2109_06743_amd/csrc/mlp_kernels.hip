@@ -685,7 +685,6 @@ mlp_judge_partial_kernel(MlpSet S, const double* __restrict__ scale, const float
     }
 }
 
-// One block per species of the set.
 // One wave per species: lane l adds partials l, l + 64, ... (the loads of
 // all lanes in flight together), then a butterfly over the wave: a fixed
 // order of additions on every call.

@@ -498,29 +498,19 @@ fit3_params_kernel(const double* __restrict__ mom_pre, double* __restrict__ U, l
 // the storage type, FP64 across pencils), then the exchange, clip (counted
 // per wave with a ballot), FP64 post-fit moments and the FP64 rescale.  The
 // block sums use the reduce-scatter (block_sum_rs).
-#ifndef FIT_KEEP_G
-#define FIT_KEEP_G 1
-#endif
-#ifndef FIT16_NW
-#define FIT16_NW 2
-#define FIT16_NT 2
-#endif
-#ifndef FIT12_NW
-#define FIT12_NW 1
-#define FIT12_NT 3
-#endif
+// Launch shapes: 16^3 two waves of two pencils per thread, 12^3 one wave of
+// three pencils per lane.
+constexpr int kFit16Waves = 2, kFit16Pencils = 2;
+constexpr int kFit12Waves = 1, kFit12Pencils = 3;
 template <class T, int N, int NW, int NT>
 __global__ void __launch_bounds__(64 * NW)
-#if defined(FIT_WPE)
-__attribute__((amdgpu_waves_per_eu(FIT_WPE)))
-#endif
 fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
                  unsigned* __restrict__ clip_part, VGrid G, XTable X, typename Bits<T>::U* __restrict__ max_out) {
     constexpr int NTH = 64 * NW;
     // every thread owns NT whole pencils (no idle positions to mask)
     constexpr bool kFull = NT * NTH == N * N;
     // keeping the pass-1 exponentials in registers pays while they fit
-    constexpr bool kKeep = FIT_KEEP_G && NT * N <= 48;
+    constexpr bool kKeep = NT * N <= 48;
     __shared__ double red[NW * 21];
     __shared__ double fin_s[21];
     const int tid = threadIdx.x;
@@ -829,8 +819,8 @@ hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, 
                            cells, a.m, ExpK<T>::scale, P, cnt);
         // waves per cell and pencils per thread: every lane busy for 16^3, 3/4 for 12^3
         if constexpr (sizeof(T) == 4) {
-            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, FIT16_NW, FIT16_NT>), grid, dim3(64 * FIT16_NW), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
-            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, FIT12_NW, FIT12_NT>), grid, dim3(64 * FIT12_NW), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, kFit16Waves, kFit16Pencils>), grid, dim3(64 * kFit16Waves), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, kFit12Waves, kFit12Pencils>), grid, dim3(64 * kFit12Waves), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == kBigCube)   // 640 threads, two pencils each (1156 pencils)
                 hipLaunchKernelGGL((fit3_cube_kernel<T, kBigCube, 10, 2>), grid, dim3(640), 0, st, fin, fout, P,

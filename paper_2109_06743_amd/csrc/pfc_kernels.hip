@@ -10,6 +10,8 @@
 // phi(j) the limited partial flux of cell j (pfc_phi).  Negative shifts run
 // the same formula on the mirrored pencil.  Integer shifts give a = 0 and
 // therefore an exact (bitwise) shift.
+#include <climits>
+
 #include "vl_internal.h"
 
 namespace vl {
@@ -121,100 +123,128 @@ __device__ __forceinline__ T sub_cell_flux(T w, T Dm, T Dp, T a, T cA, T cB, T F
 
 // ---------------------------------------------------------------------------
 // Fused X(tau) for 2X3V: the x sweep and then the y sweep with one f_inf, in
-// one pass over f.  A thread owns one (v_x, |v_y|, v_z) pair, C adjacent x
-// cells and a segment of S positions of its y pencils (S chosen at launch,
-// xy_segment).  Reflecting walls: one
-// doubled pencil (positions 0..ny-1: rows of the +v_y half; ny..2ny-1: rows
-// ny-1..0 of the -v_y half).  Periodic y: two cyclic pencils of ny positions
-// (the +v_y half walked upward, the -v_y half downward); either way every
-// walk runs downwind.  Addresses are a 64-bit row base plus a 32-bit offset
-// within the row (a row is below 4 GiB, checked on the host); the row of a
-// load is the same in every lane.  It walks its segment, x-sweeping the C
-// cells of each position on the fly (a window of C+3 inputs in registers,
-// the windows of the next three positions in flight) and feeding the result
-// to the y update, f'(q) = P(q-K) + phi(q-K-1) - phi(q-K) with P the x-swept
-// pencil, so the intermediate array never reaches memory.  Per segment the x
-// sweep runs S+3 times for S outputs; the extra rows are re-read from cache.
-// Work order: x strip fastest, so neighbouring strips stream the same rows
-// at the same time.
-template <class T, int C>
+// one pass over f.
+//
+// Work item: one wave = 64 consecutive velocity indices of the block (a
+// "chunk"; the block of a cell is contiguous, so a wave's access to one cell
+// is a 256-byte run -- whole 128-byte lines wherever the block size is a
+// multiple of 32 elements), C adjacent x cells (a strip) and a segment of S
+// rows.  Every lane owns one velocity v and writes only v.  All lanes walk
+// the rows upward together, so each step reads the same row in every lane
+// and the wave reads whole lines of it: a lane whose v_y is negative walks
+// against its flow and emits each output K_y + 1 rows after the upward
+// lanes (its output at row r depends on the x-swept rows r+K_y-1 .. r+K_y+2,
+// which it holds by then).
+//
+// y boundary, with virtual rows q outside [0, ny): periodic: row q mod ny of
+// v itself.  Reflecting walls: the pencil of v continues beyond a wall with
+// the pencil of its mirror velocity v' (v_y -> -v_y) read backwards, i.e.
+// q mod 2ny = q' < ny is row q' of v and q' >= ny is row 2ny-1-q' of v'.
+// Both velocities of a mirror pair take the shift of the positive one, so
+// the flux through a wall that the lane of v sends out and the flux the lane
+// of v' takes in are computed from the same values in the same order: the
+// wall exchange conserves mass exactly.
+//
+// For each row the x sweep of the C cells runs on the fly (a window of C+3
+// inputs in registers, three rows of loads in flight while one is
+// computed) and feeds the y update, so the x-swept array never reaches
+// memory.  A load is a wave-uniform row base plus a per-lane 32-bit byte
+// offset; the stores of one step (rows i-2-Kmax .. i-1+Kmax across the wave)
+// are a wave-uniform base plus per-lane 32-bit offsets where those rows span
+// less than 4 GiB (WIDE = false), else a per-lane 64-bit address.
+// Work order: chunk fastest, then strip, then segment, so the waves in
+// flight cover whole rows and neighbouring strips (x halos) together.
+struct XYArgs {
+    int nx, ny, Nv, nvy, nvz, S, nchunks, nst, nseg, per;
+    float inv_nvz, inv_nvyz;
+    double vx_lo, dvx, tau_dx, vy_lo, dvy, tau_dy;
+};
+
+template <class T, int C, bool WIDE>
 __global__ void __launch_bounds__(256)
-pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int S, int nx, int ny, int Nv, int nvx, int nvy, int nvz,
-              float inv_nvz, float inv_half, double vx_lo, double dvx, double tau_dx, double vy_lo, double dvy,
-              double tau_dy, int per, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
-    const int half = (nvy + 1) / 2;
-    const int npairs = nvx * half * nvz;
-    const int L = 2 * ny;
-    const unsigned nsh = (unsigned)(ny + S - 1) / S;                  // periodic: segments per pencil
-    const unsigned nst = (unsigned)(nx + C - 1) / C, nseg = per ? 2 * nsh : (unsigned)(L + S - 1) / S;
-    const unsigned wi = xcd_work_index(blockIdx.x, gridDim.x);
-    const int c0 = (int)(wi % nst) * C;
-    const unsigned kseg = (wi / nst) % nseg;
-    const int h0 = per ? (int)(kseg / nsh) : 0;                       // periodic: which pencil
-    const int i0 = per ? h0 * ny + (int)(kseg % nsh) * S : (int)kseg * S;
-    const int iend = per ? (h0 + 1) * ny : L;
-    const int pid = (int)(wi / (nst * nseg)) * 256 + threadIdx.x;
+pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, XYArgs A, const T* __restrict__ finf_p,
+              typename Bits<T>::U* __restrict__ max_out) {
+    const unsigned gw = xcd_work_index(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned chunk = gw % (unsigned)A.nchunks;
+    const unsigned rest = gw / (unsigned)A.nchunks;
+    const int c0 = (int)(rest % (unsigned)A.nst) * C;
+    const unsigned seg = rest / (unsigned)A.nst;
     const T F2 = T(2) * *finf_p;
     T mx = T(0);
-    if (pid < npairs) {
-        const int r1 = row_of(pid, inv_nvz);
-        const int ivz = pid - r1 * nvz;
-        const int ivx = row_of(r1, inv_half);
-        const int jh = r1 - ivx * half;
-        const int jup = nvy - half + jh;
-        const int jdn = nvy - 1 - jup;
-        const unsigned vu = (unsigned)((ivx * nvy + jup) * nvz + ivz), vd = (unsigned)((ivx * nvy + jdn) * nvz + ivz);
-        const unsigned rs = (unsigned)nx * (unsigned)Nv;     // row stride (< 2^31, checked on the host)
-        // x: uniform shift along the row (the same for both halves)
-        const double sxd = (vx_lo + (ivx + 0.5) * dvx) * tau_dx;
+    if (seg < (unsigned)A.nseg) {                    // wave-uniform
+        const int nx = A.nx, ny = A.ny, Nv = A.Nv;
+        const int vl = (int)chunk * kWave + lane;
+        const bool active = vl < Nv;
+        const int v = active ? vl : Nv - 1;          // idle lanes walk a real pencil and store nothing
+        const int ivx = row_of(v, A.inv_nvyz);
+        const int jy = row_of(v, A.inv_nvz) - ivx * A.nvy;
+        const int jm = A.nvy - 1 - jy;
+        const bool up = jy >= jm;                    // v_y >= 0 (an odd grid's middle cell does not move)
+        // y: both members of a mirror pair move by the shift of the positive one
+        const double syd = (jy == jm) ? 0.0 : (A.vy_lo + ((up ? jy : jm) + 0.5) * A.dvy) * A.tau_dy;
+        const ShiftT<T> shy(syd);
+        const int L = A.per ? ny : 2 * ny;
+        const int Ky = shy.K < L ? shy.K : shy.K % L;
+        int Kmax = Ky;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) Kmax = max(Kmax, __shfl_xor(Kmax, o, kWave));
+        Kmax = __builtin_amdgcn_readfirstlane(Kmax);
+        // x: uniform shift along the row
+        const double sxd = (A.vx_lo + (ivx + 0.5) * A.dvx) * A.tau_dx;
         const bool posx = sxd >= 0.0;
         const Shift<T> shx(fabs(sxd));
         const int Kx = shx.K < nx ? (int)shx.K : (int)(shx.K % nx);
-        // y: every pencil moves by sy >= 0 cells in its walking order
-        const double syd = (jup == jdn) ? 0.0 : (vy_lo + (jup + 0.5) * dvy) * tau_dy;
-        const ShiftT<T> shy(syd);
-        const int Ky = per ? shy.K % ny : (shy.K < L ? shy.K : shy.K % L);
-        // first (upwind) column of the x window
-        int wcol0 = posx ? c0 - Kx - 2 : c0 + Kx + C + 1;
-        while (wcol0 < 0) wcol0 += nx;
-        while (wcol0 >= nx) wcol0 -= nx;
-        // row of position j and whether it holds the -v_y velocity
-        auto row_of_pos = [&](int j, bool& dn) -> int {
-            if (per) {
-                int r = (j - h0 * ny) % ny;
-                if (r < 0) r += ny;
-                dn = h0 != 0;
-                return h0 ? ny - 1 - r : r;
-            }
-            j %= L;
-            if (j < 0) j += L;
-            dn = j >= ny;
-            return j < ny ? j : L - 1 - j;
-        };
-        // A load is a wave-uniform row base plus a byte offset within the row
-        // (rows are below 4 GiB, checked on the host).  The offsets of the
-        // window for the half being walked are cached in boff and rebuilt
-        // where the walk crosses into the other half (at most twice a segment).
-        const size_t rowbytes = (size_t)rs * sizeof(T);
+        int col = posx ? c0 - Kx - 2 : c0 + Kx + C + 1;  // first (upwind) column of the x window
+        while (col < 0) col += nx;
+        while (col >= nx) col -= nx;
         unsigned boff[C + 3];
-        int bhalf = -1;                               // half cached in boff (uniform)
-        auto load = [&](int j, T (&W)[C + 3]) {      // j is the same in every lane
-            bool dn;
-            const char* base = reinterpret_cast<const char*>(fin) + (size_t)row_of_pos(j, dn) * rowbytes;
-            if ((int)dn != bhalf) {
-                const unsigned v = dn ? vd : vu;
-                int col = wcol0;                      // window columns, upwind to downwind
 #pragma unroll
-                for (int w = 0; w < C + 3; ++w) {
-                    boff[w] = ((unsigned)col * (unsigned)Nv + v) * (unsigned)sizeof(T);
-                    col += posx ? 1 : -1;
-                    if (col == nx) col = 0;
-                    if (col < 0) col = nx - 1;
+        for (int w = 0; w < C + 3; ++w) {
+            boff[w] = ((unsigned)col * (unsigned)Nv + (unsigned)v) * (unsigned)sizeof(T);
+            col += posx ? 1 : -1;
+            if (col == nx) col = 0;
+            if (col < 0) col = nx - 1;
+        }
+        const unsigned dmir = (unsigned)((jm - jy) * A.nvz) * (unsigned)sizeof(T);   // v' - v (mod 2^32)
+        const size_t rowbytes = (size_t)nx * Nv * sizeof(T);
+        // output rows of the segment and the steps that produce them
+        const int r0 = (int)seg * A.S;
+        const int r1 = min(r0 + A.S, ny);
+        const int ib = r0 + 1 - Kmax, ie = r1 + 1 + Kmax;
+        const int dr = up ? Ky - 1 : -2 - Ky;        // output row = step + dr
+        const int ilo = active ? r0 - dr : INT_MAX, ihi = r1 - dr;
+        const int drmin = -2 - Kmax;
+        unsigned soff[C];
+        bool colok[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int oc = posx ? c0 + c : c0 + C - 1 - c;   // the x outputs run upwind to downwind
+            colok[c] = oc < nx;
+            const unsigned within = ((unsigned)oc * (unsigned)Nv + (unsigned)v) * (unsigned)sizeof(T);
+            soff[c] = WIDE ? within : (unsigned)(dr - drmin) * (unsigned)rowbytes + within;
+        }
+        const bool full = c0 + C <= nx;
+        // virtual row q -> (row, mirror?): wave-uniform
+        auto load = [&](int q, T (&W)[C + 3]) {
+            int row = q;
+            bool mir = false;
+            if ((unsigned)q >= (unsigned)ny) {
+                row = q % L;
+                if (row < 0) row += L;
+                if (!A.per && row >= ny) {
+                    mir = true;
+                    row = L - 1 - row;
                 }
-                bhalf = (int)dn;
             }
+            const char* base = reinterpret_cast<const char*>(fin) + (size_t)row * rowbytes;
+            if (!mir) {
 #pragma unroll
-            for (int w = 0; w < C + 3; ++w) W[w] = *reinterpret_cast<const T*>(base + boff[w]);
+                for (int w = 0; w < C + 3; ++w) W[w] = *reinterpret_cast<const T*>(base + boff[w]);
+            } else {
+#pragma unroll
+                for (int w = 0; w < C + 3; ++w) W[w] = *reinterpret_cast<const T*>(base + (boff[w] + dmir));
+            }
         };
         // partial flux without the clamp of r2 at zero: every sweep's input
         // lies in [0, f_inf] up to rounding (as in the velocity sweeps)
@@ -230,76 +260,70 @@ pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, int S, int nx, in
                 D = Dn;
             }
         };
-        const bool full = c0 + C <= nx;               // every column of the strip exists
-        const int i1 = i0 + S < iend ? i0 + S : iend;
-        // y state per column: P at the current position, its difference to the
-        // previous one and the flux through the face below it
-        T Pc[C], Dm[C], phy[C];
+        // y state per column: P1 = P(i-1), P2 = P(i-2) and ph = the flux of
+        // cell i-2 in the lane's direction of motion (up: through its upper
+        // face, from P(i-3), P(i-2), P(i-1); down: through its lower face)
+        T P1[C], P2[C], ph[C];
         {
-            T Wa[C + 3], Pa[C], Pb[C];
-            load(i0 - 2, Wa);
+            T Wa[C + 3], Pa[C];
+            load(ib - 3, Wa);
             xsweep(Wa, Pa);
-            load(i0 - 1, Wa);
-            xsweep(Wa, Pb);
-            load(i0, Wa);
-            xsweep(Wa, Pc);
+            load(ib - 2, Wa);
+            xsweep(Wa, P2);
+            load(ib - 1, Wa);
+            xsweep(Wa, P1);
 #pragma unroll
-            for (int r = 0; r < C; ++r) {
-                Dm[r] = Pc[r] - Pb[r];
-                phy[r] = sub_cell_flux(Pb[r], Pb[r] - Pa[r], Dm[r], shy.a, shy.ac1, shy.ac2, F2);
+            for (int c = 0; c < C; ++c) {
+                const T d1 = P2[c] - Pa[c], d0 = P1[c] - P2[c];
+                ph[c] = sub_cell_flux(P2[c], up ? d1 : -d0, up ? d0 : -d1, shy.a, shy.ac1, shy.ac2, F2);
             }
         }
-        // one position: the window Wc (position i+1) is x-swept and the y update
-        // of position i is stored; the window of i+4 is loaded into Wn meanwhile
-        // (three positions of loads stay in flight while one is computed)
+        // step i: x-sweep row i (window Wc), the flux of cell i-1, the
+        // output of cell i-1 (up, stored at row i-1+Ky) or i-2 (down, at row
+        // i-2-Ky); the window of row i+3 is loaded into Wn meanwhile
         auto step = [&](int i, const T (&Wc)[C + 3], T (&Wn)[C + 3]) {
-            if (i + 3 < i1) load(i + 4, Wn);
-            T Pn[C];
-            xsweep(Wc, Pn);
-            bool dn;
-            const int ro = row_of_pos(i + Ky, dn);
-            T* op = fout + (size_t)ro * rs + (dn ? vd : vu);
+            if (i + 3 <= ie) load(i + 3, Wn);
+            T P0[C];
+            xsweep(Wc, P0);
             T o[C];
 #pragma unroll
-            for (int r = 0; r < C; ++r) {
-                const T Dn = Pn[r] - Pc[r];
-                const T phi = sub_cell_flux(Pc[r], Dm[r], Dn, shy.a, shy.ac1, shy.ac2, F2);
-                o[r] = fmax(Pc[r] + phy[r] - phi, T(0));
-                phy[r] = phi;
-                Dm[r] = Dn;
-                Pc[r] = Pn[r];
+            for (int c = 0; c < C; ++c) {
+                const T d1 = P1[c] - P2[c], d0 = P0[c] - P1[c];
+                const T phn = sub_cell_flux(P1[c], up ? d1 : -d0, up ? d0 : -d1, shy.a, shy.ac1, shy.ac2, F2);
+                const T base = up ? P1[c] : P2[c];
+                const T fin_ = up ? ph[c] : phn;
+                const T fout_ = up ? phn : ph[c];
+                o[c] = fmax(base + fin_ - fout_, T(0));
+                ph[c] = phn;
+                P2[c] = P1[c];
+                P1[c] = P0[c];
             }
-            if (full) {
+            if (i >= ilo && i < ihi) {
+                char* ob = WIDE ? reinterpret_cast<char*>(fout) + (size_t)(i + dr) * rowbytes
+                                : reinterpret_cast<char*>(fout) + (long long)(i + drmin) * (long long)rowbytes;
 #pragma unroll
-                for (int r = 0; r < C; ++r) {
-                    op[(unsigned)(posx ? c0 + r : c0 + C - 1 - r) * (unsigned)Nv] = o[r];
-                    mx = max_nonneg(mx, o[r], F2);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < C; ++r) {
-                    const int col = posx ? c0 + r : c0 + C - 1 - r;
-                    if (col < nx) {
-                        op[(unsigned)col * (unsigned)Nv] = o[r];
-                        mx = max_nonneg(mx, o[r], F2);
+                for (int c = 0; c < C; ++c) {
+                    if (full || colok[c]) {
+                        *reinterpret_cast<T*>(ob + soff[c]) = o[c];
+                        mx = max_nonneg(mx, o[c], F2);
                     }
                 }
             }
         };
         T W0[C + 3], W1[C + 3], W2[C + 3], W3[C + 3];
-        load(i0 + 1, W0);
-        if (i0 + 1 < i1) load(i0 + 2, W1);
-        if (i0 + 2 < i1) load(i0 + 3, W2);
-        int i = i0;
-        for (; i + 3 < i1; i += 4) {                  // four positions: the windows rotate
+        load(ib, W0);
+        if (ib + 1 <= ie) load(ib + 1, W1);
+        if (ib + 2 <= ie) load(ib + 2, W2);
+        int i = ib;
+        for (; i + 3 <= ie; i += 4) {                 // four rows: the windows rotate
             step(i, W0, W3);
             step(i + 1, W1, W0);
             step(i + 2, W2, W1);
             step(i + 3, W3, W2);
         }
-        if (i < i1) step(i, W0, W3);
-        if (i + 1 < i1) step(i + 1, W1, W0);
-        if (i + 2 < i1) step(i + 2, W2, W1);
+        if (i <= ie) step(i, W0, W3);
+        if (i + 1 <= ie) step(i + 1, W1, W0);
+        if (i + 2 <= ie) step(i + 2, W2, W1);
     }
     if (max_out) block_max_part(mx, max_out);
 }
@@ -939,11 +963,12 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
 // x cells per thread (FP32: 8; FP64 registers allow 4)
 template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
 
-// Positions per segment of the fused X operator: 128, or, where that leaves
-// the GPU with fewer blocks than fit on it at once (three per CU), the
-// shortest segments (at least 16 positions) whose blocks still all fit, so
-// one round of blocks covers the launch with more of them walking.
-static int xy_segment(int nx, int ny, long long npairs, int per, int cols) {
+// Rows per segment of the fused X operator.  Waves in flight per CU: 12 in
+// FP32, 8 in FP64 (register-limited to 3 and 2 per SIMD).  A wave walks S + 2 Kmax + 4 rows for S outputs;
+// the model cost rounds(S) * (S + 4 + 2 Kmax), with rounds the number of
+// times the waves of the launch refill the GPU, picks the segment count
+// (at most 64, segments of at least 8 rows).
+static int xy_cus() {
     static int cus = 0;
     if (cus <= 0) {
         int d = 0;
@@ -951,49 +976,82 @@ static int xy_segment(int nx, int ny, long long npairs, int per, int cols) {
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || cus <= 0)
             cus = 256;
     }
-    const long long npb = ((npairs + 255) / 256) * ((nx + cols - 1) / cols) * (per ? 2 : 1);
-    const int L = per ? ny : 2 * ny;              // positions of one pencil
-    const long long resident = 3LL * cus;
-    int best = L < 128 ? L : 128;
-    for (int k = (L + best - 1) / best + 1; k <= L / 16; ++k) {
-        const int S = (L + k - 1) / k;
-        if (npb * ((L + S - 1) / S) > resident) break;
-        best = S;
+    return cus;
+}
+constexpr int kXyMaxSeg = 64;
+static int xy_segment(int ny, long long waves_per_seg, int kb, int waves_per_cu) {
+    const long long resident = (long long)waves_per_cu * xy_cus();
+    int bestS = ny;
+    double best = 0.0;
+    for (int n = 1; n <= kXyMaxSeg && n <= ny; ++n) {
+        const int S = (ny + n - 1) / n;
+        if (n > 1 && S < 8) break;
+        if ((ny + S - 1) / S != n) continue;      // the same split as a smaller n
+        const long long w = waves_per_seg * n;
+        const double cost = (double)((w + resident - 1) / resident) * (double)(S + 4 + 2 * kb);
+        if (n == 1 || cost < best * 0.999) {
+            best = cost;
+            bestS = S;
+        }
     }
-    return best;
+    return bestS;
 }
 
-template <class T>
-long long pfc_xy_blocks_t(int nx, int ny, int nvx, int nvy, int nvz, int per, int* seg = nullptr) {
-    const long long npairs = (long long)nvx * ((nvy + 1) / 2) * nvz;
-    const int S = xy_segment(nx, ny, npairs, per, xy_cols<T>());
-    if (seg) *seg = S;
-    const long long nseg = per ? 2LL * ((ny + S - 1) / S) : (2LL * ny + S - 1) / S;
-    return ((npairs + 255) / 256) * nseg * ((nx + xy_cols<T>() - 1) / xy_cols<T>());
+static long long xy_waves_per_seg(int nx, long long Nv, int cols) {
+    return ((Nv + kWave - 1) / kWave) * ((nx + cols - 1) / cols);
 }
+
+// Upper bound of the launch's blocks over every segment length it can pick
+// (sizes the per-block partial maxima).
 long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
-    // the largest grid over both storage types and both y boundaries
-    long long m = 0;
-    for (int per = 0; per < 2; ++per) {
-        const long long a = pfc_xy_blocks_t<float>(nx, ny, nvx, nvy, nvz, per);
-        const long long b = pfc_xy_blocks_t<double>(nx, ny, nvx, nvy, nvz, per);
-        m = a > m ? a : m;
-        m = b > m ? b : m;
-    }
-    return m;
+    const long long Nv = (long long)nvx * nvy * nvz;
+    const long long nseg = ny < kXyMaxSeg ? ny : kXyMaxSeg;
+    const long long w = xy_waves_per_seg(nx, Nv, 4) * nseg;    // the narrower FP64 strips
+    return (w + 3) / 4;
 }
 
 template <class T>
 hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vx_lo, double dvx,
                          double tau_dx, double vy_lo, double dvy, double tau_dy, int per, const void* finf,
                          void* max_out, void* part, hipStream_t st) {
-    const int Nv = nvx * nvy * nvz;
-    const int half = (nvy + 1) / 2;
-    int S = 0;
-    const long long blocks = pfc_xy_blocks_t<T>(nx, ny, nvx, nvy, nvz, per, &S);
-    hipLaunchKernelGGL((pfc_xy_kernel<T, xy_cols<T>()>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, S, nx,
-                       ny, Nv, nvx, nvy, nvz, 1.0f / (float)nvz, 1.0f / (float)half, vx_lo, dvx, tau_dx, vy_lo, dvy,
-                       tau_dy, per, (const T*)finf, (typename Bits<T>::U*)(max_out ? part : nullptr));
+    constexpr int C = xy_cols<T>();
+    XYArgs A;
+    A.nx = nx;
+    A.ny = ny;
+    A.Nv = nvx * nvy * nvz;
+    A.nvy = nvy;
+    A.nvz = nvz;
+    A.per = per;
+    A.inv_nvz = 1.0f / (float)nvz;
+    A.inv_nvyz = 1.0f / (float)(nvy * nvz);
+    A.vx_lo = vx_lo;
+    A.dvx = dvx;
+    A.tau_dx = tau_dx;
+    A.vy_lo = vy_lo;
+    A.dvy = dvy;
+    A.tau_dy = tau_dy;
+    A.nchunks = (A.Nv + kWave - 1) / kWave;
+    A.nst = (nx + C - 1) / C;
+    // bound of the whole-cell y shift (one more than the FP64 estimate: the
+    // kernel splits the shift in the storage type)
+    const double vymax = fmax(fabs(vy_lo), fabs(vy_lo + nvy * dvy));
+    const double kd = floor(vymax * tau_dy) + 1.0;
+    const int L = per ? ny : 2 * ny;
+    const int kb = kd >= (double)L ? L - 1 : (int)kd;
+    A.S = xy_segment(ny, xy_waves_per_seg(nx, A.Nv, C), kb, sizeof(T) == 4 ? 12 : 8);
+    A.nseg = (ny + A.S - 1) / A.S;
+    const long long waves = xy_waves_per_seg(nx, A.Nv, C) * A.nseg;
+    const long long blocks = (waves + 3) / 4;
+    // the stores of one step span rows i-2-Kmax .. i-1+Kmax of one pass
+    const size_t rowbytes = (size_t)nx * A.Nv * sizeof(T);
+    const bool wide = (double)(2 * kb + 3) * (double)rowbytes >= 4294967296.0;
+    auto* mo = (typename Bits<T>::U*)(max_out ? part : nullptr);
+    if (wide)
+        hipLaunchKernelGGL((pfc_xy_kernel<T, C, true>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, A,
+                           (const T*)finf, mo);
+    else
+        hipLaunchKernelGGL((pfc_xy_kernel<T, C, false>), dim3((unsigned)blocks), dim3(256), 0, st, fin, fout, A,
+                           (const T*)finf, mo);
     return finish_max<T>(max_out, part, blocks, st);
 }
 

@@ -174,7 +174,7 @@ size_t step_doubles(const vl_config& c) {
 
 // ------------------------------------------------------------ typed paths --
 template <class T>
-vl_status advect_x_typed(vl_ctx* ctx, int s, const T* fin, T* fout, T* fwork, double tau, const void* finf,
+vl_status advect_x_typed(vl_ctx* ctx, int s, const T* fin, T* fout, double tau, const void* finf,
                          void* max_x, void* max_y, hipStream_t st) {
     const vl_config& c = ctx->cfg;
     const vl_species& sp = c.sp[s];
@@ -185,7 +185,6 @@ vl_status advect_x_typed(vl_ctx* ctx, int s, const T* fin, T* fout, T* fwork, do
         return VL_OK;
     }
     // 2X3V: x and y sweeps fused into one pass (the x-swept array stays in registers)
-    (void)fwork;
     Timed tm(ctx, VL_T_PFC_X, st);
     VL_HIP((vl::launch_pfc_xy<T>(fin, fout, c.nx, c.ny, sp.nv[0], sp.nv[1], sp.nv[2], sp.v_lo[0], dv_of(sp, 0),
                                  tau / dx_of(c), sp.v_lo[1], dv_of(sp, 1), tau / dy_of(c),
@@ -466,13 +465,13 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
             T* f = (T*)S->f[s];
             T* tmp = (T*)S->f_tmp[s];
             // X(dt/2): f -> tmp; V(dt): tmp in place; X(dt/2): tmp -> f
-            if ((r = advect_x_typed<T>(ctx, s, f, tmp, nullptr, 0.5 * dt, slot(ctx, 0, s), nullptr, slot(ctx, 1, s),
+            if ((r = advect_x_typed<T>(ctx, s, f, tmp, 0.5 * dt, slot(ctx, 0, s), nullptr, slot(ctx, 1, s),
                                        st)) != VL_OK)
                 return r;
             if ((r = advect_v_typed<T>(ctx, s, tmp, tmp, E_h, B_h, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) !=
                 VL_OK)
                 return r;
-            if ((r = advect_x_typed<T>(ctx, s, tmp, f, nullptr, 0.5 * dt, slot(ctx, 2, s), nullptr,
+            if ((r = advect_x_typed<T>(ctx, s, tmp, f, 0.5 * dt, slot(ctx, 2, s), nullptr,
                                        c.fit ? nullptr : slot(ctx, 0, s), st)) != VL_OK)
                 return r;
             if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
@@ -516,7 +515,7 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         T* f = (T*)S->f[s];
         T* tmp = (T*)S->f_tmp[s];
         const double L = c.x_hi - c.x_lo;
-        if ((r = advect_x_typed<T>(ctx, s, f, tmp, nullptr, 0.5 * dt, slot(ctx, 0, s), slot(ctx, 1, s), nullptr, st)) !=
+        if ((r = advect_x_typed<T>(ctx, s, f, tmp, 0.5 * dt, slot(ctx, 0, s), slot(ctx, 1, s), nullptr, st)) !=
             VL_OK)
             return r;
         if ((r = moments_typed<T>(ctx, s, tmp, mom_half, st)) != VL_OK) return r;
@@ -527,7 +526,7 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
         if ((r = advect_v_typed<T>(ctx, s, tmp, tmp, S->fields, nullptr, dt, slot(ctx, 1, s), slot(ctx, 2, s), st)) !=
             VL_OK)
             return r;
-        if ((r = advect_x_typed<T>(ctx, s, tmp, f, nullptr, 0.5 * dt, slot(ctx, 2, s),
+        if ((r = advect_x_typed<T>(ctx, s, tmp, f, 0.5 * dt, slot(ctx, 2, s),
                                    c.fit ? nullptr : slot(ctx, 0, s), nullptr, st)) != VL_OK)
             return r;
         if ((r = moments_typed<T>(ctx, s, f, S->mom_pre[s], st)) != VL_OK) return r;
@@ -667,24 +666,22 @@ vl_status vl_destroy(vl_ctx* ctx) {
     return VL_OK;
 }
 
-vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, void* f_work, double tau,
-                          vl_stream stream) {
+vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, double tau, vl_stream stream) {
     vl_status r = check_species(ctx, s);
     if (r != VL_OK) return r;
     if (!f_in || !f_out) return fail(ctx, VL_EINVAL, "null f");
     if (!finite_pos(tau)) return fail(ctx, VL_EINVAL, "tau must be finite and > 0");
     if (f_out == f_in) return fail(ctx, VL_EALIAS, "f_out aliases f_in");
-    (void)f_work;
     if ((r = ensure_device(ctx)) != VL_OK) return r;
     hipStream_t st = (hipStream_t)stream;
     void* S = slot(ctx, 3, s);
     if (ctx->cfg.f_dtype == VL_F32) {
         if ((r = array_max_typed<float>(ctx, s, (const float*)f_in, S, st)) != VL_OK) return r;
-        return advect_x_typed<float>(ctx, s, (const float*)f_in, (float*)f_out, (float*)f_work, tau, S, nullptr,
+        return advect_x_typed<float>(ctx, s, (const float*)f_in, (float*)f_out, tau, S, nullptr,
                                      nullptr, st);
     }
     if ((r = array_max_typed<double>(ctx, s, (const double*)f_in, S, st)) != VL_OK) return r;
-    return advect_x_typed<double>(ctx, s, (const double*)f_in, (double*)f_out, (double*)f_work, tau, S, nullptr,
+    return advect_x_typed<double>(ctx, s, (const double*)f_in, (double*)f_out, tau, S, nullptr,
                                   nullptr, st);
 }
 

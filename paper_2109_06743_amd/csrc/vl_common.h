@@ -7,8 +7,8 @@ namespace vl {
 
 constexpr int kWave = 64;
 
-// Bit patterns used for atomic maxima of non-negative floating-point values:
-// for x, y >= 0 the IEEE bit patterns order like the values.
+// Bit patterns in which per-block maxima of non-negative floating-point values
+// are stored: for x, y >= 0 the IEEE bit patterns order like the values.
 template <class T> struct Bits;
 template <> struct Bits<float> {
     using U = unsigned int;

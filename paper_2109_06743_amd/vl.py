@@ -84,7 +84,7 @@ def load():
     sig = {
         "vl_create": ([ctypes.POINTER(Config), ctypes.POINTER(vp)], i32),
         "vl_destroy": ([vp], i32),
-        "vl_pfc_advect_x": ([vp, i32, vp, vp, vp, d, vp], i32),
+        "vl_pfc_advect_x": ([vp, i32, vp, vp, d, vp], i32),
         "vl_pfc_advect_v": ([vp, i32, vp, vp, vp, vp, d, vp], i32),
         "vl_moments": ([vp, i32, vp, vp, vp], i32),
         "vl_moment_fit": ([vp, i32, vp, vp, vp, vp, vp, vp, vp], i32),
@@ -192,9 +192,8 @@ class Context:
             raise VLError(st, (self.lib.vl_last_error(self.h) or b"").decode())
 
     # ---- entry points -----------------------------------------------------
-    def pfc_advect_x(self, s, f_in, f_out, f_work, tau, stream=None):
-        self._check(self.lib.vl_pfc_advect_x(self.h, s, _ptr(f_in), _ptr(f_out), _ptr(f_work), float(tau),
-                                             _stream(stream)))
+    def pfc_advect_x(self, s, f_in, f_out, tau, stream=None):
+        self._check(self.lib.vl_pfc_advect_x(self.h, s, _ptr(f_in), _ptr(f_out), float(tau), _stream(stream)))
 
     def pfc_advect_v(self, s, f_in, f_out, E, B, tau, stream=None):
         self._check(self.lib.vl_pfc_advect_v(self.h, s, _ptr(f_in), _ptr(f_out), _ptr(E), _ptr(B), float(tau),

@@ -80,11 +80,11 @@ def test_entry_points_reject_bad_arguments_before_device_use(lib):
     st, h = _create(cfg)
     p = ctypes.c_void_p(0x1000)                 # never dereferenced: validation fails first
     q = ctypes.c_void_p(0x2000)
-    assert lib.vl_pfc_advect_x(h, 0, None, p, None, 0.1, None) == 1
-    assert lib.vl_pfc_advect_x(h, 0, p, q, None, -0.1, None) == 1
-    assert lib.vl_pfc_advect_x(h, 0, p, q, None, float("nan"), None) == 1
-    assert lib.vl_pfc_advect_x(h, 0, p, p, None, 0.1, None) == 2
-    assert lib.vl_pfc_advect_x(h, 1, p, q, None, 0.1, None) == 1
+    assert lib.vl_pfc_advect_x(h, 0, None, p, 0.1, None) == 1
+    assert lib.vl_pfc_advect_x(h, 0, p, q, -0.1, None) == 1
+    assert lib.vl_pfc_advect_x(h, 0, p, q, float("nan"), None) == 1
+    assert lib.vl_pfc_advect_x(h, 0, p, p, 0.1, None) == 2
+    assert lib.vl_pfc_advect_x(h, 1, p, q, 0.1, None) == 1
     assert lib.vl_pfc_advect_v(h, 0, p, p, q, None, 0.1, None) == 2
     assert lib.vl_pfc_advect_v(h, 0, p, q, None, None, 0.1, None) == 1
     assert lib.vl_moments(h, 0, None, p, None) == 1

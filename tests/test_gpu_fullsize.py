@@ -59,7 +59,7 @@ def test_x_operator_sampled(case):
     nv = sp["nv"][0]
     fin = ft[s]
     fout = torch.empty_like(fin)
-    ctx.pfc_advect_x(s, fin, fout, None, tau)
+    ctx.pfc_advect_x(s, fin, fout, tau)
     ctx.sync()
     f64 = f[s]
     finf = float(f64.max())

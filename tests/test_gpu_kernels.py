@@ -54,7 +54,7 @@ def test_x_sweep_1x1v(dtype, nx, tau, kind):
     ctx = _ctx(cfg, dtype)
     fin = dev(f, dtype)
     fout = torch.empty_like(fin)
-    ctx.pfc_advect_x(0, fin, fout, None, tau)
+    ctx.pfc_advect_x(0, fin, fout, tau)
     ctx.sync()
     v, _ = OV.centres(cfg["v_lo"], cfg["v_hi"], cfg["nv"])
     dx = (cfg["x_hi"] - cfg["x_lo"]) / nx
@@ -74,7 +74,7 @@ def test_integer_shift_is_bitwise_exact(dtype):
     ctx = _ctx(cfg, dtype)
     fin = dev(f, dtype)
     fout = torch.empty_like(fin)
-    ctx.pfc_advect_x(0, fin, fout, None, 8.0)           # shift of cell j: 2j - 63, an integer
+    ctx.pfc_advect_x(0, fin, fout, 8.0)           # shift of cell j: 2j - 63, an integer
     ctx.sync()
     got = host(fout, f.shape)
     for j in range(nv):
@@ -99,7 +99,7 @@ def test_x_sweep_2x3v(dtype, nx, ny, nv, tau):
         f = storage_round(W.random_block((ny, nx, nv, nv, nv), seed=10 + s, kind="smooth"), dtype)
         fin = dev(f, dtype)
         fout = torch.empty_like(fin)
-        ctx.pfc_advect_x(s, fin, fout, None, tau)
+        ctx.pfc_advect_x(s, fin, fout, tau)
         ctx.sync()
         v, _ = _grid3(sp)
         ref = OV.x_advect_2x3v(f, v[0], v[1], dx, dy, tau)

@@ -40,7 +40,7 @@ def test_x_operator_periodic(dtype):
         ref = OV.x_advect_2x3v(fin, v[0], v[1], dx, dy, tau, f_inf=float(fin.max()), bc_y="periodic")
         fi = dev(fin, dtype)
         fo = torch.empty_like(fi)
-        ctx.pfc_advect_x(s, fi, fo, None, tau)
+        ctx.pfc_advect_x(s, fi, fo, tau)
         ctx.sync()
         got = host(fo, ref.shape)
         assert rel_l2(got, ref) < 2 * TOL_SWEEP[dtype], (dtype, s)
