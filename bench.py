@@ -4,10 +4,13 @@ A step is one vl_step (Algorithm 1: Maxwell half step, X(dt/2), V(dt),
 X(dt/2), moments, ten-moment fluid RK3, moment fitting, Maxwell half step)
 over all phase-space cells of both species, with inputs resident in HBM.
 
-Default workload: GEM-like 2X3V reconnection (Sec. 3.3 geometry) on
-256 x 128 spatial cells x 16^3 velocity cells x 2 species (m_i/m_e = 25),
-FP32 f with FP64 moments, fitting and fields.  The same workload is also run
-with FP64 f to report the FP32 speed-up.
+Headline workload: the large-domain magnetotail-like reconnection set-up
+(Sec. 4.1 geometry) on 1024 x 512 spatial cells x 12^3 velocity cells x 2
+species (m_i/m_e = 100, guide field 0.1), FP32 f with FP64 moments, fitting
+and fields, the largest of the benchmark configurations (1.81e9 phase-space
+cells).  The same workload runs with FP64 f for the FP32 speed-up.  The GEM
+set-up (Sec. 3.3 geometry, 256 x 128 x 16^3) is reported beside it, and the
+learned heat-flux closure is trained and run on that geometry.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -156,10 +159,10 @@ def recorded_traffic(category, workload):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    r = rec.get("kernels", {}).get(category)
-    if not r or r.get("workload") != workload or r.get("source_hash") != kernel_source_hash(category):
-        return None
-    return r["bytes_per_launch"]
+    for r in rec.get("records", []):
+        if r.get("category") == category and r.get("workload") == workload:
+            return r["bytes_per_launch"] if r.get("source_hash") == kernel_source_hash(category) else None
+    return None
 
 
 # Algorithmic bytes per phase-space cell and launch, in units of the f
@@ -373,42 +376,134 @@ def fluid_closure_report(args, trained_params):
             "runs": runs}
 
 
-def cpu_baseline(seconds_cap=30.0, nv=16, ot=False):
-    """The FP64 numpy oracle's full step on a sample of the same workload: the
-    GEM (or Orszag-Tang) set-up with the same nv^3 velocity grids and species
-    on a small spatial slab (per-cell work identical to the full grid)."""
-    from oracle import fields as OF, moments as OM, step as OS
-    from paper_2109_06743_amd import workloads as W
-    snx, sny = (16, 8) if nv <= 16 else (4, 2)
-    if ot:
-        cfg, f, F0 = W.orszag_tang(n=snx, ny=sny, nv=nv, dtype=np.float64)
-    else:
-        cfg, f, F0 = W.gem(nx=snx, ny=sny, nv=nv, dt=0.003, fit=True, dtype=np.float64)
-    F = OF.Yee(cfg["nx"], cfg["ny"])
-    for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
-        setattr(F, k, getattr(F0, k).copy())
-    moms, Us = [], []
-    for k, sp in enumerate(cfg["species"]):
-        v, dv = OS._grids(cfg, sp)
-        mm = OM.raw_moments_3v(f[k], v, dv, sp["m"])
-        moms.append(mm)
-        Us.append(mm[..., :10].copy())
-    st = dict(f=f, U=Us, mom_post=moms, F=F)
-    ncells = sum(x.size for x in f)
+def _oracle_slab(cfg, f, F, i0, j0, snx, sny):
+    """A snx x sny window of a 2X3V workload (f of every species and the Yee
+    fields) as a problem of its own with the same cell sizes: the same
+    per-cell work as the full grid, on the full grid's own values."""
+    from oracle import fields as OF
+    dx = (cfg["x_hi"] - cfg["x_lo"]) / cfg["nx"]
+    dy = (cfg["y_hi"] - cfg["y_lo"]) / cfg["ny"]
+    c = dict(cfg, nx=snx, ny=sny, x_lo=cfg["x_lo"] + i0 * dx, x_hi=cfg["x_lo"] + (i0 + snx) * dx,
+             y_lo=cfg["y_lo"] + j0 * dy, y_hi=cfg["y_lo"] + (j0 + sny) * dy)
+    fs = [np.ascontiguousarray(x[j0:j0 + sny, i0:i0 + snx], dtype=np.float64) for x in f]
+    G = OF.Yee(snx, sny)
+    for k in ("Ex", "Ez", "By"):
+        setattr(G, k, np.ascontiguousarray(getattr(F, k)[j0:j0 + sny, i0:i0 + snx], dtype=np.float64))
+    for k in ("Ey", "Bx", "Bz"):
+        setattr(G, k, np.ascontiguousarray(getattr(F, k)[j0:j0 + sny + 1, i0:i0 + snx], dtype=np.float64))
+    return c, fs, G
+
+
+def _oracle_steps(job):
+    """Worker of the CPU baseline: the FP64 numpy oracle's full 2X3V step on
+    one slab, repeated until `seconds` have passed (at least one step), on
+    one thread.  Returns (phase-space cells, steps, seconds)."""
+    cfg, f, F, seconds = job
     from threadpoolctl import threadpool_limits
+    from oracle import moments as OM, step as OS
     with threadpool_limits(limits=1):
+        moms, Us = [], []
+        for k, sp in enumerate(cfg["species"]):
+            v, dv = OS._grids(cfg, sp)
+            mm = OM.raw_moments_3v(f[k], v, dv, sp["m"])
+            moms.append(mm)
+            Us.append(mm[..., :10].copy())
+        st = dict(f=f, U=Us, mom_post=moms, F=F)
         t0 = time.perf_counter()
         n = 0
-        while True:
+        while n < 1 or time.perf_counter() - t0 < seconds:
             st = OS.step_2x3v(st, cfg, cfg["dt"])
             n += 1
-            if time.perf_counter() - t0 > seconds_cap / 2 or n >= 10:
-                break
-        dt = (time.perf_counter() - t0) / n
-    return {"value": ncells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{'Orszag-Tang' if ot else 'GEM'} {snx}x{sny} x {nv}^3 x 2 species (fit on), {n} steps of "
-                      f"the numpy FP64 oracle, "
-                      f"{dt:.2f} s/step, single-threaded numpy"}
+        dt = time.perf_counter() - t0
+    return sum(x.size for x in f), n, dt
+
+
+def cpu_baseline(cfg, f, F, label, seconds=8.0, snx=16, sny=8):
+    """The FP64 numpy oracle's full step on windows of the benchmark
+    workload's own initial state (snx x sny spatial cells with every velocity
+    cell of both species: the per-cell work of the full grid).  Timed once on
+    one thread, and once with one worker process per host core (at most 16,
+    the host share of one GPU), each on its own window, all at the same time:
+    throughput = all workers' cell-updates / the wall time of the slowest."""
+    import multiprocessing as mp
+    ny, nx = cfg["ny"], cfg["nx"]
+    ncores = max(1, min(os.cpu_count() or 1, 16))
+    # windows along the middle rows (the current sheet) at distinct x
+    wins = [(((k * nx) // ncores) // snx * snx % (nx - snx + 1), (ny - sny) // 2) for k in range(ncores)]
+    ctx = mp.get_context("spawn")              # workers never touch the GPU
+    with ctx.Pool(1) as pool:
+        c, n1, t1 = pool.apply(_oracle_steps, ((*_oracle_slab(cfg, f, F, *wins[0], snx, sny), seconds),))
+    v1 = c * n1 / t1
+    jobs = [(*_oracle_slab(cfg, f, F, i0, j0, snx, sny), seconds) for i0, j0 in wins]
+    t0 = time.perf_counter()
+    with ctx.Pool(ncores) as pool:
+        res = pool.map(_oracle_steps, jobs)
+    wall = time.perf_counter() - t0
+    tot = sum(c * n for c, n, _ in res)
+    slowest = max(t for _, _, t in res)
+    vall = tot / slowest
+    nv = cfg["species"][0]["nv"][0]
+    return {"value": vall, "unit": "cell-updates/s", "cores": ncores, "kind": "oracle",
+            "sample": f"{label}: the numpy FP64 oracle's full step (fit on, both species, {nv}^3 velocity cells) on "
+                      f"{ncores} windows of {snx}x{sny} spatial cells of the workload's own initial state, one "
+                      f"single-threaded worker process per core, {min(n for _, n, _ in res)}-"
+                      f"{max(n for _, n, _ in res)} steps each in {slowest:.1f} s ({wall:.1f} s wall with start-up)",
+            "one_thread": {"value": v1, "cores": 1, "steps": n1, "seconds": round(t1, 2)}}
+
+
+def step_fractions(res):
+    """Whole-step HBM fractions: bytes per phase-space cell per step under the
+    passes this implementation runs (two fused X passes, V, one moments read,
+    fit: 9 f-element transfers = 36 B in FP32) and the two models of separate
+    (48 B) and fully fused (32 B) passes, over the step time."""
+    e = res["elem"]
+    rate = res["ncells"] / (res["ms"] * 1e-3)
+    return {name: {"bytes_per_cell": k * e, "frac": round(k * e * rate / 1e9 / HBM_PEAK_GBS, 4)}
+            for name, k in (("moved", 9), ("model_six_passes", 12), ("model_four_passes", 8))}
+
+
+def kernel_fractions(res):
+    """Per f-pass kernel: algorithmic bytes per launch / mean launch time in
+    the warm-up breakdown (every category timed), as a fraction of peak."""
+    out = {}
+    for k, n_el in ALG_BYTES_PER_CELL.items():
+        tot, n = res["breakdown"][k]
+        if n:
+            alg = n_el * res["elem"] * res["cells_per_launch"]
+            out[k] = {"ms_per_launch": round(tot / n, 4), "frac": round(alg / (tot / n * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def measure(name, args, fp64=True, built=None):
+    """FP32 (and FP64) steps of one workload: value, roofline, fractions, drifts."""
+    t0 = time.perf_counter()
+    cfg, f, F, label = built if built is not None else build_workload(name)
+    log(f"workload {label}: built in {time.perf_counter() - t0:.1f} s")
+    r32 = run_gpu(cfg, f, F, "f32", args.steps, args.warmup)
+    r32["cells_per_launch"] = sum(_nelem(x) for x in f) / len(f)
+    log(f"{name} fp32: {r32['ms']:.3f} ms/step  warm-up breakdown {r32['breakdown']}  timed {r32['timing']}")
+    r64 = None
+    if fp64 and name not in ("gem34", "ot"):                # 34^3 cubes are FP32 only
+        r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", args.steps, args.warmup)
+        r64["cells_per_launch"] = r32["cells_per_launch"]
+        log(f"{name} fp64: {r64['ms']:.3f} ms/step")
+    value = r32["ncells"] / (r32["ms"] * 1e-3)
+    out = {"workload": label, "value": value, "ms_per_step": round(r32["ms"], 4),
+           "cells": r32["ncells"], "species": len(f), "dt": cfg["dt"],
+           "roofline": roofline(r32, label), "step_hbm_frac": step_fractions(r32),
+           "kernel_hbm_frac": kernel_fractions(r32),
+           "kernel_ms_per_step": {k: round(v[0] / r32["breakdown_steps"], 4) for k, v in r32["breakdown"].items()
+                                  if v[1]},
+           "energy_rel_drift": {"f32": r32["energy_rel_drift"], "steps": r32["steps_run"]},
+           "mass_rel_drift": {"f32": r32["mass_rel_drift"]}}
+    if r64 is not None:
+        v64 = r64["ncells"] / (r64["ms"] * 1e-3)
+        out["fp64"] = {"value": v64, "ms_per_step": round(r64["ms"], 4), "speedup_fp32_over_fp64": round(value / v64, 3),
+                       "step_hbm_frac": step_fractions(r64)}
+        out["energy_rel_drift"]["f64"] = r64["energy_rel_drift"]
+        out["energy_rel_drift"]["f64_steps"] = r64["steps_run"]
+        out["mass_rel_drift"]["f64"] = r64["mass_rel_drift"]
+    return out, (cfg, f, F, label)
 
 
 def main():
@@ -416,7 +511,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="gem", choices=["gem", "gem34", "ot", "tail"])
+    ap.add_argument("--workload", default="tail", choices=["gem", "gem34", "ot", "tail"],
+                    help="headline workload (default: magnetotail 1024x512x12^3)")
+    ap.add_argument("--secondary", default="gem", choices=["gem", "gem34", "ot", "tail", "none"],
+                    help="workload reported beside the headline")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
@@ -441,48 +539,51 @@ def main():
     from paper_2109_06743_amd import build as B
     if not os.path.exists(B.LIB):
         B.build()
-    torch.cuda.set_device(0)
     if args.only_fluid_closure:
+        torch.cuda.set_device(0)
         print(json.dumps({"fluid_closure": fluid_closure_report(args, None)}), flush=True)
         return
     t0 = time.perf_counter()
-    cfg, f, F, label = build_workload(args.workload)
+    built = build_workload(args.workload)
+    cfg, f, F, label = built
     log(f"workload {label}: built in {time.perf_counter() - t0:.1f} s")
-    r32 = run_gpu(cfg, f, F, "f32", args.steps, args.warmup)
-    r32["cells_per_launch"] = sum(_nelem(x) for x in f) / len(f)
-    log(f"fp32: {r32['ms']:.3f} ms/step  warm-up breakdown {r32['breakdown']}  timed {r32['timing']}")
-    r64 = None
-    if not args.no_fp64 and args.workload not in ("gem34", "ot"):     # 34^3 cubes are FP32 only
-        r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", args.steps, args.warmup)
-        log(f"fp64: {r64['ms']:.3f} ms/step")
-    value = r32["ncells"] / (r32["ms"] * 1e-3)
-    roof = roofline(r32, label)
+    cpu = None
+    if not args.no_cpu and cfg["kind"] == "2x3v" and args.workload != "ot":
+        # before any GPU call: the worker processes are started from a process
+        # that has not initialised the GPU
+        log("timing the CPU oracle on windows of the workload ...")
+        cpu = cpu_baseline(cfg, f, F, label)
+        log(f"  {cpu}")
+    torch.cuda.set_device(0)
+    head, _ = measure(args.workload, args, fp64=not args.no_fp64, built=built)
+    del built, f, F
     out = {
-        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(r32["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": head["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": label, "cells": r32["ncells"], "species": len(f), "dt": cfg["dt"],
+        "config": {"workload": label, "cells": head["cells"], "species": head["species"], "dt": head["dt"],
                    "moments_fields_fluid": "f64"},
-        "roofline": roof,
+        "roofline": head["roofline"],
     }
-    step_bytes = 6 * 2 * r32["elem"] * r32["ncells"]          # six read+write passes over f per step
-    out["effective_hbm_frac_step"] = round(step_bytes / (r32["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    if r64 is not None:
-        v64 = r64["ncells"] / (r64["ms"] * 1e-3)
-        out["fp64"] = {"value": v64, "ms_per_step": round(r64["ms"], 4), "speedup_fp32_over_fp64": round(value / v64, 3)}
-    out["energy_rel_drift"] = {"f32": r32["energy_rel_drift"], "steps": r32["steps_run"]}
-    out["mass_rel_drift"] = {"f32": r32["mass_rel_drift"]}
-    if r64 is not None:
-        out["energy_rel_drift"]["f64"] = r64["energy_rel_drift"]
-        out["energy_rel_drift"]["f64_steps"] = r64["steps_run"]
-        out["mass_rel_drift"]["f64"] = r64["mass_rel_drift"]
-    if not args.no_mlp and cfg["kind"] == "2x3v" and cfg.get("bc_y", "reflect") == "reflect":
+    for k in ("step_hbm_frac", "kernel_hbm_frac", "fp64", "energy_rel_drift", "mass_rel_drift",
+              "kernel_ms_per_step"):
+        if k in head:
+            out[k] = head[k]
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if args.secondary != "none" and args.secondary != args.workload:
+        sec, _ = measure(args.secondary, args, fp64=not args.no_fp64)
+        out["secondary"] = sec
+    mlp_geom = "gem"
+    params = None
+    if not args.no_mlp:
+        cfg_m0, f_m, F_m, label_m = build_workload(mlp_geom)
         log("learned closure: generating data and training ...")
-        params, tr, end = train_closure(cfg, f, F)
+        params, tr, end = train_closure(cfg_m0, f_m, F_m)
         log(f"  {tr}")
         runs = []
         for tol in args.closure_tol:
-            cfg_m = dict(cfg, closure="mlp", closure_tol=tol)
+            cfg_m = dict(cfg_m0, closure="mlp", closure_tol=tol)
             rm = run_closure(cfg_m, dict(end, f=[x.clone() for x in end["f"]], fields=end["fields"].clone(),
                                          U=[u.clone() for u in end["U"]], mom_post=[m.clone() for m in end["mom_post"]]),
                              params, args.steps, args.warmup)
@@ -493,16 +594,11 @@ def main():
                          "fallback_steps_per_species": rm["fallback_steps"], "timed_steps": args.steps,
                          "energy_rel_drift": rm["energy_rel_drift"], "mass_rel_drift": rm["mass_rel_drift"]})
         out["mlp_closure"] = {
-            "workload": label + " + learned heat-flux closure (64-64-64-64-16 tanh MLP, BF16 MFMA)",
+            "workload": label_m + " + learned heat-flux closure (64-64-64-64-16 tanh MLP, BF16 MFMA)",
             "start_time": end["t"], "runs": runs, "training": tr}
-    if not args.no_fluid_closure and cfg["kind"] == "2x3v":
-        out["fluid_closure"] = fluid_closure_report(args, params if "mlp_closure" in out else None)
-    out["kernel_ms_per_step"] = {k: round(v[0] / r32["breakdown_steps"], 4) for k, v in r32["breakdown"].items()
-                                 if v[1]}
-    if not args.no_cpu:
-        log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(nv=cfg["species"][0]["nv"][0] if args.workload in ("gem34", "ot") else 16,
-                                           ot=args.workload == "ot")
+        del end
+    if not args.no_fluid_closure:
+        out["fluid_closure"] = fluid_closure_report(args, params)
     print(json.dumps(out), flush=True)
 
 

@@ -964,10 +964,11 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
 template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
 
 // Rows per segment of the fused X operator.  Waves in flight per CU: 12 in
-// FP32, 8 in FP64 (register-limited to 3 and 2 per SIMD).  A wave walks S + 2 Kmax + 4 rows for S outputs;
-// the model cost rounds(S) * (S + 4 + 2 Kmax), with rounds the number of
-// times the waves of the launch refill the GPU, picks the segment count
-// (at most 64, segments of at least 8 rows).
+// FP32, 8 in FP64 (register-limited to 3 and 2 per SIMD).  A wave walks
+// S + 2 Kmax + 4 rows for S outputs.  Beyond the one-round case in
+// xy_segment, the model cost rounds(S) * (S + 4 + 2 Kmax), with rounds the
+// number of times the waves of the launch refill the GPU, picks the segment
+// count (at most 64, segments of at least 8 rows).
 static int xy_cus() {
     static int cus = 0;
     if (cus <= 0) {
@@ -981,6 +982,12 @@ static int xy_cus() {
 constexpr int kXyMaxSeg = 64;
 static int xy_segment(int ny, long long waves_per_seg, int kb, int waves_per_cu) {
     const long long resident = (long long)waves_per_cu * xy_cus();
+    // segments of 128 rows that fill at least half the GPU in one round: one
+    // round of long walks (GEM 256x128x16^3: 200 us per launch against 212
+    // for the two rounds of 43-row segments the cost model picks)
+    const int s128 = ny < 128 ? ny : 128;
+    const long long w128 = waves_per_seg * ((ny + s128 - 1) / s128);
+    if (w128 <= resident && 2 * w128 >= resident) return s128;
     int bestS = ny;
     double best = 0.0;
     for (int n = 1; n <= kXyMaxSeg && n <= ny; ++n) {
