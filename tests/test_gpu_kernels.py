@@ -250,6 +250,10 @@ def test_moment_fit_3v(dtype, nv):
         assert c[1] == ref_skip == 1
         if dtype == "f64":
             assert c[0] == ref_clip
+        else:
+            # FP32 takes the clip decision (f' < 0) in FP32: values within
+            # rounding of zero may fall either way
+            assert abs(int(c[0]) - ref_clip) <= max(2, ref_clip // 100), (c[0], ref_clip)
         assert (got >= 0).all()
         # density per cell is n_V
         dV = dv[0] * dv[1] * dv[2]
@@ -279,6 +283,8 @@ def test_moment_fit_1v(dtype):
     assert ref_clip > 0
     if dtype == "f64":
         assert cnt.cpu().numpy()[0] == ref_clip
+    else:
+        assert abs(int(cnt.cpu().numpy()[0]) - ref_clip) <= max(2, ref_clip // 100)
 
 
 # ------------------------------------------------------------------ fields --
