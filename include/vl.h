@@ -137,6 +137,21 @@ vl_status vl_moments(vl_ctx* ctx, int32_t s, const void* f, double* mom, vl_stre
 vl_status vl_moment_fit(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, const double* mom_pre,
                         double* U, double* mom_post, int64_t* counters, vl_stream stream);
 
+/* vl_moment_fit without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same computation and results as vl_moment_fit,
+ * with its scratch (the fitting parameters of every spatial cell, 160 bytes,
+ * and a clip partial, 4 bytes) in a static device array of 7.7 MiB that each
+ * GPU the library runs on holds until the process ends, instead of context
+ * scratch.  At most 49152 spatial cells (nx*ny): larger contexts get
+ * VL_EINVAL before any device call.  The call allocates nothing (the context
+ * is not used for device memory); its first call on a device looks up the
+ * array's address there.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams, threads or processes)
+ * race and must be serialised by the caller. */
+vl_status vl_moment_fit_noalloc(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, const double* mom_pre,
+                                double* U, double* mom_post, int64_t* counters, vl_stream stream);
+
 /* Fields.  1X1V: E[nx] at cell centres from Gauss's law with the uniform
  * neutralising background (Sec. 3.1), spectral, E_0 = 0.  The density is
  * taken from mom (species 0 moments, [nx][4]). */

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -555,6 +556,61 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free fitting --
+// vl_moment_fit_noalloc keeps the fitting parameters of every spatial cell
+// (kFitCellDoubles doubles) and the per-cell clip partials in one static
+// device array instead of context scratch, so the call allocates nothing.
+// Host code never uses the array's name as an address: the device address
+// is looked up once per device (hipGetSymbolAddress) and kept.
+constexpr long long kNoAllocCells = 49152;                       // 48 Ki spatial cells
+constexpr size_t kNoAllocParamBytes = (size_t)kNoAllocCells * vl::kFitCellDoubles * sizeof(double);
+constexpr size_t kNoAllocBytes = kNoAllocParamBytes + (size_t)kNoAllocCells * sizeof(unsigned);
+static_assert(kNoAllocParamBytes % 256 == 0, "clip partials start 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+vl_status noalloc_scratch(vl_ctx* ctx, void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return fail(ctx, VL_EDEVICE, "no current HIP device");
+    if (dev >= kMaxDevices) return fail(ctx, VL_EDEVICE, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ctx, VL_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VL_OK;
+}
+
+template <class T>
+vl_status fit_noalloc_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double* mom_pre, double* U,
+                            double* mom_post, int64_t* counters, void* sp, hipStream_t st) {
+    const vl_config& c = ctx->cfg;
+    const vl_species& sc = c.sp[s];
+    if (c.dim_v == 1) {
+        VL_HIP((vl::launch_fit1<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, sc.nv[0], sc.v_lo[0],
+                                   dv_of(sc, 0), sc.m, nullptr, nullptr, st)));
+        return VL_OK;
+    }
+    double* params = (double*)sp;
+    unsigned* clip = (unsigned*)((char*)sp + kNoAllocParamBytes);
+    VL_HIP((vl::launch_fit3<T>(fin, fout, mom_pre, U, mom_post, counters, ctx->cells, grid_args(sc), nullptr, nullptr,
+                               clip, params, st)));
+    return VL_OK;
+}
+
+}  // namespace
+
 // ====================================================================== ABI ==
 extern "C" {
 
@@ -725,6 +781,24 @@ vl_status vl_moment_fit(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, c
                                      nullptr, st),
                     fit_typed<double>(ctx, s, (const double*)f_in, (double*)f_out, mom_pre, U, mom_post, counters,
                                       nullptr, st));
+}
+
+vl_status vl_moment_fit_noalloc(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, const double* mom_pre,
+                                double* U, double* mom_post, int64_t* counters, vl_stream stream) {
+    vl_status r = check_species(ctx, s);
+    if (r != VL_OK) return r;
+    if (!f_in || !f_out || !mom_pre || !U) return fail(ctx, VL_EINVAL, "null argument");
+    if (ctx->cells > kNoAllocCells)
+        return fail(ctx, VL_EINVAL, "vl_moment_fit_noalloc: %lld spatial cells exceed the %lld its static scratch holds",
+                    ctx->cells, kNoAllocCells);
+    void* sp = nullptr;
+    if ((r = noalloc_scratch(ctx, &sp)) != VL_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+    return DISPATCH(ctx,
+                    fit_noalloc_typed<float>(ctx, s, (const float*)f_in, (float*)f_out, mom_pre, U, mom_post,
+                                             counters, sp, st),
+                    fit_noalloc_typed<double>(ctx, s, (const double*)f_in, (double*)f_out, mom_pre, U, mom_post,
+                                              counters, sp, st));
 }
 
 vl_status vl_poisson(vl_ctx* ctx, const double* mom, double* E, vl_stream stream) {

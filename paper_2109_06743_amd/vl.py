@@ -22,7 +22,8 @@ EXPORTS = ["vl_create", "vl_destroy", "vl_pfc_advect_x", "vl_pfc_advect_v", "vl_
            "vl_fluid_step", "vl_step_work_size", "vl_step", "vl_mass_energy", "vl_sync", "vl_status_str",
            "vl_last_error", "vl_version", "vl_timing_enable", "vl_timing_read", "vl_mlp_features",
            "vl_mlp_targets", "vl_mlp_forward", "vl_mlp_work_size", "vl_mlp_gradient", "vl_mlp_train_step",
-           "vl_mlp_train_epoch", "vl_field_energy", "vl_fluid_closure_work_size", "vl_fluid_closure_step"]
+           "vl_mlp_train_epoch", "vl_field_energy", "vl_fluid_closure_work_size", "vl_fluid_closure_step",
+           "vl_moment_fit_noalloc"]
 VL_CLOSURE_KINETIC, VL_CLOSURE_MLP = 0, 1
 VL_FLUID_GRADIENT, VL_FLUID_MLP = 0, 1
 MLP_IN, MLP_OUT, MLP_OUT_PAD, MLP_NPARAM = 64, 10, 16, 13520
@@ -88,6 +89,7 @@ def load():
         "vl_pfc_advect_v": ([vp, i32, vp, vp, vp, vp, d, vp], i32),
         "vl_moments": ([vp, i32, vp, vp, vp], i32),
         "vl_moment_fit": ([vp, i32, vp, vp, vp, vp, vp, vp, vp], i32),
+        "vl_moment_fit_noalloc": ([vp, i32, vp, vp, vp, vp, vp, vp, vp], i32),
         "vl_poisson": ([vp, vp, vp, vp], i32),
         "vl_yee_size": ([vp], sz),
         "vl_maxwell_half_step": ([vp, vp, vp, d, vp], i32),
@@ -205,6 +207,10 @@ class Context:
     def moment_fit(self, s, f_in, f_out, mom_pre, U, mom_post=None, counters=None, stream=None):
         self._check(self.lib.vl_moment_fit(self.h, s, _ptr(f_in), _ptr(f_out), _ptr(mom_pre), _ptr(U),
                                            _ptr(mom_post), _ptr(counters), _stream(stream)))
+
+    def moment_fit_noalloc(self, s, f_in, f_out, mom_pre, U, mom_post=None, counters=None, stream=None):
+        self._check(self.lib.vl_moment_fit_noalloc(self.h, s, _ptr(f_in), _ptr(f_out), _ptr(mom_pre), _ptr(U),
+                                                   _ptr(mom_post), _ptr(counters), _stream(stream)))
 
     def poisson(self, mom, E, stream=None):
         self._check(self.lib.vl_poisson(self.h, _ptr(mom), _ptr(E), _stream(stream)))

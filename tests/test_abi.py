@@ -170,3 +170,18 @@ def test_mlp_train_epoch_rejects_bad_arguments(lib):
     assert f(h, p, p, p, 1, float("nan"), p, y, 10, p, 4, 2, p, p, None) == 1     # learning rate
     assert f(h, p, p, p, 1, 1e-3, ctypes.c_void_p(0x1001), y, 10, p, 4, 2, p, p, None) == 1   # x alignment
     lib.vl_destroy(h)
+
+
+def test_noalloc_fit_rejects_oversized_grid_on_host(lib):
+    """vl_moment_fit_noalloc holds the scratch of at most 49152 spatial cells:
+    a larger context is refused before any device call."""
+    cfg, f, _ = workloads.gem(nx=8, ny=4, nv=8)
+    big = dict(cfg, nx=256, ny=256)                      # 65536 cells
+    st, h = _create(big)
+    assert st == 0
+    p = ctypes.c_void_p(256)
+    assert lib.vl_moment_fit_noalloc(h, 0, p, p, p, p, None, None, None) == 1
+    assert b"49152" in lib.vl_last_error(h)
+    assert lib.vl_moment_fit_noalloc(h, 0, None, p, p, p, None, None, None) == 1
+    assert lib.vl_moment_fit_noalloc(h, 2, p, p, p, p, None, None, None) == 1
+    assert lib.vl_destroy(h) == 0
