@@ -60,6 +60,7 @@ typedef enum {
 enum { VL_F32 = 0, VL_F64 = 1 };
 enum { VL_BC_REFLECT = 0, VL_BC_PERIODIC = 1 };
 enum { VL_CLOSURE_KINETIC = 0, VL_CLOSURE_MLP = 1 };
+enum { VL_VSPLIT_STRANG = 0, VL_VSPLIT_BACKSUB = 1 };
 enum { VL_MAX_SPECIES = 2 };
 
 typedef struct {
@@ -88,6 +89,15 @@ typedef struct {
                              network, the kinetic one as judge and fallback (see vl_step) */
     double closure_tol;   /* VL_CLOSURE_MLP: largest accepted relative L2 error of the network's
                              heat-flux vector against the kinetic one (e.g. 0.05) */
+    int32_t vsplit;       /* 3V velocity splitting (Sec. 2.1 names "backsubstitution"):
+                             VL_VSPLIT_STRANG: five uniform shear sweeps vx(tau/2) vy(tau/2)
+                             vz(tau) vy(tau/2) vx(tau/2);
+                             VL_VSPLIT_BACKSUB: the cell's implicit-midpoint (Boris) map of
+                             the step, v -> R v + c, factored row by row into an x-, y- and
+                             z-map that each change one component from the ones already
+                             updated, swept with a foot per cell face (every velocity axis
+                             <= 32 cells; valid while |q B/m| tau < 2, a turn below 90
+                             degrees per step) */
 } vl_config;
 
 typedef struct vl_ctx vl_ctx;
@@ -113,10 +123,12 @@ vl_status vl_pfc_advect_x(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out,
 /* Acceleration V(tau) of species s (Eq. 1, (q/m)(E + v x B) . grad_v f) with
  * zero-flux velocity boundaries (Sec. 2.1).  E, B are cell-centred FP64
  * fields [cells][3] (cells = ny*nx); B may be NULL (treated as 0).  1V uses
- * E[cells] (one double per cell) and ignores B.  3V applies the sweeps
- * vx(tau/2) vy(tau/2) vz(tau) vy(tau/2) vx(tau/2), each a uniform shift by the
- * acceleration at the pencil's transverse velocities.  Limiter bound: max of
- * f_in.  f_out must not alias f_in. */
+ * E[cells] (one double per cell) and ignores B.  3V with VL_VSPLIT_STRANG
+ * applies the sweeps vx(tau/2) vy(tau/2) vz(tau) vy(tau/2) vx(tau/2), each a
+ * uniform shift by the acceleration at the pencil's transverse velocities;
+ * with VL_VSPLIT_BACKSUB the three affine sweeps of the factored Boris map
+ * (see vl_config.vsplit).  Limiter bound: max of f_in.  f_out must not alias
+ * f_in. */
 vl_status vl_pfc_advect_v(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out,
                           const double* E, const double* B, double tau, vl_stream stream);
 

@@ -4,7 +4,9 @@ Test infrastructure only.
 Algorithm 1 of the paper (time stepping of the moment-fitting Vlasov-Maxwell
 solver), with these readings where it is silent:
 * "Full Vlasov Leapfrog Step": Strang order X(dt/2) V(dt) X(dt/2), the
-  fields for V taken at t+1/2.
+  fields for V taken at t+1/2.  V is the Strang shear sequence
+  (oracle.vlasov.v_advect_3v), or with cfg["vsplit"] == "backsub" the
+  backsubstitution split (oracle.vlasov.v_advect_3v_backsub).
 * Electromagnetic (2X3V): the first Maxwell half step uses j^t (current of the
   fitted f^t), the second j^{t+1} (current of the fitted f^{t+1}); V uses the
   cell-centred E, B after the first half step.  The fluid's stage fields are
@@ -95,7 +97,10 @@ def step_2x3v(st, cfg, dt):
         q, m = sp["q"], sp["m"]
         v, dv = _grids(cfg, sp)
         f = vlasov.x_advect_2x3v(st["f"][k], v[0], v[1], dx, dy, 0.5 * dt, bc_y=bc)
-        f = vlasov.v_advect_3v(f, E_h, B_h, q, m, v, dv, dt)
+        if cfg.get("vsplit") == "backsub":
+            f = vlasov.v_advect_3v_backsub(f, E_h, B_h, q, m, v, dv, dt)
+        else:
+            f = vlasov.v_advect_3v(f, E_h, B_h, q, m, v, dv, dt)
         f = vlasov.x_advect_2x3v(f, v[0], v[1], dx, dy, 0.5 * dt, bc_y=bc)
         mom_pre = moments.raw_moments_3v(f, v, dv, m)
         U = st["U"][k]

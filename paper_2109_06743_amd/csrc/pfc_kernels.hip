@@ -329,6 +329,171 @@ pfc_xy_kernel(const T* __restrict__ fin, T* __restrict__ fout, XYArgs A, const T
 }
 
 // ---------------------------------------------------------------------------
+// 3V velocity operator by the backsubstitution split.  The step's velocity
+// map under the cell's uniform E, B is the implicit-midpoint (Boris) map
+// v -> R v + c, R = I + [s](I + [t]) with t = (q tau/2m) B, s = 2t/(1+t.t)
+// and [a]v = v x a, c = (I + R)(q tau/2m) E.  Row by row it factors into an
+// x-, a y- and a z-map that each change one component from the components
+// already updated (x' = a x + b y + e z + cx; y' = d x' + g y + h z + cy;
+// z' = k x' + l y' + n z + cz).  Each map is affine along its pencils: the
+// stretch is the cell's (a, g or n), the shift linear in the pencil's
+// transverse cell-centre velocities.  Coefficients in FP64.
+__device__ __forceinline__ void backsub_coeffs(const double* EB, double qm, double tau, double* C) {
+    const double h = 0.5 * qm * tau;
+    const double t[3] = {h * EB[3], h * EB[4], h * EB[5]};
+    const double k = 2.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    const double s[3] = {k * t[0], k * t[1], k * t[2]};
+    // [a] as a matrix: [a]v = v x a
+    auto X = [](const double* a, double (&M)[3][3]) {
+        M[0][0] = 0.0;   M[0][1] = a[2];  M[0][2] = -a[1];
+        M[1][0] = -a[2]; M[1][1] = 0.0;   M[1][2] = a[0];
+        M[2][0] = a[1];  M[2][1] = -a[0]; M[2][2] = 0.0;
+    };
+    double S[3][3], T[3][3], R[3][3];
+    X(s, S);
+    X(t, T);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = S[i][j] + (i == j ? 1.0 : 0.0);
+            for (int l = 0; l < 3; ++l) acc += S[i][l] * T[l][j];
+            R[i][j] = acc;
+        }
+    double c[3];
+    for (int i = 0; i < 3; ++i) c[i] = h * (EB[i] + R[i][0] * EB[0] + R[i][1] * EB[1] + R[i][2] * EB[2]);
+    const double a = R[0][0], b = R[0][1], e = R[0][2];
+    const double d = R[1][0] / a;
+    const double g = R[1][1] - d * b, hh = R[1][2] - d * e;
+    const double det = R[0][0] * R[1][1] - R[0][1] * R[1][0];
+    const double kk = (R[2][0] * R[1][1] - R[2][1] * R[1][0]) / det;
+    const double l = (R[0][0] * R[2][1] - R[0][1] * R[2][0]) / det;
+    const double n = R[2][2] - kk * R[0][2] - l * R[1][2];
+    C[0] = a;  C[1] = b;  C[2] = e;  C[3] = c[0];
+    C[4] = d;  C[5] = g;  C[6] = hh; C[7] = c[1] - d * c[0];
+    C[8] = kk; C[9] = l;  C[10] = n; C[11] = c[2] - kk * c[0] - l * c[1];
+}
+
+// One affine sweep of the block in shared memory along axis dd: the content
+// at cell coordinate xi (cell j = [j, j+1]) moves to alpha xi + sigma.  Each
+// thread owns whole pencils.  Face i of the output has its foot
+// F_i = (i - sigma)/alpha, clamped to the box [0, n] (the wall faces keep
+// F_0 = 0, F_n = n: zero flux); F = j + t (0 <= t < 1) splits it, and
+// R_i = phi(j, 1 - t), the mass of cell j above the foot (phi the limited
+// partial flux; R = f_j exactly at t = 0, 0 beyond the box).  Output cell i
+// holds the mass between its two feet:
+//   j_{i+1} == j_i:  R_i - R_{i+1}
+//   else:            R_i + f_{j_i+1} + ... + f_{j_{i+1}-1} + (f_{j_{i+1}} - R_{i+1}),
+// so whole-cell moves are exact and the pencil's mass telescopes.
+template <class T, int NMAX>
+__device__ __forceinline__ void sweep_affine(T* blk, int dd, const double* C, const V3Params& P, T finf) {
+    const int nv[3] = {P.nvx, P.nvy, P.nvz};
+    const int pz = P.nvz | 1;
+    const int n = nv[dd];
+    const int npen = (P.nvx * P.nvy * P.nvz) / n;
+    const double alpha = C[dd == 0 ? 0 : (dd == 1 ? 5 : 10)];
+    for (int pen = threadIdx.x; pen < npen; pen += blockDim.x) {
+        int base, stride;
+        double vs;          // shift in velocity units
+        if (dd == 0) {      // x' = a x + b y + e z + cx
+            const int iy = pen / P.nvz, iz = pen % P.nvz;
+            base = iy * pz + iz;
+            stride = P.nvy * pz;
+            vs = C[1] * (P.lo[1] + (iy + 0.5) * P.dv[1]) + C[2] * (P.lo[2] + (iz + 0.5) * P.dv[2]) + C[3];
+        } else if (dd == 1) {   // y' = d x' + g y + h z + cy
+            const int ix = pen / P.nvz, iz = pen % P.nvz;
+            base = ix * P.nvy * pz + iz;
+            stride = pz;
+            vs = C[4] * (P.lo[0] + (ix + 0.5) * P.dv[0]) + C[6] * (P.lo[2] + (iz + 0.5) * P.dv[2]) + C[7];
+        } else {            // z' = k x' + l y' + n z + cz
+            const int ix = pen / P.nvy, iy = pen % P.nvy;
+            base = (ix * P.nvy + iy) * pz;
+            stride = 1;
+            vs = C[8] * (P.lo[0] + (ix + 0.5) * P.dv[0]) + C[9] * (P.lo[1] + (iy + 0.5) * P.dv[1]) + C[11];
+        }
+        // v -> alpha v + vs in cell units: xi -> alpha xi + sigma
+        const double sigma = ((alpha - 1.0) * P.lo[dd] + vs) * P.inv_dv[dd];
+        const T ia = (T)(1.0 / alpha), ib = (T)(-sigma / alpha);
+        const T* pc = blk + base;
+        auto val = [&](int j) -> T { return (j >= 0 && j < n) ? pc[j * stride] : T(0); };
+        // right part of cell j above a foot at j + t
+        auto rpart = [&](int j, T t) -> T {
+            if (j >= n) return T(0);
+            const T a = T(1) - t;
+            const T c1 = t * (T(1) + t) * T(1.0 / 6.0), c2 = t * (T(2) - t) * T(1.0 / 6.0);
+            return pfc_phi(val(j - 1), val(j), val(j + 1), a, c1, c2, finf);
+        };
+        T out[NMAX];
+        int jp = 0;
+        T Rp = val(0);                                  // face 0: F = 0
+        const T nT = (T)n;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            if (i < n) {
+                T F = (i + 1 == n) ? nT : fmin(fmax(fma((T)(i + 1), ia, ib), T(0)), nT);
+                const T fj = floor(F);
+                const int j = (int)fj;
+                const T t = F - fj;
+                const T R = rpart(j, t);
+                T o;
+                if (j == jp) {
+                    o = Rp - R;
+                } else {
+                    T acc = Rp;
+                    for (int m = jp + 1; m < j; ++m) acc += val(m);
+                    o = acc + (val(j) - R);
+                }
+                out[i] = fmax(o, T(0));
+                jp = j;
+                Rp = R;
+            }
+        }
+        T* pw = blk + base;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i)
+            if (i < n) pw[i * stride] = out[i];
+    }
+}
+
+template <class T, int NMAX>
+__global__ void __launch_bounds__(256)
+pfc_v3b_kernel(const T* fin, T* fout, const double* __restrict__ E, const double* __restrict__ B,
+               V3Params P, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
+    extern __shared__ unsigned char smem_raw[];
+    T* blk = reinterpret_cast<T*>(smem_raw);
+    __shared__ double EB[6];
+    __shared__ double Cs[12];
+    const long long cell = blockIdx.x;
+    const int nv = P.nvx * P.nvy * P.nvz;
+    const int pz = P.nvz | 1;
+    const T finf = *finf_p;
+    if (threadIdx.x < 3) {
+        EB[threadIdx.x] = E[cell * 3 + threadIdx.x];
+        EB[3 + threadIdx.x] = B ? B[cell * 3 + threadIdx.x] : 0.0;
+    }
+    const T* src = fin + cell * nv;
+    for (int e = threadIdx.x; e < nv; e += blockDim.x) blk[e + row_of(e, P.inv_nvz) * (pz - P.nvz)] = src[e];
+    __syncthreads();
+    if (threadIdx.x == 0) backsub_coeffs(EB, P.qm, P.tau, Cs);
+    __syncthreads();
+    double C[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) C[k] = Cs[k];
+    sweep_affine<T, NMAX>(blk, 0, C, P, finf);
+    __syncthreads();
+    sweep_affine<T, NMAX>(blk, 1, C, P, finf);
+    __syncthreads();
+    sweep_affine<T, NMAX>(blk, 2, C, P, finf);
+    __syncthreads();
+    T* dst = fout + cell * nv;
+    T mx = T(0);
+    for (int e = threadIdx.x; e < nv; e += blockDim.x) {
+        const T o = blk[e + row_of(e, P.inv_nvz) * (pz - P.nvz)];
+        dst[e] = o;
+        mx = fmax(mx, o);
+    }
+    if (max_out) block_max_part(mx, max_out);
+}
+
+// ---------------------------------------------------------------------------
 // Zero-flux sweep of one pencil held in shared memory, in upwind-to-downwind
 // order g[0..n-1] with two zero ghosts on each side (index k lives at g[k+2]).
 // With h_k = g_k + phi(k-1) - phi(k) (h_n = phi(n-1)), the output at position
@@ -1116,6 +1281,25 @@ hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E
     return finish_max<T>(max_out, part, cells, st);
 }
 
+// V(tau) by the backsubstitution split (any grid with every axis <= 32).
+template <class T>
+hipError_t launch_pfc_v3b(const T* fin, T* fout, long long cells, const double* E, const double* B,
+                          const V3Params& P, const void* finf, void* max_out, void* part, hipStream_t st) {
+    const int nmax = P.nvx > P.nvy ? (P.nvx > P.nvz ? P.nvx : P.nvz) : (P.nvy > P.nvz ? P.nvy : P.nvz);
+    const size_t shm = v3_shared_bytes(P.nvx, P.nvy, P.nvz, sizeof(T));
+    auto* mo = (typename Bits<T>::U*)(max_out ? part : nullptr);
+    const dim3 grid((unsigned)cells);
+    if (nmax <= 8)
+        hipLaunchKernelGGL((pfc_v3b_kernel<T, 8>), grid, dim3(64), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
+    else if (nmax <= 16)
+        hipLaunchKernelGGL((pfc_v3b_kernel<T, 16>), grid, dim3(256), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
+    else if (nmax <= 32)
+        hipLaunchKernelGGL((pfc_v3b_kernel<T, 32>), grid, dim3(256), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
+    else
+        return hipErrorInvalidValue;
+    return finish_max<T>(max_out, part, cells, st);
+}
+
 template <class T>
 hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipStream_t st) {
     long long blocks = (n + 255) / 256;
@@ -1133,6 +1317,8 @@ hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipS
                                          void*, hipStream_t);                                              \
     template hipError_t launch_pfc_v3<T>(const T*, T*, long long, const double*, const double*,             \
                                          const V3Params&, const void*, void*, void*, hipStream_t);         \
+    template hipError_t launch_pfc_v3b<T>(const T*, T*, long long, const double*, const double*,            \
+                                          const V3Params&, const void*, void*, void*, hipStream_t);        \
     template hipError_t launch_array_max<T>(const T*, long long, void*, void*, hipStream_t);                \
     template hipError_t launch_pfc_xy<T>(const T*, T*, int, int, int, int, int, double, double, double, double, \
                                          double, double, int, const void*, void*, void*, hipStream_t);     \

@@ -216,7 +216,10 @@ vl_status advect_v_typed(vl_ctx* ctx, int s, const T* fin, T* fout, const double
     P.qm = sp.q / sp.m;
     P.tau = tau;
     P.inv_nvz = 1.0f / (float)sp.nv[2];
-    VL_HIP((vl::launch_pfc_v3<T>(fin, fout, ctx->cells, E, B, P, finf, max_out, ctx->bpart, st)));
+    if (c.vsplit == VL_VSPLIT_BACKSUB)
+        VL_HIP((vl::launch_pfc_v3b<T>(fin, fout, ctx->cells, E, B, P, finf, max_out, ctx->bpart, st)));
+    else
+        VL_HIP((vl::launch_pfc_v3<T>(fin, fout, ctx->cells, E, B, P, finf, max_out, ctx->bpart, st)));
     return VL_OK;
 }
 
@@ -655,6 +658,8 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
     } else if (c.closure != VL_CLOSURE_KINETIC) {
         return VL_ENOTSUP;
     }
+    if (c.vsplit != VL_VSPLIT_STRANG && c.vsplit != VL_VSPLIT_BACKSUB) return VL_EINVAL;
+    if (c.vsplit == VL_VSPLIT_BACKSUB && c.dim_v != 3) return VL_ENOTSUP;   // a 3V splitting
     const size_t elem = c.f_dtype == VL_F32 ? 4 : 8;
     for (int s = 0; s < c.nspecies; ++s) {
         const vl_species& sp = c.sp[s];
@@ -676,6 +681,7 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
             // the 34^3 cube (FP32: the block fills one CU's LDS) has its own kernels
             const bool big = sp.nv[0] == vl::kBigCube && sp.nv[1] == vl::kBigCube && sp.nv[2] == vl::kBigCube;
             if (big && c.f_dtype != VL_F32) return VL_ENOTSUP;
+            if (big && c.vsplit == VL_VSPLIT_BACKSUB) return VL_ENOTSUP;   // the affine sweeps: axes <= 32
             for (int d = 0; d < 3 && !big; ++d)
                 if (sp.nv[d] > 32) return VL_ENOTSUP;
             if (!big && (long long)sp.nv[0] * sp.nv[1] * sp.nv[2] > 8192) return VL_ENOTSUP;

@@ -38,6 +38,11 @@ template <class T>
 hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E, const double* B, const V3Params& P,
                          const void* finf, void* max_out, void* part, hipStream_t st);
 size_t v3_shared_bytes(int nvx, int nvy, int nvz, size_t elem);
+// V(tau) by the backsubstitution split: three affine sweeps with per-face
+// feet (every velocity axis <= 32).
+template <class T>
+hipError_t launch_pfc_v3b(const T* fin, T* fout, long long cells, const double* E, const double* B, const V3Params& P,
+                          const void* finf, void* max_out, void* part, hipStream_t st);
 template <class T>
 hipError_t launch_array_max(const T* f, long long n, void* out, void* part, hipStream_t st);
 // Launchers that produce a maximum store per-block partials in `part` (8 bytes

@@ -25,6 +25,7 @@ EXPORTS = ["vl_create", "vl_destroy", "vl_pfc_advect_x", "vl_pfc_advect_v", "vl_
            "vl_mlp_train_epoch", "vl_field_energy", "vl_fluid_closure_work_size", "vl_fluid_closure_step",
            "vl_moment_fit_noalloc"]
 VL_CLOSURE_KINETIC, VL_CLOSURE_MLP = 0, 1
+VL_VSPLIT_STRANG, VL_VSPLIT_BACKSUB = 0, 1
 VL_FLUID_GRADIENT, VL_FLUID_MLP = 0, 1
 MLP_IN, MLP_OUT, MLP_OUT_PAD, MLP_NPARAM = 64, 10, 16, 13520
 TIMING_CATEGORIES = ["max", "pfc_x", "pfc_y", "pfc_v", "moments", "fluid", "fit", "fields", "copy"]
@@ -47,7 +48,7 @@ class Config(ctypes.Structure):
                 ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double), ("bc_y", ctypes.c_int32),
                 ("nspecies", ctypes.c_int32), ("sp", Species * MAX_SPECIES), ("f_dtype", ctypes.c_int32),
                 ("c", ctypes.c_double), ("fit", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("closure_tol", ctypes.c_double)]
+                ("closure_tol", ctypes.c_double), ("vsplit", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -132,6 +133,7 @@ def make_config(cfg, f_dtype="f32"):
     c.fit = int(bool(cfg.get("fit", False)))
     c.closure = VL_CLOSURE_MLP if cfg.get("closure") == "mlp" else VL_CLOSURE_KINETIC
     c.closure_tol = float(cfg.get("closure_tol", 0.0))
+    c.vsplit = VL_VSPLIT_BACKSUB if cfg.get("vsplit") == "backsub" else VL_VSPLIT_STRANG
     c.bc_y = VL_BC_PERIODIC if cfg.get("bc_y") == "periodic" else VL_BC_REFLECT
     if cfg["kind"] == "1x1v":
         c.dim_x, c.dim_v = 1, 1
