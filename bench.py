@@ -474,7 +474,7 @@ def kernel_fractions(res):
     return out
 
 
-def measure(name, args, fp64=True, built=None):
+def measure(name, args, fp64=True, built=None, backsub=True):
     """FP32 (and FP64) steps of one workload: value, roofline, fractions, drifts."""
     t0 = time.perf_counter()
     cfg, f, F, label = built if built is not None else build_workload(name)
@@ -500,10 +500,57 @@ def measure(name, args, fp64=True, built=None):
         v64 = r64["ncells"] / (r64["ms"] * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": round(r64["ms"], 4), "speedup_fp32_over_fp64": round(value / v64, 3),
                        "step_hbm_frac": step_fractions(r64)}
+    if backsub and name not in ("gem34", "ot"):             # the affine sweeps take axes <= 32
+        rb = run_gpu(dict(cfg, vsplit="backsub"), f, F, "f32", args.steps, args.warmup)
+        log(f"{name} fp32 backsubstitution split: {rb['ms']:.3f} ms/step")
+        vb, va = rb["breakdown"]["pfc_v"], r32["breakdown"]["pfc_v"]
+        out["backsub_split"] = {
+            "value": rb["ncells"] / (rb["ms"] * 1e-3), "ms_per_step": round(rb["ms"], 4),
+            "pfc_v_ms_per_launch": round(vb[0] / vb[1], 4), "strang_pfc_v_ms_per_launch": round(va[0] / va[1], 4),
+            "energy_rel_drift": rb["energy_rel_drift"], "mass_rel_drift": rb["mass_rel_drift"]}
         out["energy_rel_drift"]["f64"] = r64["energy_rel_drift"]
         out["energy_rel_drift"]["f64_steps"] = r64["steps_run"]
         out["mass_rel_drift"]["f64"] = r64["mass_rel_drift"]
     return out, (cfg, f, F, label)
+
+
+def v_operator_report(steps=5):
+    """The V operator alone with the two velocity splittings (Strang shear
+    sweeps and backsubstitution) on random f and random cell fields, on the
+    GEM 16^3 and magnetotail 12^3 grids: average time per launch (one
+    species' block) from the library's HIP-event timing."""
+    import torch
+    from paper_2109_06743_amd import vl, workloads as W
+    out = {}
+    for name, builder, (nx, ny, nv), dt in (("gem", W.gem, (256, 128, 16), 0.003),
+                                           ("tail", W.tail, (1024, 512, 12), 0.0012)):
+        cfg, _, _ = builder(nx=8, ny=4, nv=nv, dt=dt, dtype=np.float32)
+        cfg = dict(cfg, nx=nx, ny=ny)
+        cells = nx * ny
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        fin = torch.rand((ny, nx, nv, nv, nv), dtype=torch.float32, device="cuda", generator=g)
+        fout = torch.empty_like(fin)
+        E = (torch.rand(cells * 3, dtype=torch.float64, device="cuda", generator=g) - 0.5) * 0.2
+        B = (torch.rand(cells * 3, dtype=torch.float64, device="cuda", generator=g) - 0.5) * 2.0
+        for split in ("strang", "backsub"):
+            ctx = vl.Context(dict(cfg, vsplit=split), "f32")
+            for s in range(2):
+                ctx.pfc_advect_v(s, fin, fout, E, B, dt)
+            ctx.sync()
+            ctx.timing_enable(["pfc_v"])
+            for _ in range(steps):
+                for s in range(2):
+                    ctx.pfc_advect_v(s, fin, fout, E, B, dt)
+            ctx.sync()
+            ms, n = ctx.timing_read()["pfc_v"]
+            out[f"{name}_{split}"] = {"grid": f"{nx}x{ny} x {nv}^3", "ms_per_launch": round(ms / n, 4),
+                                     "launches": n}
+            log(f"V operator {name} {split}: {ms / n:.4f} ms per launch")
+            del ctx
+        del fin, fout
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -517,6 +564,7 @@ def main():
                     help="workload reported beside the headline")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-backsub", action="store_true", help="skip the step with the backsubstitution velocity split")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
     ap.add_argument("--closure-tol", type=float, nargs="+", default=[0.25, 1.0],
                     help="judge tolerances of the learned-closure runs (one run each)")
@@ -524,6 +572,8 @@ def main():
     ap.add_argument("--fluid-grid", type=int, nargs=2, default=[2048, 1024], metavar=("NX", "NY"))
     ap.add_argument("--only-fluid-closure", action="store_true",
                     help="only the fluid-only closure runs (one JSON object), e.g. for profiling")
+    ap.add_argument("--only-v-operator", action="store_true",
+                    help="only the V operator with both velocity splittings (one JSON object), e.g. for profiling")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -543,6 +593,10 @@ def main():
         torch.cuda.set_device(0)
         print(json.dumps({"fluid_closure": fluid_closure_report(args, None)}), flush=True)
         return
+    if args.only_v_operator:
+        torch.cuda.set_device(0)
+        print(json.dumps({"v_operator": v_operator_report()}), flush=True)
+        return
     t0 = time.perf_counter()
     built = build_workload(args.workload)
     cfg, f, F, label = built
@@ -555,7 +609,7 @@ def main():
         cpu = cpu_baseline(cfg, f, F, label)
         log(f"  {cpu}")
     torch.cuda.set_device(0)
-    head, _ = measure(args.workload, args, fp64=not args.no_fp64, built=built)
+    head, _ = measure(args.workload, args, fp64=not args.no_fp64, built=built, backsub=not args.no_backsub)
     del built, f, F
     out = {
         "metric": METRIC, "value": head["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -565,14 +619,14 @@ def main():
                    "moments_fields_fluid": "f64"},
         "roofline": head["roofline"],
     }
-    for k in ("step_hbm_frac", "kernel_hbm_frac", "fp64", "energy_rel_drift", "mass_rel_drift",
+    for k in ("step_hbm_frac", "kernel_hbm_frac", "fp64", "backsub_split", "energy_rel_drift", "mass_rel_drift",
               "kernel_ms_per_step"):
         if k in head:
             out[k] = head[k]
     if cpu is not None:
         out["cpu_baseline"] = cpu
     if args.secondary != "none" and args.secondary != args.workload:
-        sec, _ = measure(args.secondary, args, fp64=not args.no_fp64)
+        sec, _ = measure(args.secondary, args, fp64=not args.no_fp64, backsub=not args.no_backsub)
         out["secondary"] = sec
     mlp_geom = "gem"
     params = None
