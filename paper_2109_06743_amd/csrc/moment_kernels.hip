@@ -635,6 +635,142 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
     if (max_out) block_max_part(mx, max_out);
 }
 
+// Moment fitting of one cubic cell per block when the cell's pencils do not
+// fit the block's registers (FP64 34^3, 314 KB): thread t owns the v_x
+// pencils t + NTH j, the NR full sets in registers and the remainder
+// (t < N^2 - NR NTH) in shared memory, so f is read and written once.  The
+// steps are fit3_cube_kernel's; the exponentials are computed again in the
+// exchange pass instead of being kept.
+template <class T, int N, int NTH>
+__global__ void __launch_bounds__(NTH)
+fit3_big_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
+                unsigned* __restrict__ clip_part, VGrid G, XTable X, typename Bits<T>::U* __restrict__ max_out) {
+    constexpr int NN = N * N;
+    constexpr int NR = NN / NTH;                 // full pencil sets in registers
+    constexpr int REM = NN - NR * NTH;           // pencils in shared memory
+    constexpr int NW = NTH / kWave;
+    constexpr unsigned XB = NN * sizeof(T);      // bytes between v_x planes
+    static_assert(NTH % kWave == 0 && REM < NTH, "launch shape");
+    __shared__ T rem[(REM > 0 ? REM : 1) * N];
+    __shared__ double red[NW * 21];
+    __shared__ double fin_s[21];
+    const int tid = threadIdx.x;
+    const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
+    const double dV = G.dv[0] * G.dv[1] * G.dv[2];
+    const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(fin + cell * (N * NN)), 0, N * XB, kBufWord3);
+    const auto rd = __builtin_amdgcn_make_buffer_rsrc(fout + cell * (N * NN), 0, N * XB, kBufWord3);
+    const bool has_rem = tid < REM;
+    T fv[NR][N];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const unsigned po = (unsigned)(tid + NTH * j) * sizeof(T);
+#pragma unroll
+        for (int k = 0; k < N; ++k) fv[j][k] = buf_ld(rs, po, k * XB, T());
+    }
+    if (has_rem) {
+        const unsigned po = (unsigned)(tid + NTH * NR) * sizeof(T);
+#pragma unroll
+        for (int k = 0; k < N; ++k) rem[k * REM + tid] = buf_ld(rs, po, k * XB, T());
+    }
+    // element k of the thread's pencil j (j = NR: the shared-memory one)
+    auto fget = [&](int j, int k) -> T { return j < NR ? fv[j < NR ? j : 0][k] : rem[k * REM + tid]; };
+    auto fset = [&](int j, int k, T v) {
+        if (j < NR)
+            fv[j < NR ? j : 0][k] = v;
+        else
+            rem[k * REM + tid] = v;
+    };
+    const FitCell& C = P[cell];
+    const bool ok = C.ok != 0.0;
+    const double nV = C.nV;
+    unsigned nclip = 0;     // clipped elements of this wave (the same in every lane)
+    if (ok) {
+        // normalisation sums of the two Maxwellians (FP64)
+        double s[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j <= NR; ++j) {
+            if (j < NR || has_rem) {
+                const int t = tid + NTH * j;
+                QuadX<T> qv, qf;
+                qv.set(C.aV, C.uV, vc(G, 1, t / N), vc(G, 2, t % N));
+                qf.set(C.aF, C.uF, vc(G, 1, t / N), vc(G, 2, t % N));
+                T pa[2] = {T(0), T(0)}, pb[2] = {T(0), T(0)};
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    pa[k & 1] += qv.g((T)X.v[k]);
+                    pb[k & 1] += qf.g((T)X.v[k]);
+                }
+                s[0] += (double)(pa[0] + pa[1]);
+                s[1] += (double)(pb[0] + pb[1]);
+            }
+        }
+        block_sum_rs<2>(s, red, fin_s);
+        const T A = (T)(nV / (fin_s[0] * dV));
+        const T Bc = (T)(nV / (fin_s[1] * dV));
+        // exchange and clip
+#pragma unroll
+        for (int j = 0; j <= NR; ++j) {
+            const bool act = j < NR || has_rem;
+            const int t = tid + NTH * j;
+            QuadX<T> qv, qf;
+            qv.set(C.aV, C.uV, vc(G, 1, t / N), vc(G, 2, t % N));
+            qf.set(C.aF, C.uF, vc(G, 1, t / N), vc(G, 2, t % N));
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const T x = act ? fget(j, k) - A * qv.g((T)X.v[k]) + Bc * qf.g((T)X.v[k]) : T(0);
+                const bool neg = x < T(0);
+                nclip += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(act && neg));
+                if (act) fset(j, k, neg ? T(0) : x);
+            }
+        }
+    }
+    // raw moments of the clipped f'' (FP64 pencil sums)
+    double acc[21];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) acc[q] = 0.0;
+    acc[20] = (tid & (kWave - 1)) == 0 ? (double)nclip : 0.0;
+#pragma unroll
+    for (int j = 0; j <= NR; ++j) {
+        if (j < NR || has_rem) {
+            const int t = tid + NTH * j;
+            double Se[4] = {0.0, 0.0, 0.0, 0.0}, So[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const double g = (double)fget(j, k);
+                double* S = (k & 1) ? So : Se;
+                S[0] += g;
+                S[1] = fma(g, X.v[k], S[1]);
+                S[2] = fma(g, X.v2[k], S[2]);
+                S[3] = fma(g, X.v3[k], S[3]);
+            }
+            const double S[4] = {Se[0] + So[0], Se[1] + So[1], Se[2] + So[2], Se[3] + So[3]};
+            double a[20];
+            pencil_moments(S, vc(G, 1, t / N), vc(G, 2, t % N), a);
+#pragma unroll
+            for (int q = 0; q < 20; ++q) acc[q] += a[q];
+        }
+    }
+    block_sum_rs<21>(acc, red, fin_s);
+    const double scale = ok ? nV / (fin_s[0] * dV) : 1.0;
+    const T sc = (T)scale;     // 1 exactly when the cell is skipped
+    T mx = T(0);
+#pragma unroll
+    for (int j = 0; j <= NR; ++j) {
+        if (j < NR || has_rem) {
+            const unsigned po = (unsigned)(tid + NTH * j) * sizeof(T);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const T o = fget(j, k) * sc;
+                buf_st(o, rd, po, k * XB);
+                mx = fmax(mx, o);
+            }
+        }
+    }
+    if (mom_post && tid < 20) mom_post[cell * 20 + tid] = fin_s[tid] * (tid < 4 ? dV : G.m * dV) * scale;
+    if (clip_part && tid == 0) clip_part[blockIdx.x] = (unsigned)fin_s[20];
+    if (max_out) block_max_part(mx, max_out);
+}
+
 template <class T>
 __global__ void __launch_bounds__(256)
 fit1_kernel(const T* fin, T* fout, const double* __restrict__ mom_pre, double* __restrict__ U,
@@ -829,6 +965,9 @@ hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, 
             if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, 4, 1>), grid, dim3(256), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, 3, 1>), grid, dim3(192), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
+            if (N == kBigCube)   // 512 threads: two pencils each in registers, 132 in shared memory
+                hipLaunchKernelGGL((fit3_big_kernel<T, kBigCube, 512>), grid, dim3(512), 0, st, fin, fout, P, mom_post,
+                                   cp, G, X, mo);
         }
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && cnt)

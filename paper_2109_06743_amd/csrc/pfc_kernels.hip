@@ -1042,6 +1042,169 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
 }
 
 // ---------------------------------------------------------------------------
+// The same operator when the block is larger than a CU's shared memory (the
+// FP64 34^3 block, 314 KB, against 160 KB).  The v_y, v_z, v_y sweeps stay
+// inside the planes of fixed v_x, so they run on PL planes at a time in shared
+// memory (N / PL = 2 rounds); the rest of the block waits in registers.
+// Thread t owns the v_x pencils p = t + NTH j (p < N^2):
+//  1. each pencil is loaded, swept along v_x in registers, and split: its
+//     values in the first PL planes go to shared memory, the others stay in
+//     registers (a[j]);
+//  2. round 0 sweeps the first PL planes; each thread then swaps its own
+//     plane values with a[j] (no other thread touches them), and round 1
+//     sweeps the last PL planes;
+//  3. each pencil is reassembled from a[j] and shared memory, swept along v_x
+//     again and stored.
+// Eight waves per block leave 256 registers per lane.  A v_x pencil that
+// shifts by a cell or more is swept in the cell's output block, in its own
+// positions, which nothing else reads or writes meanwhile (in place as well:
+// the pencil's input has been read by then).
+template <class T, int N, int NTH, int PL>
+__global__ void __launch_bounds__(NTH)
+pfc_v3_planes_kernel(const T* fin, T* fout, const double* __restrict__ E, const double* __restrict__ B,
+                     V3Params P, const T* __restrict__ finf_p, typename Bits<T>::U* __restrict__ max_out) {
+    constexpr int PZ = N | 1;
+    constexpr int NN = N * N;
+    constexpr int NP = (NN + NTH - 1) / NTH;     // v_x pencils per thread (the last one partial)
+    constexpr unsigned XB = NN * sizeof(T);      // bytes between v_x planes
+    static_assert(2 * PL == N, "two rounds of PL planes");
+    static_assert(NN <= NP * NTH, "pencils cover the block");
+    __shared__ T blk[PL * N * PZ];
+    const int t = threadIdx.x;
+    const long long cell = xcd_work_index(blockIdx.x, gridDim.x);
+    const T F2 = T(2) * *finf_p;
+    T* dst = fout + cell * (N * NN);
+    const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(fin + cell * (N * NN)), 0, N * XB, kBufWord3);
+    const auto rd = __builtin_amdgcn_make_buffer_rsrc(dst, 0, N * XB, kBufWord3);
+    double eb[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        eb[k] = E[cell * 3 + k];
+        eb[3 + k] = B ? B[cell * 3 + k] : 0.0;
+    }
+    const double half = 0.5 * P.tau;
+    T xs0, xs1, xs2, y0, y1, y2, z0, z1, z2;
+    sweep_coeffs<T>(0, half, P, eb, xs0, xs1, xs2);
+    sweep_coeffs<T>(1, half, P, eb, y0, y1, y2);
+    sweep_coeffs<T>(2, P.tau, P, eb, z0, z1, z2);
+    // v_x sweep of pencil p held in g; shifts of a cell or more go through the
+    // pencil's own positions of the output block
+    auto sweep_x = [&](T (&g)[N], int p) {
+        const T sx = cube_pencil_shift<T, N>(p, xs0, xs1, xs2);
+        const bool pos = sx >= T(0);
+        const ShiftT<T> sh(fabs(sx));
+        if (__all(sh.K == 0) && __all(pos)) {
+            regs_one_way<T, N, false>(g, sh.a, sh.ac1, sh.ac2, F2);
+        } else if (__all(sh.K == 0) && __all(!pos)) {
+            regs_one_way<T, N, true>(g, sh.a, sh.ac1, sh.ac2, F2);
+        } else if (__all(sh.K == 0)) {
+            regs_mixed<T, N>(g, pos, sh.a, sh.ac1, sh.ac2, F2);
+        } else {
+            const unsigned po = (unsigned)p * sizeof(T);
+#pragma unroll
+            for (int m = 0; m < N; ++m) buf_st(g[m], rd, po, m * XB);
+            const int K = sh.K > N + 2 ? N + 2 : sh.K;
+            const int first = pos ? p : p + (N - 1) * NN;
+            pencil_shifted<T, N>(dst, first, pos ? NN : -NN, K, sh.a, sh.ac1, sh.ac2, F2);
+#pragma unroll
+            for (int m = 0; m < N; ++m) g[m] = buf_ld(rd, po, m * XB, T());
+        }
+    };
+    // the last plane halves of the full pencils wait in registers, those of
+    // the partial last pencil (NN - (NP - 1) NTH of them) in its own
+    // positions of the output block
+    T a[NP - 1][PL];
+    // 1. v_x half sweep; the first PL planes to shared memory
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int p = t + NTH * j;
+        if (p < NN) {
+            const int o = (p / N) * PZ + p % N;
+            const unsigned po = (unsigned)p * sizeof(T);
+            T g[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) g[k] = buf_ld(rs, po, k * XB, T());
+            sweep_x(g, p);
+#pragma unroll
+            for (int k = 0; k < PL; ++k) {
+                blk[k * N * PZ + o] = g[k];
+                if (j < NP - 1)
+                    a[j < NP - 1 ? j : 0][k] = g[PL + k];
+                else
+                    buf_st(g[PL + k], rd, po, (PL + k) * XB);
+            }
+        }
+    }
+    // 2. in-plane sweeps, round r on planes r PL .. r PL + PL - 1
+    auto in_plane = [&](int r) {
+        for (int pen = t; pen < PL * N; pen += NTH) {
+            const int pg = pen + r * PL * N;        // (v_x plane, second index) over the whole block
+            const T sy = cube_pencil_shift<T, N>(pg, y0, y1, y2);
+            sweep_cube_pencil<T, N>(blk, 1, pen, sy >= T(0), ShiftT<T>(fabs(sy)), F2);
+        }
+        __syncthreads();
+        for (int pen = t; pen < PL * N; pen += NTH) {
+            const int pg = pen + r * PL * N;
+            const T sz = cube_pencil_shift<T, N>(pg, z0, z1, z2);
+            sweep_cube_pencil<T, N>(blk, 2, pen, sz >= T(0), ShiftT<T>(fabs(sz)), F2);
+        }
+        __syncthreads();
+        for (int pen = t; pen < PL * N; pen += NTH) {
+            const int pg = pen + r * PL * N;
+            const T sy = cube_pencil_shift<T, N>(pg, y0, y1, y2);
+            sweep_cube_pencil<T, N>(blk, 1, pen, sy >= T(0), ShiftT<T>(fabs(sy)), F2);
+        }
+        __syncthreads();
+    };
+    __syncthreads();
+    in_plane(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int p = t + NTH * j;
+        if (p < NN) {
+            const int o = (p / N) * PZ + p % N;
+            const unsigned po = (unsigned)p * sizeof(T);
+#pragma unroll
+            for (int k = 0; k < PL; ++k) {
+                const T v = blk[k * N * PZ + o];
+                if (j < NP - 1) {
+                    blk[k * N * PZ + o] = a[j < NP - 1 ? j : 0][k];
+                    a[j < NP - 1 ? j : 0][k] = v;
+                } else {
+                    blk[k * N * PZ + o] = buf_ld(rd, po, (PL + k) * XB, T());
+                    buf_st(v, rd, po, k * XB);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    in_plane(1);
+    // 3. second v_x half sweep and the store
+    T mx = T(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int p = t + NTH * j;
+        if (p < NN) {
+            const int o = (p / N) * PZ + p % N;
+            const unsigned po = (unsigned)p * sizeof(T);
+            T g[N];
+#pragma unroll
+            for (int k = 0; k < PL; ++k) {
+                g[k] = j < NP - 1 ? a[j < NP - 1 ? j : 0][k] : buf_ld(rd, po, k * XB, T());
+                g[PL + k] = blk[k * N * PZ + o];
+            }
+            sweep_x(g, p);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                buf_st(g[k], rd, po, k * XB);
+                mx = fmax(mx, g[k]);
+            }
+        }
+    }
+    if (max_out) block_max_part(mx, max_out);
+}
+
+// ---------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(256)
 array_max_kernel(const T* __restrict__ f, long long n, typename Bits<T>::U* __restrict__ out) {
@@ -1255,13 +1418,15 @@ hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E
     const bool cube = P.nvx == P.nvy && P.nvy == P.nvz;
     auto* mo = (typename Bits<T>::U*)(max_out ? part : nullptr);
     const dim3 grid((unsigned)cells);
-    if constexpr (sizeof(T) == 4) {
-        if (cube && P.nvx == kBigCube) {
-            // one cell per CU (its LDS); 578 threads = two pencils each per sweep
+    if (cube && P.nvx == kBigCube) {
+        // one cell per CU (its LDS); 578 threads = two v_x pencils each
+        if constexpr (sizeof(T) == 4)
             hipLaunchKernelGGL((pfc_v3_cube_kernel<T, kBigCube, 578>), grid, dim3(578), 0, st, fin, fout, E, B, P,
                                (const T*)finf, mo);
-            return finish_max<T>(max_out, part, cells, st);
-        }
+        else        // the FP64 block is twice the LDS: half its v_x planes at a time
+            hipLaunchKernelGGL((pfc_v3_planes_kernel<T, kBigCube, 512, 17>), grid, dim3(512), 0, st, fin, fout, E, B,
+                               P, (const T*)finf, mo);
+        return finish_max<T>(max_out, part, cells, st);
     }
     if (cube && P.nvx == 16) {
         hipLaunchKernelGGL((pfc_v3_cube_kernel<T, 16, 256>), grid, dim3(256), 0, st, fin, fout, E, B, P, (const T*)finf, mo);

@@ -678,9 +678,9 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
         // element and byte offsets
         if ((long long)c.nx * sp.nv[0] * sp.nv[1] * sp.nv[2] * elem >= (1LL << 32)) return VL_ENOTSUP;
         if (nd == 3) {
-            // the 34^3 cube (FP32: the block fills one CU's LDS) has its own kernels
+            // the 34^3 cube has its own kernels (FP32: the block fills one CU's
+            // LDS; FP64: half the block at a time)
             const bool big = sp.nv[0] == vl::kBigCube && sp.nv[1] == vl::kBigCube && sp.nv[2] == vl::kBigCube;
-            if (big && c.f_dtype != VL_F32) return VL_ENOTSUP;
             if (big && c.vsplit == VL_VSPLIT_BACKSUB) return VL_ENOTSUP;   // the affine sweeps: axes <= 32
             for (int d = 0; d < 3 && !big; ++d)
                 if (sp.nv[d] > 32) return VL_ENOTSUP;

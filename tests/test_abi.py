@@ -100,14 +100,15 @@ def test_entry_points_reject_bad_arguments_before_device_use(lib):
     lib.vl_destroy(h)
 
 
-def test_cube34_is_fp32_only(lib):
+def test_cube34_grids(lib):
     cfg = dict(kind="2x3v", nx=4, ny=2, x_lo=0.0, x_hi=1.0, y_lo=-1.0, y_hi=1.0, c=20.0, fit=True,
                species=[dict(q=-1.0, m=0.04, v_lo=[-1.0] * 3, v_hi=[1.0] * 3, nv=[34] * 3)])
-    st, h = _create(cfg, "f32")
-    assert st == 0
-    lib.vl_destroy(h)
-    st, h = _create(cfg, "f64")
-    assert st == 3
+    for dt in ("f32", "f64"):
+        st, h = _create(cfg, dt)
+        assert st == 0
+        lib.vl_destroy(h)
+    st, h = _create(dict(cfg, vsplit="backsub"), "f64")
+    assert st == 3                                  # the affine sweeps take axes <= 32
     cfg["species"][0]["nv"] = [34, 34, 33]           # non-cubic beyond the generic limits
     st, h = _create(cfg, "f32")
     assert st == 3
