@@ -483,10 +483,24 @@ def measure(name, args, fp64=True, built=None, backsub=True):
     r32["cells_per_launch"] = sum(_nelem(x) for x in f) / len(f)
     log(f"{name} fp32: {r32['ms']:.3f} ms/step  warm-up breakdown {r32['breakdown']}  timed {r32['timing']}")
     r64 = None
-    if fp64 and name not in ("gem34", "ot"):                # 34^3 cubes are FP32 only
+    if fp64 and name != "ot":
         r64 = run_gpu(cfg, [x.astype(np.float64) for x in f], F, "f64", args.steps, args.warmup)
         r64["cells_per_launch"] = r32["cells_per_launch"]
         log(f"{name} fp64: {r64['ms']:.3f} ms/step")
+    half = None
+    if fp64 and name == "ot":
+        # FP64 f of the 512^2 box is 165 GB per copy and the step holds two:
+        # both precisions on half the box, 512 x 256, for the speed-up
+        import torch
+        from paper_2109_06743_amd import workloads as W
+        half = {}
+        for dt in ("f32", "f64"):
+            cfg_h, f_h, F_h = W.orszag_tang_device(n=512, ny=256, nv=34, dtype=dt)
+            half[dt] = run_gpu(cfg_h, f_h, F_h, dt, args.steps, args.warmup)
+            half[dt]["cells_per_launch"] = sum(_nelem(x) for x in f_h) / len(f_h)
+            log(f"{name} 512x256 {dt}: {half[dt]['ms']:.3f} ms/step")
+            del f_h
+            torch.cuda.empty_cache()
     value = r32["ncells"] / (r32["ms"] * 1e-3)
     out = {"workload": label, "value": value, "ms_per_step": round(r32["ms"], 4),
            "cells": r32["ncells"], "species": len(f), "dt": cfg["dt"],
@@ -500,6 +514,20 @@ def measure(name, args, fp64=True, built=None, backsub=True):
         v64 = r64["ncells"] / (r64["ms"] * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": round(r64["ms"], 4), "speedup_fp32_over_fp64": round(value / v64, 3),
                        "step_hbm_frac": step_fractions(r64)}
+    if half is not None:
+        v32h = half["f32"]["ncells"] / (half["f32"]["ms"] * 1e-3)
+        v64h = half["f64"]["ncells"] / (half["f64"]["ms"] * 1e-3)
+        out["fp64"] = {"grid": "512x256 x 34^3 x 2 species (half the box: the FP64 step on 512^2 needs 330 GB)",
+                       "value": v64h, "ms_per_step": round(half["f64"]["ms"], 4),
+                       "fp32_same_grid": {"value": v32h, "ms_per_step": round(half["f32"]["ms"], 4),
+                                          "kernel_hbm_frac": kernel_fractions(half["f32"])},
+                       "speedup_fp32_over_fp64": round(v32h / v64h, 3), "step_hbm_frac": step_fractions(half["f64"]),
+                       "kernel_hbm_frac": kernel_fractions(half["f64"]),
+                       "kernel_ms_per_step": {k: round(v[0] / half["f64"]["breakdown_steps"], 4)
+                                              for k, v in half["f64"]["breakdown"].items() if v[1]},
+                       "energy_rel_drift": {"f32": half["f32"]["energy_rel_drift"], "f64": half["f64"]["energy_rel_drift"],
+                                            "steps": half["f64"]["steps_run"]},
+                       "mass_rel_drift": {"f32": half["f32"]["mass_rel_drift"], "f64": half["f64"]["mass_rel_drift"]}}
     if backsub and name not in ("gem34", "ot"):             # the affine sweeps take axes <= 32
         rb = run_gpu(dict(cfg, vsplit="backsub"), f, F, "f32", args.steps, args.warmup)
         log(f"{name} fp32 backsubstitution split: {rb['ms']:.3f} ms/step")
