@@ -345,7 +345,7 @@ moments3_cube_kernel(const T* __restrict__ f, double* __restrict__ mom, long lon
     for (int j = 0; j < NT; ++j) {
         const int t = lane + 64 * j;
 #pragma unroll
-        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? __builtin_nontemporal_load(src + t + k * N * N) : T(0);
+        for (int k = 0; k < N; ++k) fv[j][k] = (t < N * N) ? ld_f<kRowsWholeLines<T, N>>(src + t + k * N * N) : T(0);
     }
     double acc[20];
 #pragma unroll

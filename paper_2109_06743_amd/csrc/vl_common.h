@@ -111,6 +111,28 @@ __device__ __forceinline__ void block_sum_rs(const double (&a)[K], double* red, 
     __syncthreads();
 }
 
+// Streaming access to f: non-temporal (the lines are not kept in the caches)
+// when NT, else an ordinary access.  Velocity blocks whose rows are not whole
+// 128-byte lines (12^3 FP32: 576 B) have lines shared by two wave accesses;
+// there the caches merge the halves instead of fetching or writing each line
+// twice.
+template <class T, int N>
+constexpr bool kRowsWholeLines = (N * N * (int)sizeof(T)) % 128 == 0;
+template <bool NT, class T>
+__device__ __forceinline__ T ld_f(const T* p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st_f(T v, T* p) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // Raw buffer access to a block of memory (one cell's f): its base in a buffer
 // descriptor (wave-uniform, scalar registers), a per-lane byte offset and a
 // scalar byte offset, so a pencil of elements a plane apart costs one vector
