@@ -197,44 +197,88 @@ def calibrate_copy(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
-def train_closure(cfg, f, F, gen_steps=300, start=60, every=15, epochs=16, batch=16384, lr=2e-3, seed=0):
-    """Learned heat-flux closure on the benchmark geometry: the solver generates
-    its own training data (features, with the cell-centred field direction, and
-    normalised kinetic heat flux of every cell and species, every `every` steps
-    after `start`), every fifth snapshot is held out, and the network is
-    trained with the library's BF16-MFMA gradient and Adam calls.  Returns the
+def _closure_snapshots(ctx, st, cfg, steps, start, every, keep):
+    """Run `steps` steps of the kinetic (moment-fitting) solver and, every
+    `every` steps from `start`, store the network features, the normalised
+    kinetic heat flux and the scale n m v_t^3 of every cell and species
+    (keep(k) says whether snapshot k is stored).  Returns lists of tensors
+    and (step, species) labels."""
+    import torch
+    cells = cfg["nx"] * cfg["ny"]
+    Ec = torch.zeros(cells * 3, dtype=torch.float64, device="cuda")
+    Bc = torch.zeros(cells * 3, dtype=torch.float64, device="cuda")
+    X, Y, S, K = [], [], [], []
+    for k in range(1, steps + 1):
+        ctx.step(st, cfg["dt"])
+        if k >= start and k % every == 0 and keep(k):
+            ctx.cell_fields(st.fields, Ec, Bc)
+            for s in range(2):
+                x = torch.zeros(cells, 64, dtype=torch.int16, device="cuda")
+                sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
+                y = torch.zeros(cells, 16, dtype=torch.float32, device="cuda")
+                ctx.mlp_features(s, st.mom_pre[s], 20, x, sc, B=Bc)
+                ctx.mlp_targets(s, st.mom_pre[s], y)
+                X.append(x)
+                Y.append(y)
+                S.append(sc)
+                K.append((k, s))
+    return X, Y, S, K
+
+
+def _heat_flux_vector_error(ctx, P, X, Y, S):
+    """Relative L2 error over the rows of the heat-flux vector q_i = Q_ijj
+    (the in-step judge's measure) of the network against the kinetic targets,
+    and the same for the per-component mean of the targets as predictor."""
+    import torch
+    # q_i = Q_ijj over the ten ordered triples (xxx, xxy, xxz, xyy, xyz, xzz, yyy, yyz, yzz, zzz)
+    J = torch.zeros(10, 3, dtype=torch.float64, device="cuda")
+    for c, d in ((0, 0), (3, 0), (5, 0), (1, 1), (6, 1), (8, 1), (2, 2), (7, 2), (9, 2)):
+        J[c, d] = 1.0
+    yh = torch.zeros_like(Y)
+    ctx.mlp_forward(P, X, yh)
+    qk = (Y[:, :10].double() * S[:, None]) @ J
+    qn = (yh[:, :10].double() * S[:, None]) @ J
+    qm = (Y[:, :10].double().mean(0)[None, :] * S[:, None]) @ J
+    den = qk.norm().item()
+    return (qn - qk).norm().item() / den, (qm - qk).norm().item() / den
+
+
+def train_closure(cfg, f, F, gen_steps=3000, start=60, every=15, epochs=96, batch=16384, lr=2e-3, seed=0,
+                  other_psi0=0.15, other_steps=600):
+    """Learned heat-flux closure on the benchmark geometry.  The solver
+    generates its own training data: features (with the cell-centred field
+    direction) and normalised kinetic heat flux of every cell and species
+    every `every` steps after `start` over a `gen_steps`-step run; every fifth
+    snapshot is held out.  The network is trained with the library's
+    BF16-MFMA gradient and Adam calls on batches drawn with probability
+    proportional to each sample's scale n m v_t^3 (the in-step judge weighs
+    cells by their heat flux, which scales so).  A second run with a different
+    initial perturbation (psi0 = other_psi0) is held out whole.  Returns the
     parameters, figures, and the solver state at the end of the data run."""
     import torch
     from paper_2109_06743_amd import vl, workloads as W
     ctx = vl.Context(cfg, "f32")
     st = vl.StepState(ctx, f, vl.yee_pack(F))
-    cells = cfg["nx"] * cfg["ny"]
-    snaps = [k for k in range(1, gen_steps + 1) if k >= start and k % every == 0]
-    held = {k for i, k in enumerate(snaps) if i % 5 == 2}
-    nsamp = len(snaps) * 2 * cells
-    n_held = len(held) * 2 * cells
-    n_train = nsamp - n_held
-    X = torch.zeros(nsamp, 64, dtype=torch.int16, device="cuda")
-    Y = torch.zeros(nsamp, 16, dtype=torch.float32, device="cuda")
-    sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
-    Ec = torch.zeros(cells * 3, dtype=torch.float64, device="cuda")
-    Bc = torch.zeros(cells * 3, dtype=torch.float64, device="cuda")
-    r_tr, r_ho = 0, n_train                               # held-out rows at the end
     t0 = time.perf_counter()
-    for k in range(1, gen_steps + 1):
-        ctx.step(st, cfg["dt"])
-        if k in snaps:
-            ctx.cell_fields(st.fields, Ec, Bc)
-            for s in range(2):
-                r = r_ho if k in held else r_tr
-                ctx.mlp_features(s, st.mom_pre[s], 20, X[r:r + cells], sc, B=Bc)
-                ctx.mlp_targets(s, st.mom_pre[s], Y[r:r + cells])
-                if k in held:
-                    r_ho += cells
-                else:
-                    r_tr += cells
+    snaps = [k for k in range(start, gen_steps + 1) if k % every == 0]
+    held = {k for i, k in enumerate(snaps) if i % 5 == 2}
+    X, Y, S, K = _closure_snapshots(ctx, st, cfg, gen_steps, start, every, lambda k: True)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
+    tr = [i for i, (k, s) in enumerate(K) if k not in held]
+    ho = [i for i, (k, s) in enumerate(K) if k in held]
+    Xt = torch.cat([X[i] for i in tr]).contiguous()
+    Yt = torch.cat([Y[i] for i in tr]).contiguous()
+    w = torch.cat([S[i] for i in tr]).float()
+    w = w / w.mean() + 1e-3
+    Xh = torch.cat([X[i] for i in ho]).contiguous()
+    Yh = torch.cat([Y[i] for i in ho]).contiguous()
+    Sh = torch.cat([S[i] for i in ho])
+    del X, Y
+    n_train, n_held = Xt.shape[0], Xh.shape[0]
+    end = dict(f=[x.clone() for x in st.f], fields=st.fields.clone(), U=[u.clone() for u in st.U],
+               mom_post=[m.clone() for m in st.mom_post], t=gen_steps * cfg["dt"])
+    del st
     P = torch.as_tensor(W.mlp_init(seed)).cuda()
     m1, m2 = torch.zeros_like(P), torch.zeros_like(P)
     work = torch.zeros(ctx.mlp_work_size(batch), dtype=torch.float32, device="cuda")
@@ -245,37 +289,57 @@ def train_closure(cfg, f, F, gen_steps=300, start=60, every=15, epochs=16, batch
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     losses = []
     a.record()
-    Xt, Yt = X[:n_train], Y[:n_train]
     for ep in range(epochs):
-        lr_ep = lr * 0.5 ** (ep // 4)                    # halved every four epochs
-        perm = torch.randperm(n_train, device="cuda", generator=gen)
-        # one call per epoch: the batches perm[k*batch:(k+1)*batch] are gathered in the gradient kernel
-        step += ctx.mlp_train_epoch(P, m1, m2, step + 1, lr_ep, Xt, Yt, perm, batch, work, gl)
+        lr_ep = lr * 0.5 ** (ep // (epochs // 4))          # halved every quarter of the epochs
+        idx = torch.multinomial(w, n_train, replacement=True, generator=gen)
+        # one call per epoch: the batches idx[k*batch:(k+1)*batch] are gathered in the gradient kernel
+        step += ctx.mlp_train_epoch(P, m1, m2, step + 1, lr_ep, Xt, Yt, idx, batch, work, gl)
         losses.append(gl[-1].item())
     b.record()
     torch.cuda.synchronize()
     train_ms = a.elapsed_time(b)
-    # held-out: relative L2 error of the normalised heat flux
-    yh = torch.zeros(n_held, 16, dtype=torch.float32, device="cuda")
-    ctx.mlp_forward(P, X[n_train:].contiguous(), yh)
+    # held-out snapshots of the same run: relative L2 error of the normalised heat flux
+    yh = torch.zeros_like(Yh)
+    ctx.mlp_forward(P, Xh, yh)
     torch.cuda.synchronize()
-    d = (yh[:, :10] - Y[n_train:, :10]).double()
-    heldout = (d.norm() / Y[n_train:, :10].double().norm()).item()
+    d = (yh[:, :10] - Yh[:, :10]).double()
+    heldout = (d.norm() / Yh[:, :10].double().norm()).item()
+    cells = cfg["nx"] * cfg["ny"]
+    same = {}
+    for s, name in enumerate(("electrons", "ions")):
+        rows = torch.cat([torch.arange(j * cells, (j + 1) * cells, device="cuda")
+                          for j, i in enumerate(ho) if K[i][1] == s])
+        e_net, e_mean = _heat_flux_vector_error(ctx, P, Xh[rows].contiguous(), Yh[rows].contiguous(), Sh[rows])
+        same[name] = {"network": round(e_net, 4), "mean_predictor": round(e_mean, 4), "zero_predictor": 1.0}
     a.record()
     for _ in range(5):
-        ctx.mlp_forward(P, X[n_train:].contiguous(), yh)
+        ctx.mlp_forward(P, Xh, yh)
     b.record()
     torch.cuda.synchronize()
     inf_ms = a.elapsed_time(b) / 5
-    end = dict(f=[x.clone() for x in st.f], fields=st.fields.clone(), U=[u.clone() for u in st.U],
-               mom_post=[m.clone() for m in st.mom_post], t=gen_steps * cfg["dt"])
-    del X, Y, st, ctx
+    # a run with another initial perturbation, held out whole
+    cfg_o, f_o, F_o = W.gem(nx=cfg["nx"], ny=cfg["ny"], nv=cfg["species"][0]["nv"][0], dt=cfg["dt"], fit=True,
+                            dtype=np.float32, psi0=other_psi0)
+    st_o = vl.StepState(ctx, f_o, vl.yee_pack(F_o))
+    Xo, Yo, So, Ko = _closure_snapshots(ctx, st_o, cfg_o, other_steps, 60, 60, lambda k: True)
+    other = {}
+    for s, name in enumerate(("electrons", "ions")):
+        rows = [i for i, (k, sp) in enumerate(Ko) if sp == s]
+        e_net, e_mean = _heat_flux_vector_error(ctx, P, torch.cat([Xo[i] for i in rows]).contiguous(),
+                                                torch.cat([Yo[i] for i in rows]).contiguous(),
+                                                torch.cat([So[i] for i in rows]))
+        other[name] = {"network": round(e_net, 4), "mean_predictor": round(e_mean, 4), "zero_predictor": 1.0}
+    del st_o, Xo, Yo, So, Xt, Yt, Xh, Yh, ctx
     torch.cuda.empty_cache()
     return P.cpu().numpy(), {
-        "samples": nsamp, "train_samples": n_train, "heldout_samples": n_held, "data_steps": gen_steps,
+        "samples": n_train + n_held, "train_samples": n_train, "heldout_samples": n_held, "data_steps": gen_steps,
         "data_seconds": round(gen_s, 2), "epochs": epochs, "batch": batch, "adam_steps": step,
+        "sampling": "probability proportional to n m v_t^3",
         "train_ms": round(train_ms, 1), "train_samples_per_s": round(step * batch / (train_ms * 1e-3)),
-        "loss_per_epoch": [round(x, 6) for x in losses], "heldout_rel_l2_Q": round(heldout, 4),
+        "loss_per_epoch": [round(x, 6) for x in losses[::max(len(losses) // 16, 1)]], "heldout_rel_l2_Q": round(heldout, 4),
+        "heldout_rel_l2_heat_flux_vector": same,
+        "heldout_other_run": {"psi0": other_psi0, "steps": other_steps, "snapshot_every": 60,
+                              "rel_l2_heat_flux_vector": other},
         "forward_samples_per_s": round(n_held / (inf_ms * 1e-3))}, end
 
 
@@ -594,7 +658,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-backsub", action="store_true", help="skip the step with the backsubstitution velocity split")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-closure form")
-    ap.add_argument("--closure-tol", type=float, nargs="+", default=[0.25, 1.0],
+    ap.add_argument("--closure-tol", type=float, nargs="+", default=[0.25, 0.5, 1.0],
                     help="judge tolerances of the learned-closure runs (one run each)")
     ap.add_argument("--no-fluid-closure", action="store_true", help="skip the fluid-only closure runs")
     ap.add_argument("--fluid-grid", type=int, nargs=2, default=[2048, 1024], metavar=("NX", "NY"))

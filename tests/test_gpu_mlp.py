@@ -344,13 +344,13 @@ def test_closure_fallback_equals_kinetic_step():
 
 
 # ------------------------------------------------------------- the gain ----
-def _gem_snapshots(nx, ny, nv, steps, every, start):
-    """Run the GEM set-up on the GPU (FP32 f, fitting on) and collect the
-    post-step raw moments of both species and the cell-centred B every
-    `every` steps."""
+def _gem_snapshots(nx, ny, nv, steps, every, start, psi0=0.1):
+    """Run the GEM set-up (initial perturbation psi0) on the GPU (FP32 f,
+    fitting on) and collect the post-step raw moments of both species and the
+    cell-centred B every `every` steps."""
     import torch
     from paper_2109_06743_amd import vl
-    cfg, f, F0 = W.gem(nx=nx, ny=ny, nv=nv, dt=0.003, fit=True, dtype=np.float32)
+    cfg, f, F0 = W.gem(nx=nx, ny=ny, nv=nv, dt=0.003, fit=True, dtype=np.float32, psi0=psi0)
     ctx = vl.Context(cfg, "f32")
     st = vl.StepState(ctx, f, vl.yee_pack(F0))
     cells = nx * ny
@@ -366,19 +366,10 @@ def _gem_snapshots(nx, ny, nv, steps, every, start):
     return cfg, ctx, snaps
 
 
-def test_trained_network_beats_gradient_closure():
-    """Train on the solver's own moments and kinetic heat flux (GEM set-up,
-    32x16 x 16^3, both species), then compare on held-out snapshots (every
-    fifth) the heat-flux divergence (the term the fluid update uses) predicted
-    by the network and by Eq. 5 against the kinetic one."""
+def _features(ctx, snaps, cells):
     import torch
-    nx, ny, nv = 32, 16, 16
-    cfg, ctx, snaps = _gem_snapshots(nx, ny, nv, steps=600, every=15, start=60)
-    cells = nx * ny
-    train = [sn for i, sn in enumerate(snaps) if i % 5 != 2]
-    held = [sn for i, sn in enumerate(snaps) if i % 5 == 2]
-    xs, ys = [], []
-    for mom, B in train:
+    xs, ys, ss = [], [], []
+    for mom, B in snaps:
         for s in range(2):
             x = torch.zeros(cells, 64, dtype=torch.int16, device="cuda")
             sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
@@ -387,8 +378,32 @@ def test_trained_network_beats_gradient_closure():
             ctx.mlp_targets(s, mom[s], y)
             xs.append(x)
             ys.append(y)
+            ss.append(sc)
+    return xs, ys, ss
+
+
+def test_trained_network_beats_gradient_closure():
+    """Train on the solver's own moments and kinetic heat flux (GEM set-up,
+    32x16 x 16^3, both species, 1500 steps), with batches drawn with
+    probability proportional to n m v_t^3 (the weight the heat flux carries),
+    then evaluate on a run held out whole: the same set-up with another
+    initial perturbation (psi0 0.15 instead of 0.1).  Per species, the error
+    of the heat-flux divergence (the term the fluid update uses) and of the
+    heat-flux vector q_i = Q_ijj (the in-step judge's measure) is compared
+    with four predictors that need no training data or only its mean: zero
+    (error 1 exactly), the per-component mean of the normalised training
+    targets, and Eq. 5's temperature-gradient closure (divergence only)."""
+    import torch
+    nx, ny, nv = 32, 16, 16
+    cells = nx * ny
+    cfg, ctx, train = _gem_snapshots(nx, ny, nv, steps=1500, every=15, start=60)
+    _, _, held = _gem_snapshots(nx, ny, nv, steps=600, every=30, start=60, psi0=0.15)
+    xs, ys, ss = _features(ctx, train, cells)
     X = torch.cat(xs).contiguous()
     Y = torch.cat(ys).contiguous()
+    w = torch.cat(ss).float()
+    w = w / w.mean() + 1e-3
+    mean_y = host(Y[:, :10].double().mean(0))
     n = X.shape[0]
     P = _t(W.mlp_init(0), torch.float32)
     m1 = torch.zeros_like(P)
@@ -399,19 +414,21 @@ def test_trained_network_beats_gradient_closure():
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     step = 0
-    for epoch in range(60):
-        perm = torch.randperm(n, device="cuda", generator=gen)
-        for b0 in range(0, n - batch + 1, batch):
-            idx = perm[b0:b0 + batch]
-            step += 1
-            ctx.mlp_train_step(P, m1, m2, step, 2e-3, X[idx].contiguous(), Y[idx].contiguous(), work, gl)
+    epochs = 96
+    for epoch in range(epochs):
+        idx = torch.multinomial(w, n, replacement=True, generator=gen)
+        step += ctx.mlp_train_epoch(P, m1, m2, step + 1, 2e-3 * 0.5 ** (epoch // (epochs // 4)), X, Y, idx, batch,
+                                    work, gl)
     ctx.sync()
-    # held-out evaluation
     dx = (cfg["x_hi"] - cfg["x_lo"]) / nx
     dy = (cfg["y_hi"] - cfg["y_lo"]) / ny
-    err_net, err_grad = [], []
-    for momt, B in held:
-        for s, sp in enumerate(cfg["species"]):
+    J = np.zeros((10, 3))
+    for c, d in ((0, 0), (3, 0), (5, 0), (1, 1), (6, 1), (8, 1), (2, 2), (7, 2), (9, 2)):
+        J[c, d] = 1.0                      # q_i = Q_ijj over the ten ordered triples
+    res = {}
+    for s, sp in enumerate(cfg["species"]):
+        e = {k: [] for k in ("div_net", "div_grad", "div_mean", "q_net", "q_mean")}
+        for momt, B in held:
             x = torch.zeros(cells, 64, dtype=torch.int16, device="cuda")
             sc = torch.zeros(cells, dtype=torch.float64, device="cuda")
             y = torch.zeros(cells, 16, dtype=torch.float32, device="cuda")
@@ -419,13 +436,23 @@ def test_trained_network_beats_gradient_closure():
             ctx.mlp_forward(P, x, y)
             ctx.sync()
             mom = host(momt[s]).reshape(ny, nx, 20)
+            scale = host(sc).reshape(ny, nx, 1)
             Qk = OM.heat_flux(mom, sp["m"])
-            Qn = host(sc).reshape(ny, nx, 1) * host(y).reshape(ny, nx, 16)[..., :10]
+            Qn = scale * host(y).reshape(ny, nx, 16)[..., :10]
+            Qm = scale * mean_y
             dk = OM.divergence_heat_flux(Qk, dx, dy)
-            dn = OM.divergence_heat_flux(Qn, dx, dy)
-            dg = OM.gradient_closure_divergence(mom[..., :10], sp["m"], sp["q"], dx, dy)
-            err_net.append(rel_l2(dn, dk))
-            err_grad.append(rel_l2(dg, dk))
-    e_net, e_grad = float(np.mean(err_net)), float(np.mean(err_grad))
-    print(f"held-out rel-L2 of div Q: network {e_net:.3f}, gradient closure (Eq. 5) {e_grad:.3f}")
-    assert e_net < 0.5 * e_grad, (e_net, e_grad)
+            e["div_net"].append(rel_l2(OM.divergence_heat_flux(Qn, dx, dy), dk))
+            e["div_mean"].append(rel_l2(OM.divergence_heat_flux(Qm, dx, dy), dk))
+            e["div_grad"].append(rel_l2(OM.gradient_closure_divergence(mom[..., :10], sp["m"], sp["q"], dx, dy), dk))
+            e["q_net"].append(rel_l2(Qn @ J, Qk @ J))
+            e["q_mean"].append(rel_l2(Qm @ J, Qk @ J))
+        res[s] = {k: float(np.mean(v)) for k, v in e.items()}
+        print(f"species {s} held-out run: " + ", ".join(f"{k} {v:.3f}" for k, v in res[s].items()), flush=True)
+    # measured on the held-out run: electrons div 0.60, q 0.51 (Eq. 5: div 1.25; mean predictor: div 1.11,
+    # q 1.36); ions div 0.27, q 0.30 (Eq. 5: div 13.6; mean predictor: div 0.99, q 1.10)
+    bars = {0: (0.75, 0.65), 1: (0.4, 0.45)}
+    for s in range(2):
+        r = res[s]
+        assert r["div_net"] < bars[s][0] and r["q_net"] < bars[s][1], (s, r)     # zero predictor: 1, 1
+        assert r["div_net"] < r["div_grad"], (s, r)
+        assert r["div_net"] < r["div_mean"] - 0.2 and r["q_net"] < r["q_mean"] - 0.3, (s, r)
