@@ -600,6 +600,7 @@ def measure(name, args, fp64=True, built=None, backsub=True):
             "value": rb["ncells"] / (rb["ms"] * 1e-3), "ms_per_step": round(rb["ms"], 4),
             "pfc_v_ms_per_launch": round(vb[0] / vb[1], 4), "strang_pfc_v_ms_per_launch": round(va[0] / va[1], 4),
             "energy_rel_drift": rb["energy_rel_drift"], "mass_rel_drift": rb["mass_rel_drift"]}
+    if r64 is not None:
         out["energy_rel_drift"]["f64"] = r64["energy_rel_drift"]
         out["energy_rel_drift"]["f64_steps"] = r64["steps_run"]
         out["mass_rel_drift"]["f64"] = r64["mass_rel_drift"]
