@@ -197,7 +197,7 @@ def calibrate_copy(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
-def _closure_snapshots(ctx, st, cfg, steps, start, every, keep):
+def _closure_snapshots(ctx, st, cfg, steps, start, every, keep, after_step=None):
     """Run `steps` steps of the kinetic (moment-fitting) solver and, every
     `every` steps from `start`, store the network features, the normalised
     kinetic heat flux and the scale n m v_t^3 of every cell and species
@@ -210,6 +210,8 @@ def _closure_snapshots(ctx, st, cfg, steps, start, every, keep):
     X, Y, S, K = [], [], [], []
     for k in range(1, steps + 1):
         ctx.step(st, cfg["dt"])
+        if after_step is not None:
+            after_step()
         if k >= start and k % every == 0 and keep(k):
             ctx.cell_fields(st.fields, Ec, Bc)
             for s in range(2):
@@ -243,8 +245,38 @@ def _heat_flux_vector_error(ctx, P, X, Y, S):
     return (qn - qk).norm().item() / den, (qm - qk).norm().item() / den
 
 
+def _train_network(ctx, X, Y, w, epochs, batch, lr, seed):
+    """Adam on the library's BF16-MFMA gradient: `epochs` passes of len(X)
+    samples drawn with probability proportional to w (inverse of the
+    cumulative weights), lr halved every quarter of the epochs."""
+    import torch
+    from paper_2109_06743_amd import vl, workloads as W
+    P = torch.as_tensor(W.mlp_init(seed)).cuda()
+    m1, m2 = torch.zeros_like(P), torch.zeros_like(P)
+    work = torch.zeros(ctx.mlp_work_size(batch), dtype=torch.float32, device="cuda")
+    gl = torch.zeros(vl.MLP_NPARAM + 1, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    n = X.shape[0]
+    cdf = torch.cumsum(w.double(), 0)
+    step = 0
+    losses = []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for ep in range(epochs):
+        lr_ep = lr * 0.5 ** (ep // (epochs // 4))
+        u = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen) * cdf[-1]
+        idx = torch.searchsorted(cdf, u).clamp_(max=n - 1)
+        # one call per epoch: the batches idx[k*batch:(k+1)*batch] are gathered in the gradient kernel
+        step += ctx.mlp_train_epoch(P, m1, m2, step + 1, lr_ep, X, Y, idx, batch, work, gl)
+        losses.append(gl[-1].item())
+    b.record()
+    torch.cuda.synchronize()
+    return P, losses, step, a.elapsed_time(b)
+
+
 def train_closure(cfg, f, F, gen_steps=3000, start=60, every=15, epochs=96, batch=16384, lr=2e-3, seed=0,
-                  other_psi0=0.15, other_steps=600):
+                  closure_steps=600, other_psi0=0.15, other_steps=600):
     """Learned heat-flux closure on the benchmark geometry.  The solver
     generates its own training data: features (with the cell-centred field
     direction) and normalised kinetic heat flux of every cell and species
@@ -252,9 +284,14 @@ def train_closure(cfg, f, F, gen_steps=3000, start=60, every=15, epochs=96, batc
     snapshot is held out.  The network is trained with the library's
     BF16-MFMA gradient and Adam calls on batches drawn with probability
     proportional to each sample's scale n m v_t^3 (the in-step judge weighs
-    cells by their heat flux, which scales so).  A second run with a different
-    initial perturbation (psi0 = other_psi0) is held out whole.  Returns the
-    parameters, figures, and the solver state at the end of the data run."""
+    cells by their heat flux, which scales so).  Then the solver runs
+    `closure_steps` steps from the data run's end with that network as its
+    closure (judge tolerance 1, so the states are the ones the closure
+    produces; the targets stay the kinetic heat flux of f), those snapshots
+    join the training set and the network is trained again from its initial
+    weights.  A run with a different initial perturbation (psi0 = other_psi0)
+    is held out whole.  Returns the parameters, figures, and the solver state
+    at the end of the kinetic data run."""
     import torch
     from paper_2109_06743_amd import vl, workloads as W
     ctx = vl.Context(cfg, "f32")
@@ -267,43 +304,52 @@ def train_closure(cfg, f, F, gen_steps=3000, start=60, every=15, epochs=96, batc
     gen_s = time.perf_counter() - t0
     tr = [i for i, (k, s) in enumerate(K) if k not in held]
     ho = [i for i, (k, s) in enumerate(K) if k in held]
-    Xt = torch.cat([X[i] for i in tr]).contiguous()
-    Yt = torch.cat([Y[i] for i in tr]).contiguous()
-    w = torch.cat([S[i] for i in tr]).float()
-    w = w / w.mean() + 1e-3
     Xh = torch.cat([X[i] for i in ho]).contiguous()
     Yh = torch.cat([Y[i] for i in ho]).contiguous()
     Sh = torch.cat([S[i] for i in ho])
-    del X, Y
-    n_train, n_held = Xt.shape[0], Xh.shape[0]
+    Xtr, Ytr, Str = [X[i] for i in tr], [Y[i] for i in tr], [S[i] for i in tr]
+    del X, Y, S
     end = dict(f=[x.clone() for x in st.f], fields=st.fields.clone(), U=[u.clone() for u in st.U],
                mom_post=[m.clone() for m in st.mom_post], t=gen_steps * cfg["dt"])
     del st
-    P = torch.as_tensor(W.mlp_init(seed)).cuda()
-    m1, m2 = torch.zeros_like(P), torch.zeros_like(P)
-    work = torch.zeros(ctx.mlp_work_size(batch), dtype=torch.float32, device="cuda")
-    gl = torch.zeros(vl.MLP_NPARAM + 1, dtype=torch.float32, device="cuda")
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    step = 0
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    losses = []
-    a.record()
-    for ep in range(epochs):
-        lr_ep = lr * 0.5 ** (ep // (epochs // 4))          # halved every quarter of the epochs
-        idx = torch.multinomial(w, n_train, replacement=True, generator=gen)
-        # one call per epoch: the batches idx[k*batch:(k+1)*batch] are gathered in the gradient kernel
-        step += ctx.mlp_train_epoch(P, m1, m2, step + 1, lr_ep, Xt, Yt, idx, batch, work, gl)
-        losses.append(gl[-1].item())
-    b.record()
+
+    def heldout_Q(P):
+        yh = torch.zeros_like(Yh)
+        ctx.mlp_forward(P, Xh, yh)
+        torch.cuda.synchronize()
+        d = (yh[:, :10] - Yh[:, :10]).double()
+        return (d.norm() / Yh[:, :10].double().norm()).item()
+
+    # round 1: the kinetic run's snapshots
+    Xt, Yt = torch.cat(Xtr).contiguous(), torch.cat(Ytr).contiguous()
+    w = torch.cat(Str).float()
+    P1, _, steps1, ms1 = _train_network(ctx, Xt, Yt, w / w.mean() + 1e-3, epochs, batch, lr, seed)
+    q1 = heldout_Q(P1)
+    del Xt, Yt
+    # the states the closure produces, with kinetic targets
+    ctx_c = vl.Context(dict(cfg, closure="mlp", closure_tol=1.0), "f32")
+    st_c = vl.StepState(ctx_c, end["f"], end["fields"], U_list=end["U"], mom_post_list=end["mom_post"],
+                        mlp_params=P1.cpu().numpy())
+    fb = torch.zeros(2, dtype=torch.int64, device="cuda")
+
+    def count_fallbacks():
+        fb.add_(st_c.closure_fallback.to(torch.int64))
+    t1 = time.perf_counter()
+    Xc, Yc, Sc, _ = _closure_snapshots(ctx_c, st_c, cfg, closure_steps, every, every, lambda k: True,
+                                       after_step=count_fallbacks)
     torch.cuda.synchronize()
-    train_ms = a.elapsed_time(b)
-    # held-out snapshots of the same run: relative L2 error of the normalised heat flux
-    yh = torch.zeros_like(Yh)
-    ctx.mlp_forward(P, Xh, yh)
-    torch.cuda.synchronize()
-    d = (yh[:, :10] - Yh[:, :10]).double()
-    heldout = (d.norm() / Yh[:, :10].double().norm()).item()
+    closure_s = time.perf_counter() - t1
+    fb1 = fb.cpu().numpy().tolist()
+    del st_c, ctx_c
+    # round 2: both sets, from the initial weights
+    Xt, Yt = torch.cat(Xtr + Xc).contiguous(), torch.cat(Ytr + Yc).contiguous()
+    w = torch.cat(Str + Sc).float()
+    n_train = Xt.shape[0]
+    del Xtr, Ytr, Xc, Yc
+    P, losses, step, train_ms = _train_network(ctx, Xt, Yt, w / w.mean() + 1e-3, epochs, batch, lr, seed)
+    del Xt, Yt
+    n_held = Xh.shape[0]
+    heldout = heldout_Q(P)
     cells = cfg["nx"] * cfg["ny"]
     same = {}
     for s, name in enumerate(("electrons", "ions")):
@@ -311,6 +357,8 @@ def train_closure(cfg, f, F, gen_steps=3000, start=60, every=15, epochs=96, batc
                           for j, i in enumerate(ho) if K[i][1] == s])
         e_net, e_mean = _heat_flux_vector_error(ctx, P, Xh[rows].contiguous(), Yh[rows].contiguous(), Sh[rows])
         same[name] = {"network": round(e_net, 4), "mean_predictor": round(e_mean, 4), "zero_predictor": 1.0}
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    yh = torch.zeros_like(Yh)
     a.record()
     for _ in range(5):
         ctx.mlp_forward(P, Xh, yh)
@@ -329,11 +377,14 @@ def train_closure(cfg, f, F, gen_steps=3000, start=60, every=15, epochs=96, batc
                                                 torch.cat([Yo[i] for i in rows]).contiguous(),
                                                 torch.cat([So[i] for i in rows]))
         other[name] = {"network": round(e_net, 4), "mean_predictor": round(e_mean, 4), "zero_predictor": 1.0}
-    del st_o, Xo, Yo, So, Xt, Yt, Xh, Yh, ctx
+    del st_o, Xo, Yo, So, Xh, Yh, ctx
     torch.cuda.empty_cache()
     return P.cpu().numpy(), {
         "samples": n_train + n_held, "train_samples": n_train, "heldout_samples": n_held, "data_steps": gen_steps,
-        "data_seconds": round(gen_s, 2), "epochs": epochs, "batch": batch, "adam_steps": step,
+        "data_seconds": round(gen_s, 2), "closure_data_steps": closure_steps,
+        "closure_data_seconds": round(closure_s, 2), "closure_data_fallback_steps": fb1,
+        "round1_heldout_rel_l2_Q": round(q1, 4), "round1_train_ms": round(ms1, 1), "round1_adam_steps": steps1,
+        "epochs": epochs, "batch": batch, "adam_steps": step,
         "sampling": "probability proportional to n m v_t^3",
         "train_ms": round(train_ms, 1), "train_samples_per_s": round(step * batch / (train_ms * 1e-3)),
         "loss_per_epoch": [round(x, 6) for x in losses[::max(len(losses) // 16, 1)]], "heldout_rel_l2_Q": round(heldout, 4),
