@@ -220,8 +220,11 @@ def _fluid_from(mom, m, du, tscale, kind):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("nv", [8, 16])
+@pytest.mark.parametrize("nv", [8, 16, 34])
 def test_moment_fit_3v(dtype, nv):
+    """Fit per cell against the oracle on rough data (clipping) with one
+    skipped cell; 34^3 runs the one-block-per-cell kernels (FP64: two pencils
+    per thread in registers, the rest in LDS)."""
     import torch
     nx, ny = 7, 3
     cfg, f0, _ = W.gem(nx=nx, ny=ny, nv=nv, dtype=np.float64)
