@@ -1048,8 +1048,9 @@ pfc_v3_cube_kernel(const T* fin, T* fout, const double* __restrict__ E, const do
 // memory (N / PL = 2 rounds); the rest of the block waits in registers.
 // Thread t owns the v_x pencils p = t + NTH j (p < N^2):
 //  1. each pencil is loaded, swept along v_x in registers, and split: its
-//     values in the first PL planes go to shared memory, the others stay in
-//     registers (a[j]);
+//     values in the first PL planes go to shared memory, the others wait in
+//     registers (a[j]; those of the partial last pencil set, which only some
+//     threads own, in the pencil's own positions of the output block);
 //  2. round 0 sweeps the first PL planes; each thread then swaps its own
 //     plane values with a[j] (no other thread touches them), and round 1
 //     sweeps the last PL planes;
