@@ -509,11 +509,16 @@ def _oracle_slab(cfg, f, F, i0, j0, snx, sny):
     return c, fs, G
 
 
+YEE = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+
+
 def _oracle_steps(job):
     """Worker of the CPU baseline: the FP64 numpy oracle's full 2X3V step on
-    one slab, repeated until `seconds` have passed (at least one step), on
-    one thread.  Returns (phase-space cells, steps, seconds)."""
-    cfg, f, F, seconds = job
+    one slab, repeated until `seconds` have passed (at least `capture` steps,
+    at least one), on one thread.  Returns (phase-space cells, steps, seconds,
+    state) with state = f of every species and the Yee fields (plain arrays)
+    after the first `capture` steps, or None when capture is 0."""
+    cfg, f, F, seconds, capture = job
     from threadpoolctl import threadpool_limits
     from oracle import moments as OM, step as OS
     with threadpool_limits(limits=1):
@@ -526,14 +531,17 @@ def _oracle_steps(job):
         st = dict(f=f, U=Us, mom_post=moms, F=F)
         t0 = time.perf_counter()
         n = 0
-        while n < 1 or time.perf_counter() - t0 < seconds:
+        state = None
+        while n < max(capture, 1) or time.perf_counter() - t0 < seconds:
             st = OS.step_2x3v(st, cfg, cfg["dt"])
             n += 1
+            if n == capture:
+                state = dict(f=[np.array(x) for x in st["f"]], fields={k: np.array(getattr(st["F"], k)) for k in YEE})
         dt = time.perf_counter() - t0
-    return sum(x.size for x in f), n, dt
+    return sum(x.size for x in f), n, dt, state
 
 
-def cpu_baseline(cfg, f, F, label, seconds=8.0, snx=16, sny=8):
+def cpu_baseline(cfg, f, F, label, seconds=8.0, snx=16, sny=8, check_steps=2):
     """The FP64 numpy oracle's full step on windows of the benchmark
     workload's own initial state (snx x sny spatial cells with every velocity
     cell of both species: the per-cell work of the full grid).  Timed once on
@@ -546,24 +554,59 @@ def cpu_baseline(cfg, f, F, label, seconds=8.0, snx=16, sny=8):
     # windows along the middle rows (the current sheet) at distinct x
     wins = [(((k * nx) // ncores) // snx * snx % (nx - snx + 1), (ny - sny) // 2) for k in range(ncores)]
     ctx = mp.get_context("spawn")              # workers never touch the GPU
+    cw, fw, Fw = _oracle_slab(cfg, f, F, *wins[0], snx, sny)
     with ctx.Pool(1) as pool:
-        c, n1, t1 = pool.apply(_oracle_steps, ((*_oracle_slab(cfg, f, F, *wins[0], snx, sny), seconds),))
+        c, n1, t1, ref = pool.apply(_oracle_steps, ((cw, fw, Fw, seconds, check_steps),))
     v1 = c * n1 / t1
-    jobs = [(*_oracle_slab(cfg, f, F, i0, j0, snx, sny), seconds) for i0, j0 in wins]
+    # the oracle's state after check_steps steps of window 0, and that window's
+    # start, for the GPU's error against it (plain arrays)
+    check = dict(cfg=cw, f0=fw, F0={k: np.array(getattr(Fw, k)) for k in YEE}, ref=ref, steps=check_steps,
+                 window=f"{snx}x{sny} spatial cells at x index {wins[0][0]}, y index {wins[0][1]}")
+    jobs = [(*_oracle_slab(cfg, f, F, i0, j0, snx, sny), seconds, 0) for i0, j0 in wins]
     t0 = time.perf_counter()
     with ctx.Pool(ncores) as pool:
         res = pool.map(_oracle_steps, jobs)
     wall = time.perf_counter() - t0
-    tot = sum(c * n for c, n, _ in res)
-    slowest = max(t for _, _, t in res)
+    tot = sum(c * n for c, n, _, _ in res)
+    slowest = max(t for _, _, t, _ in res)
     vall = tot / slowest
     nv = cfg["species"][0]["nv"][0]
     return {"value": vall, "unit": "cell-updates/s", "cores": ncores, "kind": "oracle",
             "sample": f"{label}: the numpy FP64 oracle's full step (fit on, both species, {nv}^3 velocity cells) on "
                       f"{ncores} windows of {snx}x{sny} spatial cells of the workload's own initial state, one "
-                      f"single-threaded worker process per core, {min(n for _, n, _ in res)}-"
-                      f"{max(n for _, n, _ in res)} steps each in {slowest:.1f} s ({wall:.1f} s wall with start-up)",
-            "one_thread": {"value": v1, "cores": 1, "steps": n1, "seconds": round(t1, 2)}}
+                      f"single-threaded worker process per core, {min(n for _, n, _, _ in res)}-"
+                      f"{max(n for _, n, _, _ in res)} steps each in {slowest:.1f} s ({wall:.1f} s wall with start-up)",
+            "one_thread": {"value": v1, "cores": 1, "steps": n1, "seconds": round(t1, 2)}}, check
+
+
+def oracle_error(check):
+    """The GPU step against the FP64 oracle: the same window of the workload
+    (its own problem, as in the CPU baseline) stepped `steps` times by the
+    library in FP32 and in FP64 storage, compared with the oracle's state
+    that the CPU-baseline leg recorded: relative L2 error of f per species and
+    the largest field difference relative to the largest field value."""
+    import types
+    import torch
+    from paper_2109_06743_amd import vl
+    cfg, ref, steps = check["cfg"], check["ref"], check["steps"]
+    F0 = types.SimpleNamespace(**check["F0"])
+    out = {"window": check["window"], "steps": steps, "reference": "FP64 numpy oracle, same initial state"}
+    for dt in ("f32", "f64"):
+        ctx = vl.Context(cfg, dt)
+        st = vl.StepState(ctx, check["f0"], vl.yee_pack(F0))
+        for _ in range(steps):
+            ctx.step(st, cfg["dt"])
+        ctx.sync()
+        errs = []
+        for s, fr in enumerate(ref["f"]):
+            g = st.f[s].double().cpu().numpy().reshape(fr.shape)
+            errs.append(float(np.linalg.norm(g - fr) / np.linalg.norm(fr)))
+        fg = st.fields.cpu().numpy()
+        fo = vl.yee_pack(types.SimpleNamespace(**ref["fields"]))
+        out[dt] = {"f_rel_l2_per_species": errs,
+                   "fields_max_abs_rel": float(np.abs(fg - fo).max() / np.abs(fo).max())}
+        del st, ctx
+    return out
 
 
 def step_fractions(res):
@@ -745,12 +788,12 @@ def main():
     built = build_workload(args.workload)
     cfg, f, F, label = built
     log(f"workload {label}: built in {time.perf_counter() - t0:.1f} s")
-    cpu = None
+    cpu = check = None
     if not args.no_cpu and cfg["kind"] == "2x3v" and args.workload != "ot":
         # before any GPU call: the worker processes are started from a process
         # that has not initialised the GPU
         log("timing the CPU oracle on windows of the workload ...")
-        cpu = cpu_baseline(cfg, f, F, label)
+        cpu, check = cpu_baseline(cfg, f, F, label)
         log(f"  {cpu}")
     torch.cuda.set_device(0)
     head, _ = measure(args.workload, args, fp64=not args.no_fp64, built=built, backsub=not args.no_backsub)
@@ -769,6 +812,9 @@ def main():
             out[k] = head[k]
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if check is not None:
+        out["oracle_error"] = oracle_error(check)
+        log(f"error against the oracle: {out['oracle_error']}")
     if args.secondary != "none" and args.secondary != args.workload:
         sec, _ = measure(args.secondary, args, fp64=not args.no_fp64, backsub=not args.no_backsub)
         out["secondary"] = sec
