@@ -153,7 +153,8 @@ vl_status vl_moment_fit(vl_ctx* ctx, int32_t s, const void* f_in, void* f_out, c
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc): the same computation and results as vl_moment_fit,
  * with its scratch (the fitting parameters of every spatial cell, 160 bytes,
- * and a clip partial, 4 bytes) in a static device array of 7.7 MiB that each
+ * a clip partial, 4 bytes, and 640 bytes for the sum of the clip partials)
+ * in a static device array of 7.7 MiB that each
  * GPU the library runs on holds until the process ends, instead of context
  * scratch.  At most 49152 spatial cells (nx*ny): larger contexts get
  * VL_EINVAL before any device call.  The call allocates nothing (the context

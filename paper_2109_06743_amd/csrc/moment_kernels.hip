@@ -635,23 +635,28 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
     if (max_out) block_max_part(mx, max_out);
 }
 
-// Moment fitting of one cubic cell per block when the cell's pencils do not
-// fit the block's registers (FP64 34^3, 314 KB): thread t owns the v_x
-// pencils t + NTH j, the NR full sets in registers and the remainder
-// (t < N^2 - NR NTH) in shared memory, so f is read and written once.  The
-// steps are fit3_cube_kernel's; the exponentials are computed again in the
-// exchange pass instead of being kept.
+// Moment fitting of one large cubic cell per block (34^3) without holding the
+// cell: the normalisation sums need only the two Maxwellians, so the block
+// computes them first; f is then streamed once, pencil by pencil (thread t
+// owns the v_x pencils t + NTH j), exchanged, clipped, summed into the FP64
+// post-fit moments and stored unscaled, through the caches.  Where the
+// density rescale factor rounds to one in the storage type the stored values
+// are final, equal to fit3_cube_kernel's; elsewhere (a quarter to a third of
+// the cells in FP32) each thread reads back the values it stored, which are
+// mostly still in L2, and rescales them.  No 157 KB (FP32) or 314 KB (FP64)
+// cell is held in registers or shared memory, so several cells share a CU.
+// The arithmetic is fit3_cube_kernel's (pencil sums of the samples in four
+// chains in FP32, two in FP64; samples computed again in the exchange).
 template <class T, int N, int NTH>
 __global__ void __launch_bounds__(NTH)
-fit3_big_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
-                unsigned* __restrict__ clip_part, VGrid G, XTable X, typename Bits<T>::U* __restrict__ max_out) {
+fit3_stream_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __restrict__ mom_post,
+                   unsigned* __restrict__ clip_part, VGrid G, XTable X, typename Bits<T>::U* __restrict__ max_out) {
     constexpr int NN = N * N;
-    constexpr int NR = NN / NTH;                 // full pencil sets in registers
-    constexpr int REM = NN - NR * NTH;           // pencils in shared memory
+    constexpr int NS = (NN + NTH - 1) / NTH;     // pencil sets
     constexpr int NW = NTH / kWave;
+    constexpr int CH = sizeof(T) == 4 ? 4 : 2;   // pass-1 sum chains
     constexpr unsigned XB = NN * sizeof(T);      // bytes between v_x planes
-    static_assert(NTH % kWave == 0 && REM < NTH, "launch shape");
-    __shared__ T rem[(REM > 0 ? REM : 1) * N];
+    static_assert(NTH % kWave == 0, "launch shape");
     __shared__ double red[NW * 21];
     __shared__ double fin_s[21];
     const int tid = threadIdx.x;
@@ -659,110 +664,107 @@ fit3_big_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* __
     const double dV = G.dv[0] * G.dv[1] * G.dv[2];
     const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(fin + cell * (N * NN)), 0, N * XB, kBufWord3);
     const auto rd = __builtin_amdgcn_make_buffer_rsrc(fout + cell * (N * NN), 0, N * XB, kBufWord3);
-    const bool has_rem = tid < REM;
-    T fv[NR][N];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        const unsigned po = (unsigned)(tid + NTH * j) * sizeof(T);
-#pragma unroll
-        for (int k = 0; k < N; ++k) fv[j][k] = buf_ld(rs, po, k * XB, T());
-    }
-    if (has_rem) {
-        const unsigned po = (unsigned)(tid + NTH * NR) * sizeof(T);
-#pragma unroll
-        for (int k = 0; k < N; ++k) rem[k * REM + tid] = buf_ld(rs, po, k * XB, T());
-    }
-    // element k of the thread's pencil j (j = NR: the shared-memory one)
-    auto fget = [&](int j, int k) -> T { return j < NR ? fv[j < NR ? j : 0][k] : rem[k * REM + tid]; };
-    auto fset = [&](int j, int k, T v) {
-        if (j < NR)
-            fv[j < NR ? j : 0][k] = v;
-        else
-            rem[k * REM + tid] = v;
-    };
+    auto act = [&](int j) { return tid + NTH * j < NN; };
     const FitCell& C = P[cell];
     const bool ok = C.ok != 0.0;
     const double nV = C.nV;
-    unsigned nclip = 0;     // clipped elements of this wave (the same in every lane)
+    T A = T(0), Bc = T(0);
     if (ok) {
-        // normalisation sums of the two Maxwellians (FP64)
+        // normalisation sums of the two Maxwellians (FP64 across pencils)
         double s[2] = {0.0, 0.0};
-#pragma unroll
-        for (int j = 0; j <= NR; ++j) {
-            if (j < NR || has_rem) {
+#pragma unroll 1
+        for (int j = 0; j < NS; ++j) {
+            if (act(j)) {
                 const int t = tid + NTH * j;
                 QuadX<T> qv, qf;
                 qv.set(C.aV, C.uV, vc(G, 1, t / N), vc(G, 2, t % N));
                 qf.set(C.aF, C.uF, vc(G, 1, t / N), vc(G, 2, t % N));
-                T pa[2] = {T(0), T(0)}, pb[2] = {T(0), T(0)};
+                T pa[CH], pb[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) pa[c] = pb[c] = T(0);
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
-                    pa[k & 1] += qv.g((T)X.v[k]);
-                    pb[k & 1] += qf.g((T)X.v[k]);
+                    pa[k % CH] += qv.g((T)X.v[k]);
+                    pb[k % CH] += qf.g((T)X.v[k]);
                 }
-                s[0] += (double)(pa[0] + pa[1]);
-                s[1] += (double)(pb[0] + pb[1]);
+                if constexpr (CH == 4) {
+                    s[0] += (double)((pa[0] + pa[1]) + (pa[2] + pa[3]));
+                    s[1] += (double)((pb[0] + pb[1]) + (pb[2] + pb[3]));
+                } else {
+                    s[0] += (double)(pa[0] + pa[1]);
+                    s[1] += (double)(pb[0] + pb[1]);
+                }
             }
         }
         block_sum_rs<2>(s, red, fin_s);
-        const T A = (T)(nV / (fin_s[0] * dV));
-        const T Bc = (T)(nV / (fin_s[1] * dV));
-        // exchange and clip
+        A = (T)(nV / (fin_s[0] * dV));
+        Bc = (T)(nV / (fin_s[1] * dV));
+    }
+    // exchange, clip, FP64 moments and the unscaled store, one pencil at a time
+    double acc[21];
 #pragma unroll
-        for (int j = 0; j <= NR; ++j) {
-            const bool act = j < NR || has_rem;
-            const int t = tid + NTH * j;
+    for (int q = 0; q < 21; ++q) acc[q] = 0.0;
+    unsigned nclip = 0;     // clipped elements of this wave (the same in every lane)
+    T mx = T(0);
+#pragma unroll 1
+    for (int j = 0; j < NS; ++j) {
+        const bool a = act(j);
+        const int t = a ? tid + NTH * j : 0;
+        const unsigned po = (unsigned)t * sizeof(T);
+        T g[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) g[k] = a ? buf_ld(rs, po, k * XB, T()) : T(0);
+        if (ok) {
             QuadX<T> qv, qf;
             qv.set(C.aV, C.uV, vc(G, 1, t / N), vc(G, 2, t % N));
             qf.set(C.aF, C.uF, vc(G, 1, t / N), vc(G, 2, t % N));
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const T x = act ? fget(j, k) - A * qv.g((T)X.v[k]) + Bc * qf.g((T)X.v[k]) : T(0);
+                const T x = g[k] - A * qv.g((T)X.v[k]) + Bc * qf.g((T)X.v[k]);
                 const bool neg = x < T(0);
-                nclip += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(act && neg));
-                if (act) fset(j, k, neg ? T(0) : x);
+                nclip += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64(a && neg));
+                g[k] = neg ? T(0) : x;
             }
         }
-    }
-    // raw moments of the clipped f'' (FP64 pencil sums)
-    double acc[21];
-#pragma unroll
-    for (int q = 0; q < 20; ++q) acc[q] = 0.0;
-    acc[20] = (tid & (kWave - 1)) == 0 ? (double)nclip : 0.0;
-#pragma unroll
-    for (int j = 0; j <= NR; ++j) {
-        if (j < NR || has_rem) {
-            const int t = tid + NTH * j;
+        if (a) {
             double Se[4] = {0.0, 0.0, 0.0, 0.0}, So[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                const double g = (double)fget(j, k);
+                const double v = (double)g[k];
                 double* S = (k & 1) ? So : Se;
-                S[0] += g;
-                S[1] = fma(g, X.v[k], S[1]);
-                S[2] = fma(g, X.v2[k], S[2]);
-                S[3] = fma(g, X.v3[k], S[3]);
+                S[0] += v;
+                S[1] = fma(v, X.v[k], S[1]);
+                S[2] = fma(v, X.v2[k], S[2]);
+                S[3] = fma(v, X.v3[k], S[3]);
+                buf_st<kBufCached>(g[k], rd, po, k * XB);
+                mx = fmax(mx, g[k]);
             }
             const double S[4] = {Se[0] + So[0], Se[1] + So[1], Se[2] + So[2], Se[3] + So[3]};
-            double a[20];
-            pencil_moments(S, vc(G, 1, t / N), vc(G, 2, t % N), a);
+            double m[20];
+            pencil_moments(S, vc(G, 1, t / N), vc(G, 2, t % N), m);
 #pragma unroll
-            for (int q = 0; q < 20; ++q) acc[q] += a[q];
+            for (int q = 0; q < 20; ++q) acc[q] += m[q];
         }
     }
+    acc[20] = (tid & (kWave - 1)) == 0 ? (double)nclip : 0.0;
     block_sum_rs<21>(acc, red, fin_s);
     const double scale = ok ? nV / (fin_s[0] * dV) : 1.0;
     const T sc = (T)scale;     // 1 exactly when the cell is skipped
-    T mx = T(0);
+    if (sc != T(1)) {          // uniform over the block
+        mx = T(0);
+#pragma unroll 1
+        for (int j = 0; j < NS; ++j) {
+            if (act(j)) {
+                const unsigned po = (unsigned)(tid + NTH * j) * sizeof(T);
+                T g[N];
 #pragma unroll
-    for (int j = 0; j <= NR; ++j) {
-        if (j < NR || has_rem) {
-            const unsigned po = (unsigned)(tid + NTH * j) * sizeof(T);
+                for (int k = 0; k < N; ++k) g[k] = buf_ld<kBufCached>(rd, po, k * XB, T());
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const T o = fget(j, k) * sc;
-                buf_st(o, rd, po, k * XB);
-                mx = fmax(mx, o);
+                for (int k = 0; k < N; ++k) {
+                    const T o = g[k] * sc;
+                    buf_st(o, rd, po, k * XB);
+                    mx = fmax(mx, o);
+                }
             }
         }
     }
@@ -905,33 +907,58 @@ hipError_t launch_moments1(const T* f, double* mom, long long cells, int nv, dou
     return hipGetLastError();
 }
 
-// counters[0] += sum of the per-block clip counts (one block, 16-byte loads,
-// fixed order).
-__global__ void __launch_bounds__(1024)
-count_finalize_kernel(const unsigned* __restrict__ part, long long n, unsigned long long* __restrict__ counters) {
-    __shared__ unsigned long long red[16];
+// counters[0] += sum of the per-block clip counts part[0..n), in two launches
+// like the maxima (launch_max_finalize): up to kFinStage blocks sum ranges
+// into a stage of 64-bit sums right after the partials, one wave adds the
+// stage to the counter.  Integer sums: exact in any order.
+__global__ void __launch_bounds__(256)
+count_stage_kernel(const unsigned* __restrict__ part, long long n, long long chunk,
+                   unsigned long long* __restrict__ out, int add) {
+    __shared__ unsigned long long red[256 / kWave];
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < n ? lo + chunk : n;
     unsigned long long acc = 0;
-    const long long n16 = n / 4;
-    const uint4* p16 = reinterpret_cast<const uint4*>(part);
-    for (long long b = 0; b < n16; b += 8 * (long long)blockDim.x) {
-        uint4 v[8];
+    for (long long b = lo; b < hi; b += 8 * 256) {
+        unsigned v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const long long i = b + u * (long long)blockDim.x + threadIdx.x;
-            v[u] = i < n16 ? p16[i] : make_uint4(0, 0, 0, 0);
+            const long long i = b + u * 256 + threadIdx.x;
+            v[u] = i < hi ? part[i] : 0u;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += (unsigned long long)v[u].x + v[u].y + v[u].z + v[u].w;
+        for (int u = 0; u < 8; ++u) acc += v[u];
     }
-    for (long long i = n16 * 4 + threadIdx.x; i < n; i += blockDim.x) acc += part[i];
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) acc += red[w];
-        counters[0] += acc;
+        for (int w = 1; w < 256 / kWave; ++w) acc += red[w];
+        if (add)
+            out[0] += acc;
+        else
+            out[blockIdx.x] = acc;
     }
+}
+
+__global__ void __launch_bounds__(kWave)
+count_final_kernel(const unsigned long long* __restrict__ stage, int g, unsigned long long* __restrict__ counters) {
+    unsigned long long a = (int)threadIdx.x < g ? stage[threadIdx.x] : 0ull;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kWave);
+    if (threadIdx.x == 0) counters[0] += a;
+}
+
+static void launch_count_finalize(const unsigned* part, long long n, unsigned long long* counters, hipStream_t st) {
+    const FinSplit fs = fin_split(n);
+    if (fs.blocks == 1) {
+        hipLaunchKernelGGL(count_stage_kernel, dim3(1), dim3(256), 0, st, part, n, n, counters, 1);
+        return;
+    }
+    auto* stage = (unsigned long long*)((char*)part + fin_stage(n, sizeof(unsigned)));
+    hipLaunchKernelGGL(count_stage_kernel, dim3(fs.blocks), dim3(256), 0, st, part, n, fs.chunk, stage, 0);
+    hipLaunchKernelGGL(count_final_kernel, dim3(1), dim3(kWave), 0, st, (const unsigned long long*)stage, fs.blocks,
+                       counters);
 }
 
 template <class T>
@@ -958,20 +985,20 @@ hipError_t launch_fit3(const T* fin, T* fout, const double* mom_pre, double* U, 
             if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, kFit16Waves, kFit16Pencils>), grid, dim3(64 * kFit16Waves), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, kFit12Waves, kFit12Pencils>), grid, dim3(64 * kFit12Waves), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
-            if (N == kBigCube)   // 640 threads, two pencils each (1156 pencils)
-                hipLaunchKernelGGL((fit3_cube_kernel<T, kBigCube, 10, 2>), grid, dim3(640), 0, st, fin, fout, P,
+            if (N == kBigCube)   // streamed: the cell is not held
+                hipLaunchKernelGGL((fit3_stream_kernel<T, kBigCube, 256>), grid, dim3(256), 0, st, fin, fout, P,
                                    mom_post, cp, G, X, mo);
         } else {
             if (N == 16) hipLaunchKernelGGL((fit3_cube_kernel<T, 16, 4, 1>), grid, dim3(256), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 12) hipLaunchKernelGGL((fit3_cube_kernel<T, 12, 3, 1>), grid, dim3(192), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
             if (N == 8) hipLaunchKernelGGL((fit3_cube_kernel<T, 8, 1, 1>), grid, dim3(64), 0, st, fin, fout, P, mom_post, cp, G, X, mo);
-            if (N == kBigCube)   // 512 threads: two pencils each in registers, 132 in shared memory
-                hipLaunchKernelGGL((fit3_big_kernel<T, kBigCube, 512>), grid, dim3(512), 0, st, fin, fout, P, mom_post,
-                                   cp, G, X, mo);
+            if (N == kBigCube)   // streamed: the cell is not held
+                hipLaunchKernelGGL((fit3_stream_kernel<T, kBigCube, 256>), grid, dim3(256), 0, st, fin, fout, P,
+                                   mom_post, cp, G, X, mo);
         }
         hipError_t e = hipGetLastError();
         if (e == hipSuccess && cnt)
-            hipLaunchKernelGGL(count_finalize_kernel, dim3(1), dim3(1024), 0, st, clip_part, cells, cnt);
+            launch_count_finalize(clip_part, cells, cnt, st);
         if (e == hipSuccess && max_out) e = launch_max_finalize<T>(part, cells, max_out, st);
         return e == hipSuccess ? hipGetLastError() : e;
     }

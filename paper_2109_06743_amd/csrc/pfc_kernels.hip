@@ -1217,32 +1217,28 @@ array_max_kernel(const T* __restrict__ f, long long n, typename Bits<T>::U* __re
 }
 
 // Maximum of the per-block partial maxima part[0..n) into *slot (bits of
-// non-negative values order like the values).  One block; 16-byte loads,
-// eight in flight per thread; fixed order.
-template <class T>
-__global__ void __launch_bounds__(1024)
-max_finalize_kernel(const typename Bits<T>::U* __restrict__ part, long long n, typename Bits<T>::U* __restrict__ slot) {
-    using U = typename Bits<T>::U;
-    constexpr int PER = 16 / sizeof(U);            // partials per 16-byte load
-    __shared__ U red[16];
+// non-negative values order like the values), in two launches: up to
+// kFinStage blocks each fold a contiguous range of the partials (eight loads
+// in flight per thread) into stage[b], placed right after the partials
+// (fin_stage); one wave folds the stage into the slot.  With a single range
+// the first launch writes the slot itself.  Fixed order.
+template <class U>
+__global__ void __launch_bounds__(256)
+max_stage_kernel(const U* __restrict__ part, long long n, long long chunk, U* __restrict__ out) {
+    __shared__ U red[256 / kWave];
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < n ? lo + chunk : n;
     U m = 0;
-    const long long n16 = n / PER;
-    const uint4* p16 = reinterpret_cast<const uint4*>(part);
-    for (long long b = 0; b < n16; b += 8 * (long long)blockDim.x) {
-        uint4 v[8];
+    for (long long b = lo; b < hi; b += 8 * 256) {
+        U v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const long long i = b + u * (long long)blockDim.x + threadIdx.x;
-            v[u] = i < n16 ? p16[i] : make_uint4(0, 0, 0, 0);
+            const long long i = b + u * 256 + threadIdx.x;
+            v[u] = i < hi ? part[i] : U(0);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const U* e = reinterpret_cast<const U*>(&v[u]);
-#pragma unroll
-            for (int k = 0; k < PER; ++k) m = e[k] > m ? e[k] : m;
-        }
+        for (int u = 0; u < 8; ++u) m = v[u] > m ? v[u] : m;
     }
-    for (long long i = n16 * PER + threadIdx.x; i < n; i += blockDim.x) m = part[i] > m ? part[i] : m;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         const U y = __shfl_xor(m, o, kWave);
@@ -1251,15 +1247,33 @@ max_finalize_kernel(const typename Bits<T>::U* __restrict__ part, long long n, t
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) m = red[w] > m ? red[w] : m;
-        *slot = m;
+        for (int w = 1; w < 256 / kWave; ++w) m = red[w] > m ? red[w] : m;
+        out[blockIdx.x] = m;
     }
+}
+
+template <class U>
+__global__ void __launch_bounds__(kWave) max_final_kernel(const U* __restrict__ stage, int g, U* __restrict__ slot) {
+    U m = (int)threadIdx.x < g ? stage[threadIdx.x] : U(0);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const U y = __shfl_xor(m, o, kWave);
+        m = y > m ? y : m;
+    }
+    if (threadIdx.x == 0) *slot = m;
 }
 
 template <class T>
 hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStream_t st) {
     using U = typename Bits<T>::U;
-    hipLaunchKernelGGL((max_finalize_kernel<T>), dim3(1), dim3(1024), 0, st, (const U*)part, n, (U*)slot);
+    const FinSplit fs = fin_split(n);
+    if (fs.blocks == 1) {
+        hipLaunchKernelGGL((max_stage_kernel<U>), dim3(1), dim3(256), 0, st, (const U*)part, n, n, (U*)slot);
+        return hipGetLastError();
+    }
+    U* stage = (U*)((char*)part + fin_stage(n, sizeof(U)));
+    hipLaunchKernelGGL((max_stage_kernel<U>), dim3(fs.blocks), dim3(256), 0, st, (const U*)part, n, fs.chunk, stage);
+    hipLaunchKernelGGL((max_final_kernel<U>), dim3(1), dim3(kWave), 0, st, (const U*)stage, fs.blocks, (U*)slot);
     return hipGetLastError();
 }
 

@@ -122,9 +122,12 @@ vl_status ensure_device(vl_ctx* ctx) {
     VL_HIP(hipMalloc(&p, bytes));
     VL_HIP(hipMemset(p, 0, bytes));
     void* q = nullptr;
-    VL_HIP(hipMalloc(&q, 12 * (size_t)ctx->max_blocks));
+    // per-block maxima (8 bytes a block), then the clip counts (4 bytes), each
+    // followed by the stage of its two-level reduction
+    const size_t part_bytes = 8 * (size_t)ctx->max_blocks + vl::kFinSlack;
+    VL_HIP(hipMalloc(&q, part_bytes + 4 * (size_t)ctx->max_blocks + vl::kFinSlack));
     ctx->bpart = q;
-    ctx->bclip = (unsigned*)((char*)q + 8 * (size_t)ctx->max_blocks);
+    ctx->bclip = (unsigned*)((char*)q + part_bytes);
     ctx->slots = (unsigned long long*)p;
     ctx->dft = (double*)(ctx->slots + kSlots * VL_MAX_SPECIES);
     ctx->part = ctx->dft + 2 * (size_t)ctx->cfg.nx + 2;
@@ -561,13 +564,14 @@ vl_status step_typed(vl_ctx* ctx, vl_state* S, double dt, hipStream_t st) {
 
 // ------------------------------------------------ allocation-free fitting --
 // vl_moment_fit_noalloc keeps the fitting parameters of every spatial cell
-// (kFitCellDoubles doubles) and the per-cell clip partials in one static
-// device array instead of context scratch, so the call allocates nothing.
+// (kFitCellDoubles doubles) and the per-cell clip partials (with the stage of
+// their sum) in one static device array instead of context scratch, so the
+// call allocates nothing.
 // Host code never uses the array's name as an address: the device address
 // is looked up once per device (hipGetSymbolAddress) and kept.
 constexpr long long kNoAllocCells = 49152;                       // 48 Ki spatial cells
 constexpr size_t kNoAllocParamBytes = (size_t)kNoAllocCells * vl::kFitCellDoubles * sizeof(double);
-constexpr size_t kNoAllocBytes = kNoAllocParamBytes + (size_t)kNoAllocCells * sizeof(unsigned);
+constexpr size_t kNoAllocBytes = kNoAllocParamBytes + (size_t)kNoAllocCells * sizeof(unsigned) + vl::kFinSlack;
 static_assert(kNoAllocParamBytes % 256 == 0, "clip partials start 256-byte aligned");
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 

@@ -140,18 +140,23 @@ __device__ __forceinline__ void st_f(T v, T* p) {
 // Word 3 of the descriptor is the gfx9 raw-buffer format (32-bit data).
 constexpr int kBufWord3 = 0x00020000;
 constexpr int kBufNT = 2;          // cache policy: non-temporal
+constexpr int kBufCached = 0;      // cache policy: ordinary (kept in the caches)
+template <int POL = kBufNT>
 __device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kBufNT));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, POL));
 }
+template <int POL = kBufNT>
 __device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kBufNT));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, POL));
 }
+template <int POL = kBufNT>
 __device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, kBufNT);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, POL);
 }
+template <int POL = kBufNT>
 __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, kBufNT);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, POL);
 }
 
 // Maximum over the block of non-negative values, stored (as its bit pattern)

@@ -57,6 +57,25 @@ hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy
                          double tau_dx, double vy_lo, double dvy, double tau_dy, int per, const void* finf,
                          void* max_out, void* part, hipStream_t st);
 constexpr long long kMaxArrayBlocks = 4096;
+// Reductions of per-block partials (maxima, clip counts) run in two launches:
+// fin_split(n).blocks <= kFinStage blocks fold ranges of fin_split(n).chunk
+// partials into a stage of kFinStage entries that sits fin_stage(n, size)
+// bytes after the partials' start, then one wave folds the stage.  A partials
+// buffer of n entries of `size` bytes therefore needs kFinSlack bytes beyond
+// its n * size.
+constexpr int kFinStage = 64;
+constexpr long long kFinRange = 8192;          // partials per first-level block, at least
+constexpr size_t kFinSlack = 128 + kFinStage * 8;
+struct FinSplit {
+    int blocks;
+    long long chunk;
+};
+inline FinSplit fin_split(long long n) {
+    long long g = (n + kFinRange - 1) / kFinRange;
+    g = g < 1 ? 1 : (g > kFinStage ? kFinStage : g);
+    return {(int)g, (n + g - 1) / g};
+}
+inline size_t fin_stage(long long n, size_t size) { return ((size_t)n * size + 127) / 128 * 128; }
 template <class T>
 hipError_t launch_max_finalize(const void* part, long long n, void* slot, hipStream_t st);
 

@@ -223,8 +223,9 @@ def _fluid_from(mom, m, du, tscale, kind):
 @pytest.mark.parametrize("nv", [8, 16, 34])
 def test_moment_fit_3v(dtype, nv):
     """Fit per cell against the oracle on rough data (clipping) with one
-    skipped cell; 34^3 runs the one-block-per-cell kernels (FP64: two pencils
-    per thread in registers, the rest in LDS)."""
+    skipped cell; 34^3 runs the streamed kernel (the cell is not held; cells
+    whose density rescale is not one re-read and rescale their output, which
+    the per-cell density check below covers)."""
     import torch
     nx, ny = 7, 3
     cfg, f0, _ = W.gem(nx=nx, ny=ny, nv=nv, dtype=np.float64)
