@@ -130,6 +130,28 @@ def test_step_conserves_mass_and_is_deterministic(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_step_kept_maximum_matches_recomputed(dtype):
+    """The limiter bound max f of each step comes from the per-block maxima of
+    the kernel that wrote f (reduced in two launches once there are more than
+    8192 partials: 128 x 72 cells).  Steps that take the kept maximum and
+    steps told to recompute it from f (f_max_valid = 0) give the same f and
+    fields bit for bit."""
+    import torch
+    cfg, f, F0 = W.gem(nx=128, ny=72, nv=8, dt=0.003, fit=True, dtype=np.float64)
+    runs = []
+    for recompute in (False, True):
+        ctx, st, _ = _start_2x3v(cfg, f, F0, dtype)
+        for _ in range(3):
+            if recompute:
+                st.c.f_max_valid = 0
+            ctx.step(st, cfg["dt"])
+        ctx.sync()
+        runs.append([x.clone() for x in st.f] + [st.fields.clone()])
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_step_2x3v_one_species(dtype):
     """Electrons alone (the fluid kernels launched for a set of one species
     inside the step), three steps with moment fitting against the oracle."""
