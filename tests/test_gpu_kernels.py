@@ -182,6 +182,16 @@ def test_moments_3v(dtype):
         ref = OM.raw_moments_3v(f, v, dv, sp["m"])
         got = host(mom, ref.shape)
         assert _mom_groups_err(got, ref, 3, vscale=sp["v_hi"][0]) < 1e-13   # FP64 sums of the same stored values
+        # 12^3 FP32 cells are read in 16-byte pieces (50 cells: a partial last
+        # workgroup of four); an f that is not 16-byte aligned takes the
+        # plane-piece kernel: the same sums in the same order
+        fd = dev(f, dtype).reshape(-1)
+        shifted = torch.empty(fd.numel() + 1, dtype=fd.dtype, device="cuda")
+        shifted[1:] = fd
+        mom2 = torch.empty_like(mom)
+        ctx.moments(s, shifted[1:], mom2)
+        ctx.sync()
+        assert torch.equal(mom2, mom)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
