@@ -88,7 +88,10 @@ def test_integer_shift_is_bitwise_exact(dtype):
                                           (37, 41, 6, 2.3), (8, 20, 8, 0.05),
                                           # two y segments of the doubled pencil (2*ny > 128),
                                           # the last one short
-                                          (37, 75, 6, 2.3)])
+                                          (37, 75, 6, 2.3),
+                                          # 34^3 blocks: 16 (FP32) / 8 (FP64) columns per lane,
+                                          # ragged last strip
+                                          (37, 3, 34, 2.3)])
 def test_x_sweep_2x3v(dtype, nx, ny, nv, tau):
     import torch
     cfg, _, _ = W.gem(nx=nx, ny=ny, nv=nv, dtype=np.float64)
