@@ -434,6 +434,9 @@ moments3_staged_kernel(const float* __restrict__ f, double* __restrict__ mom, lo
 // Large cubic blocks (a cell's pencils do not fit one wave's registers): one
 // block per cell; thread t sums the v_x pencils at transverse positions
 // t, t + NTH, ... one pencil at a time, then a block reduction of the 20 sums.
+// A 34^3 v_x plane is not a whole number of lines (4624 B in FP32), so the
+// loads are ordinary and the caches merge the lines two wave accesses share
+// (938 -> 839 us per 256x128x34^3 FP32 launch against non-temporal loads).
 template <class T, int N, int NTH>
 __global__ void __launch_bounds__(NTH)
 moments3_big_kernel(const T* __restrict__ f, double* __restrict__ mom, VGrid G, XTable X) {
@@ -447,7 +450,7 @@ moments3_big_kernel(const T* __restrict__ f, double* __restrict__ mom, VGrid G, 
     for (int t = threadIdx.x; t < N * N; t += NTH) {
         T fv[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) fv[k] = __builtin_nontemporal_load(src + t + k * N * N);
+        for (int k = 0; k < N; ++k) fv[k] = ld_f<kRowsWholeLines<T, N>>(src + t + k * N * N);
         double Se[4] = {0.0, 0.0, 0.0, 0.0}, So[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -703,6 +706,9 @@ fit3_cube_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double* _
 // the cells in FP32) each thread reads back the values it stored, which are
 // mostly still in L2, and rescales them.  No 157 KB (FP32) or 314 KB (FP64)
 // cell is held in registers or shared memory, so several cells share a CU.
+// The loads are ordinary too: a 34^3 v_x plane is not a whole number of
+// lines, and the caches merge the lines two wave accesses share (FP32: 2.82
+// -> 2.47 ms per 256x128x34^3 launch; FP64 unchanged).
 // The arithmetic is fit3_cube_kernel's (pencil sums of the samples in four
 // chains in FP32, two in FP64; samples computed again in the exchange).
 template <class T, int N, int NTH>
@@ -771,7 +777,7 @@ fit3_stream_kernel(const T* fin, T* fout, const FitCell* __restrict__ P, double*
         const unsigned po = (unsigned)t * sizeof(T);
         T g[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) g[k] = a ? buf_ld(rs, po, k * XB, T()) : T(0);
+        for (int k = 0; k < N; ++k) g[k] = a ? buf_ld<kBufCached>(rs, po, k * XB, T()) : T(0);
         if (ok) {
             QuadX<T> qv, qf;
             qv.set(C.aV, C.uV, vc(G, 1, t / N), vc(G, 2, t % N));
