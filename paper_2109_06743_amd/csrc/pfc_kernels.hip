@@ -1490,7 +1490,8 @@ hipError_t launch_pfc_v3(const T* fin, T* fout, long long cells, const double* E
     return finish_max<T>(max_out, part, cells, st);
 }
 
-// V(tau) by the backsubstitution split (any grid with every axis <= 32).
+// V(tau) by the backsubstitution split (any grid with every axis <= 32, and
+// the 34^3 cube in FP32, whose padded block, 158 KB, fills one CU's LDS).
 template <class T>
 hipError_t launch_pfc_v3b(const T* fin, T* fout, long long cells, const double* E, const double* B,
                           const V3Params& P, const void* finf, void* max_out, void* part, hipStream_t st) {
@@ -1504,8 +1505,13 @@ hipError_t launch_pfc_v3b(const T* fin, T* fout, long long cells, const double* 
         hipLaunchKernelGGL((pfc_v3b_kernel<T, 16>), grid, dim3(256), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
     else if (nmax <= 32)
         hipLaunchKernelGGL((pfc_v3b_kernel<T, 32>), grid, dim3(256), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
-    else
+    else if constexpr (sizeof(T) == 4) {
+        if (nmax > kBigCube || shm > 160 * 1024) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((pfc_v3b_kernel<T, kBigCube>), grid, dim3(256), shm, st, fin, fout, E, B, P,
+                           (const T*)finf, mo);
+    } else {
         return hipErrorInvalidValue;
+    }
     return finish_max<T>(max_out, part, cells, st);
 }
 

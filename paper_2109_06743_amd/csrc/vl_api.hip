@@ -685,7 +685,9 @@ vl_status vl_create(const vl_config* cfg, vl_ctx** out) {
             // the 34^3 cube has its own kernels (FP32: the block fills one CU's
             // LDS; FP64: half the block at a time)
             const bool big = sp.nv[0] == vl::kBigCube && sp.nv[1] == vl::kBigCube && sp.nv[2] == vl::kBigCube;
-            if (big && c.vsplit == VL_VSPLIT_BACKSUB) return VL_ENOTSUP;   // the affine sweeps: axes <= 32
+            // the affine sweeps hold the whole block in LDS: axes <= 32, or the
+            // 34^3 cube in FP32 (158 KB padded)
+            if (big && c.vsplit == VL_VSPLIT_BACKSUB && elem != 4) return VL_ENOTSUP;
             for (int d = 0; d < 3 && !big; ++d)
                 if (sp.nv[d] > 32) return VL_ENOTSUP;
             if (!big && (long long)sp.nv[0] * sp.nv[1] * sp.nv[2] > 8192) return VL_ENOTSUP;

@@ -107,8 +107,11 @@ def test_cube34_grids(lib):
         st, h = _create(cfg, dt)
         assert st == 0
         lib.vl_destroy(h)
+    st, h = _create(dict(cfg, vsplit="backsub"), "f32")
+    assert st == 0                                  # the FP32 block fills one CU's LDS
+    lib.vl_destroy(h)
     st, h = _create(dict(cfg, vsplit="backsub"), "f64")
-    assert st == 3                                  # the affine sweeps take axes <= 32
+    assert st == 3                                  # the FP64 block does not fit the LDS
     cfg["species"][0]["nv"] = [34, 34, 33]           # non-cubic beyond the generic limits
     st, h = _create(cfg, "f32")
     assert st == 3

@@ -5,7 +5,8 @@ oracle.step with cfg["vsplit"] = "backsub") on the same seeded inputs.
 
 * V per call on 8^3, 12^3 and 16^3 blocks and a non-cubic 8 x 12 x 10 block,
   several field strengths (|Omega| tau up to about 1): rel-L2 <= 3e-6 (FP32
-  storage and arithmetic) / 1e-13 (FP64), per-cell mass to rounding;
+  storage and arithmetic) / 1e-13 (FP64), per-cell mass to rounding; 34^3
+  blocks in FP32;
 * B = 0 with whole-cell shifts: f moves exactly (FP32, where the shift
   rounds to whole cells; FP64 to the rounding of the shift);
 * full moment-fitting steps (GEM set-up 8x4x8^3 and 12x6x12^3): f within the
@@ -72,6 +73,33 @@ def test_v_backsub_3v(dtype, nv, fscale):
         assert rel_l2(got, ref) < TOL_V[dtype], (s, rel_l2(got, ref))
         assert (got >= 0).all()
         np.testing.assert_allclose(got.sum((2, 3, 4)), f.sum((2, 3, 4)), rtol=1e-6 if dtype == "f32" else 1e-13)
+
+
+@pytest.mark.parametrize("fscale", [0.5, 3.0])
+def test_v_backsub_34_f32(fscale):
+    """34^3 blocks in FP32 (the padded block fills one CU's LDS)."""
+    import torch
+    from paper_2109_06743_amd import vl
+    nx, ny = 3, 2
+    cfg, _, _ = _gem(nx, ny, 8)
+    cfg["species"] = [dict(sp, nv=[34, 34, 34]) for sp in cfg["species"]]
+    ctx = vl.Context(cfg, "f32")
+    rng = np.random.default_rng(34)
+    E = fscale * rng.normal(size=(ny, nx, 3))
+    B = fscale * rng.normal(size=(ny, nx, 3))
+    tau = 0.01
+    for s, sp in enumerate(cfg["species"]):
+        f = storage_round(W.random_block((ny, nx, 34, 34, 34), seed=50 + s, kind="smooth"), "f32")
+        fin = dev(f, "f32")
+        fout = torch.empty_like(fin)
+        ctx.pfc_advect_v(s, fin, fout, dev(E, "f64"), dev(B, "f64"), tau)
+        ctx.sync()
+        v, dv = _grid3(sp)
+        ref = OV.v_advect_3v_backsub(f, E, B, sp["q"], sp["m"], v, dv, tau)
+        got = host(fout, ref.shape)
+        assert rel_l2(got, ref) < TOL_V["f32"], (s, rel_l2(got, ref))
+        assert (got >= 0).all()
+        np.testing.assert_allclose(got.sum((2, 3, 4)), f.sum((2, 3, 4)), rtol=1e-6)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])

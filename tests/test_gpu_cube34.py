@@ -110,10 +110,14 @@ def test_moments_and_fit_34(gem34, dtype):
                     assert np.linalg.norm(gotp[j, i] - mp) / np.linalg.norm(mp) < 1e-12, (s, j, i)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_step_34(gem34, dtype):
+@pytest.mark.parametrize("dtype,vsplit", [("f32", "strang"), ("f64", "strang"), ("f32", "backsub")])
+def test_step_34(gem34, dtype, vsplit):
+    """Two full steps against the oracle; FP32 also with the backsubstitution
+    velocity split (34^3 blocks: FP32 only)."""
     from paper_2109_06743_amd import vl
     cfg, f, F0 = gem34
+    if vsplit == "backsub":
+        cfg = dict(cfg, vsplit="backsub")
     nx, ny = cfg["nx"], cfg["ny"]
     F = OF.Yee(nx, ny)
     for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
@@ -129,7 +133,7 @@ def test_step_34(gem34, dtype):
     st = vl.StepState(ctx, f, vl.yee_pack(F), U_list=Us, mom_post_list=moms)
     ref = dict(f=f, U=[u.copy() for u in Us], mom_post=moms, F=F)
     for k in range(2):
-        print(f"step {k} {dtype}", flush=True)
+        print(f"step {k} {dtype} {vsplit}", flush=True)
         ctx.step(st, cfg["dt"])
         ref = OS.step_2x3v(ref, cfg, cfg["dt"])
         ctx.sync()
