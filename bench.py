@@ -686,7 +686,7 @@ def measure(name, args, fp64=True, built=None, backsub=True):
                        "energy_rel_drift": {"f32": half["f32"]["energy_rel_drift"], "f64": half["f64"]["energy_rel_drift"],
                                             "steps": half["f64"]["steps_run"]},
                        "mass_rel_drift": {"f32": half["f32"]["mass_rel_drift"], "f64": half["f64"]["mass_rel_drift"]}}
-    if backsub and name not in ("gem34", "ot"):             # the affine sweeps take axes <= 32
+    if backsub:             # 34^3 blocks: FP32 (the affine sweeps hold the block in LDS)
         rb = run_gpu(dict(cfg, vsplit="backsub"), f, F, "f32", args.steps, args.warmup)
         log(f"{name} fp32 backsubstitution split: {rb['ms']:.3f} ms/step")
         vb, va = rb["breakdown"]["pfc_v"], r32["breakdown"]["pfc_v"]
