@@ -277,6 +277,34 @@ def test_moment_fit_3v(dtype, nv):
         np.testing.assert_allclose(got.sum((2, 3, 4)) * dV, mom[..., 0], rtol=2e-6 if dtype == "f32" else 1e-13)
 
 
+def test_moment_fit_counts_many_cells():
+    """Clip and skip counts over 128 x 72 cells (9216 per-cell partials: the
+    sum runs in two launches) equal the oracle's (FP64: the clip decisions
+    are the oracle's), and the fitted f matches."""
+    import torch
+    nx, ny = 128, 72
+    cfg, f0, _ = W.gem(nx=nx, ny=ny, nv=8, dtype=np.float64)
+    ctx = _ctx(cfg, "f64")
+    sp = cfg["species"][0]
+    v, dv = _grid3(sp)
+    vt = math.sqrt(0.5 / sp["m"]) * 0.3
+    f = f0[0] * (1 + 0.3 * W.random_block(f0[0].shape, seed=44, kind="rough"))
+    mom = OM.raw_moments_3v(f, v, dv, sp["m"])
+    U = _fluid_from(mom, sp["m"], np.array([0.3, -0.2, 0.1]) * vt, 1.1, 3)
+    U[5, 7, 4] = -1.0                                   # two skipped cells
+    U[60, 100, 4] = -1.0
+    ref_f, ref_U, ref_clip, ref_skip = OM.moment_fit_3v(f, mom, U, sp["m"], v, dv)
+    fin = dev(f, "f64")
+    fout = torch.empty_like(fin)
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ctx.moment_fit(0, fin, fout, dev(mom, "f64"), dev(U, "f64"), None, cnt)
+    ctx.sync()
+    c = cnt.cpu().numpy()
+    assert ref_clip > 10000
+    assert c[0] == ref_clip and c[1] == ref_skip == 2
+    assert rel_l2(host(fout, ref_f.shape), ref_f) < TOL_SWEEP["f64"] * 3
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_moment_fit_1v(dtype):
     import torch
