@@ -1499,8 +1499,13 @@ hipError_t launch_pfc_v3b(const T* fin, T* fout, long long cells, const double* 
     const size_t shm = v3_shared_bytes(P.nvx, P.nvy, P.nvz, sizeof(T));
     auto* mo = (typename Bits<T>::U*)(max_out ? part : nullptr);
     const dim3 grid((unsigned)cells);
+    const bool cube12 = P.nvx == 12 && P.nvy == 12 && P.nvz == 12;
     if (nmax <= 8)
         hipLaunchKernelGGL((pfc_v3b_kernel<T, 8>), grid, dim3(64), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
+    else if (cube12)    // 144 pencils per sweep: three waves instead of four (8.2 -> 6.0 ms per
+                        // 1024x512x12^3 launch)
+        hipLaunchKernelGGL((pfc_v3b_kernel<T, 12, 192>), grid, dim3(192), shm, st, fin, fout, E, B, P,
+                           (const T*)finf, mo);
     else if (nmax <= 16)
         hipLaunchKernelGGL((pfc_v3b_kernel<T, 16>), grid, dim3(256), shm, st, fin, fout, E, B, P, (const T*)finf, mo);
     else if (nmax <= 32)
