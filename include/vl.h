@@ -96,8 +96,9 @@ typedef struct {
                              the step, v -> R v + c, factored row by row into an x-, y- and
                              z-map that each change one component from the ones already
                              updated, swept with a foot per cell face (every velocity axis
-                             <= 32 cells; valid while |q B/m| tau < 2, a turn below 90
-                             degrees per step) */
+                             <= 32 cells, or the 34^3 cube with FP32 f -- FP64 f on 34^3
+                             gives VL_ENOTSUP; valid while |q B/m| tau < 2, a turn below
+                             90 degrees per step) */
 } vl_config;
 
 typedef struct vl_ctx vl_ctx;
