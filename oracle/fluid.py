@@ -119,10 +119,12 @@ def _source_3v(U, E, B, q, m):
 
 
 def _pad(arr, axis, bc, parity):
-    """Two ghost cells on each side of `axis` (0 = y, 1 = x)."""
+    """Two ghost cells on each side of `axis` (0 = y, 1 = x).  Periodic
+    ghosts are the cells of index mod n, also where the axis has fewer cells
+    than ghosts (n = 1)."""
     if bc == "periodic":
-        return np.concatenate([np.take(arr, [-2, -1], axis=axis), arr,
-                               np.take(arr, [0, 1], axis=axis)], axis=axis)
+        return np.concatenate([np.take(arr, [-2, -1], axis=axis, mode="wrap"), arr,
+                               np.take(arr, [0, 1], axis=axis, mode="wrap")], axis=axis)
     lo = np.take(arr, [1, 0], axis=axis) * parity
     hi = np.take(arr, [-1, -2], axis=axis) * parity
     return np.concatenate([lo, arr, hi], axis=axis)

@@ -300,3 +300,28 @@ def test_cold_advection_between_reflecting_walls():
     r1, r2 = e[0] / e[1], e[1] / e[2]
     assert (r1[even] > 5.0).all() and (r2[even] > 5.0).all(), (e, r1, r2)
     assert (e[:, odd] == 0.0).all(), e[:, odd]
+
+
+@pytest.mark.parametrize("bc_y", ["reflect", "periodic"])
+def test_one_cell_periodic_axis_equals_x_uniform_grid(bc_y):
+    """Periodic ghosts are the cells of index mod nx: with one cell along x
+    every ghost is that cell, so the RK3 step of an nx = 1 grid is the step of
+    any x-uniform state on a wider grid, column by column (the x fluxes of a
+    uniform row cancel exactly)."""
+    rng = np.random.default_rng(21)
+    ny, m = 6, 0.6
+    U = _uniform_state(ny, 1, 1.0, [0, 0, 0], np.eye(3) * 0.5, m)
+    U[..., 0] *= 1 + 0.2 * rng.uniform(-1, 1, size=(ny, 1))
+    U[..., 1:4] = 0.1 * rng.uniform(-1, 1, size=(ny, 1, 3))
+    for k, (a, b) in enumerate(PAIRS):
+        U[..., 4 + k] = U[..., 0] * (0.5 if a == b else 0.05) + m * U[..., 1 + a] * U[..., 1 + b] / U[..., 0]
+    Q = 0.05 * rng.uniform(-1, 1, size=(ny, 1, 10))
+    E = [0.1 * rng.uniform(-1, 1, size=(ny, 1, 3)) for _ in range(3)]
+    B = [rng.uniform(-1, 1, size=(ny, 1, 3)) for _ in range(3)]
+    wide = lambda a: np.repeat(a, 5, axis=1)
+    one = fluid.rk3_3v(U, Q, Q, (E[0], B[0]), (E[1], B[1]), (E[2], B[2]), -1.0, m, 0.3, 0.4, 0.01, bc_y=bc_y)
+    five = fluid.rk3_3v(wide(U), wide(Q), wide(Q), (wide(E[0]), wide(B[0])), (wide(E[1]), wide(B[1])),
+                        (wide(E[2]), wide(B[2])), -1.0, m, 0.3, 0.4, 0.01, bc_y=bc_y)
+    assert np.abs(one - U).max() > 1e-4                 # the step does change the state
+    for i in range(5):
+        np.testing.assert_array_equal(five[:, i:i + 1], one)
