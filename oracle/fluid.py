@@ -193,9 +193,10 @@ def rhs_1v(U, Qc, E, q, m, dx):
     S = np.zeros_like(U)
     S[:, 1] = (q / m) * n_ * E
     S[:, 2] = 2.0 * q * nu * E
-    Ug = np.concatenate([U[-2:], U, U[:2]], axis=0)
-    Qg = np.concatenate([Qc[-2:], Qc, Qc[:2]])
     N = U.shape[0]
+    ring = np.arange(-2, N + 2)                  # two ghosts each side, cell index mod N
+    Ug = np.take(U, ring, axis=0, mode="wrap")
+    Qg = np.take(Qc, ring, mode="wrap")
     UL, UR = cweno_faces(Ug[0:N + 2], Ug[1:N + 3], Ug[2:N + 4])
     QL, QR = cweno_faces(Qg[0:N + 2], Qg[1:N + 3], Qg[2:N + 4])
     Um, Up = UR[0:N + 1], UL[1:N + 2]

@@ -325,3 +325,16 @@ def test_one_cell_periodic_axis_equals_x_uniform_grid(bc_y):
     assert np.abs(one - U).max() > 1e-4                 # the step does change the state
     for i in range(5):
         np.testing.assert_array_equal(five[:, i:i + 1], one)
+
+
+def test_one_cell_periodic_axis_equals_uniform_grid_1v():
+    """The 1V fluid step on one periodic cell is the step of the same uniform
+    state on a wider grid, cell by cell."""
+    U = np.array([[1.1, 0.2, 0.7]])
+    Q, E = np.array([0.03]), np.array([0.4])
+    one = fluid.rk3_1v(U, Q, Q, E, E, -1.0, 1.0, 0.3, 0.01)
+    four = fluid.rk3_1v(np.repeat(U, 4, axis=0), np.repeat(Q, 4), np.repeat(Q, 4), np.repeat(E, 4),
+                        np.repeat(E, 4), -1.0, 1.0, 0.3, 0.01)
+    assert np.abs(one - U).max() > 1e-4
+    for i in range(4):
+        np.testing.assert_array_equal(four[i:i + 1], one)
