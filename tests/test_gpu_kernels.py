@@ -157,6 +157,36 @@ def test_v_sweep_3v(dtype, nv, fscale):
         np.testing.assert_allclose(got.sum((2, 3, 4)), f.sum((2, 3, 4)), rtol=1e-6 if dtype == "f32" else 1e-13)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("nv", [(2, 2, 2), (2, 5, 3), (10, 10, 10), (8, 12, 10), (20, 6, 32), (32, 16, 4)])
+def test_v_sweep_3v_general_blocks(dtype, nv):
+    """Blocks without a kernel of their own (not 8^3, 12^3, 16^3 or 34^3): the
+    general operator with run-time pencil lengths, from the shortest pencil
+    the library accepts (2) to the longest (32), several pencil lengths in one
+    block, and shifts of several cells (|E|, |B| up to about 3)."""
+    import torch
+    nx, ny = 5, 3
+    cfg, _, _ = W.gem(nx=nx, ny=ny, nv=8, dtype=np.float64)
+    cfg["species"] = [dict(sp, nv=list(nv)) for sp in cfg["species"]]
+    ctx = _ctx(cfg, dtype)
+    rng = np.random.default_rng(sum(nv))
+    E = 1.5 * rng.normal(size=(ny, nx, 3))
+    B = 1.5 * rng.normal(size=(ny, nx, 3))
+    tau = 0.05
+    for s, sp in enumerate(cfg["species"]):
+        f = storage_round(W.random_block((ny, nx) + nv, seed=60 + s, kind="smooth"), dtype)
+        fin = dev(f, dtype)
+        fout = torch.empty_like(fin)
+        ctx.pfc_advect_v(s, fin, fout, dev(E, "f64"), dev(B, "f64"), tau)
+        ctx.sync()
+        v, dv = _grid3(sp)
+        ref = OV.v_advect_3v(f, E, B, sp["q"], sp["m"], v, dv, tau)
+        got = host(fout, ref.shape)
+        assert rel_l2(got, ref) < TOL_SWEEP[dtype] * 3, s
+        assert (got >= 0).all()
+        np.testing.assert_allclose(got.sum((2, 3, 4)), f.sum((2, 3, 4)), rtol=1e-6 if dtype == "f32" else 1e-13)
+
+
 # ----------------------------------------------------------------- moments --
 def _mom_groups_err(got, ref, kind, vscale=1.0):
     """Max over moment groups (n, M1, P, Q) of the relative L2 error, each group's

@@ -161,6 +161,40 @@ def test_step_2x3v_degenerate_grids(dtype, fit, nx, ny):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("nv", [(8, 12, 10), (6, 4, 20)])
+def test_step_2x3v_general_blocks(dtype, nv):
+    """Non-cubic velocity blocks (the general V operator, moments and fit
+    kernels) through full moment-fitting steps on a 10 x 6 grid."""
+    from paper_2109_06743_amd import vl
+    nx, ny = 10, 6
+    cfg, f, F0 = W.gem(nx=nx, ny=ny, nv=8, dt=0.003, fit=True, dtype=np.float64)
+    cfg["species"] = [dict(sp, nv=list(nv)) for sp in cfg["species"]]
+    f = []
+    for sp in cfg["species"]:
+        v, dv = OS._grids(cfg, sp)
+        u = np.zeros((ny, nx, 3))
+        u[..., 2] = 0.05 * sp["v_hi"][2]
+        # thermal speed sqrt(T/m) about a third of the velocity box
+        T = np.broadcast_to(np.eye(3) * (0.12 * sp["m"] * sp["v_hi"][0] ** 2), (ny, nx, 3, 3))
+        n = 1.0 + 0.1 * np.cos(2 * np.pi * (np.arange(nx) + 0.5) / nx)[None, :] * np.ones((ny, 1))
+        f.append(np.stack([np.stack([OM.maxwellian_3v(n[j, i], u[j, i], T[j, i], sp["m"], v, dv)
+                                     for i in range(nx)]) for j in range(ny)]))
+    ctx, st, ref = _start_2x3v(cfg, f, F0, dtype)
+    for k in range(3):
+        ctx.step(st, cfg["dt"])
+        ref = OS.step_2x3v(ref, cfg, cfg["dt"])
+        ctx.sync()
+        for s in range(2):
+            got = host(st.f[s], ref["f"][s].shape)
+            assert rel_l2(got, ref["f"][s]) < TOL_STEP[dtype] * (k + 1), (k, s)
+            assert rel_l2(host(st.U[s], ref["U"][s].shape), ref["U"][s]) < (1e-5 if dtype == "f32" else 1e-12)
+        yee = vl.yee_unpack(host(st.fields), nx, ny)
+        for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+            np.testing.assert_allclose(yee[c], getattr(ref["F"], c), rtol=0,
+                                       atol=(1e-6 if dtype == "f32" else 1e-12), err_msg=c)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_step_conserves_mass_and_is_deterministic(dtype):
     import torch
     from paper_2109_06743_amd import vl
