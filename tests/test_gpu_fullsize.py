@@ -5,6 +5,8 @@ time: GEM 256x128 x 16^3 (the headline workload) and the magnetotail-like
 recomputes a seeded sample of pencils (X: whole reflecting y pencil pairs of
 the x-then-y-swept output) and spatial cells (V, moments, fitting) from the
 same inputs."""
+import math
+
 import numpy as np
 import pytest
 
@@ -160,3 +162,62 @@ def test_moments_and_fit_sampled(case):
         got = fout[j, i].double().cpu().numpy()
         assert rel_l2(got, ref) < 1e-5, (name, j, i)
         assert abs(got.sum() * np.prod(dv) - m_ref[0]) <= 1e-6 * m_ref[0]
+
+
+def test_x_operator_wide_store_window():
+    """The fused X operator's variant with 64-bit store addresses: the stores
+    of one step span rows i-2-Kmax .. i-1+Kmax, and where those rows hold
+    4 GiB or more the kernel addresses them per lane in 64 bits.  Here a
+    2048 x 32 grid of 16^3 FP32 blocks (33.5 MB per row) with y shifts up to
+    66 cells (longer than the doubled 64-cell pencil) spans 129 rows, 4.33 GB.
+    Sampled reflecting pencil pairs against the oracle, as above."""
+    import torch
+    from gpu_util import ensure_lib
+    from paper_2109_06743_amd import vl
+    ensure_lib()
+    nx, ny, nv = 2048, 32, 16
+    cfg, _, _ = W.gem(nx=8, ny=4, nv=nv, dtype=np.float64)
+    cfg = dict(cfg, nx=nx, ny=ny, x_lo=0.0, x_hi=float(nx), y_lo=0.0, y_hi=float(ny))
+    vmax = [0.1, 10.0, 1.0]                  # sub-cell x shifts, y shifts of many cells
+    cfg["species"] = [dict(sp, nv=[nv] * 3, v_lo=[-w for w in vmax], v_hi=list(vmax)) for sp in cfg["species"]]
+    tau = 7.0
+    # the launcher's choice (whole-cell y shift bound, rows a step's stores span)
+    kd = math.floor(vmax[1] * tau) + 1
+    kb = min(kd, 2 * ny - 1)
+    assert (2 * kb + 3) * nx * nv ** 3 * 4 >= 2 ** 32
+    ctx = vl.Context(cfg, "f32")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    dev = torch.device("cuda")
+    ax = torch.arange(nv, device=dev, dtype=torch.float32)
+    prof = torch.exp(-0.5 * ((ax - 7.5) / 4.0) ** 2)
+    blk = prof[:, None, None] * prof[None, :, None] * prof[None, None, :]
+    xi = torch.arange(nx, device=dev, dtype=torch.float32)
+    yj = torch.arange(ny, device=dev, dtype=torch.float32)
+    mod = 1.0 + 0.3 * torch.sin(2 * math.pi * xi[None, :] / nx + 0.4 * yj[:, None])
+    f = (mod[:, :, None, None, None] * blk).contiguous()
+    f.mul_(torch.rand(f.shape, device=dev, generator=g).mul_(0.5).add_(0.75))
+    fout = torch.empty_like(f)
+    print("wide X launch", flush=True)
+    ctx.pfc_advect_x(0, f, fout, tau)
+    ctx.sync()
+    finf = float(f.max().item())
+    v, _ = _grid(cfg["species"][0])
+    rng = np.random.default_rng(13)
+    for _ in range(8):
+        i = int(rng.integers(nx))
+        a, c = int(rng.integers(nv)), int(rng.integers(nv))
+        jy = int(rng.integers(nv // 2, nv))
+        jm = nv - 1 - jy
+        cols = []
+        for jv in (jy, jm):
+            pen = f[:, :, a, jv, c].double().cpu().numpy()
+            xs = OP.pfc_sweep(pen, np.full(ny, v[0][a] * tau), "periodic", finf)
+            cols.append(xs[:, i])
+        up, dn = OP.pfc_sweep_reflect_pair(cols[0][None], cols[1][None], np.array([v[1][jy] * tau]), finf)
+        got_up = fout[:, i, a, jy, c].double().cpu().numpy()
+        got_dn = fout[:, i, a, jm, c].double().cpu().numpy()
+        assert rel_l2(got_up, up[0]) < 2 * TOL_SWEEP["f32"], (i, a, jy, c)
+        assert rel_l2(got_dn, dn[0]) < 2 * TOL_SWEEP["f32"], (i, a, jm, c)
+    del f, fout
+    torch.cuda.empty_cache()
