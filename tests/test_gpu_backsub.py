@@ -3,8 +3,9 @@ VL_VSPLIT_BACKSUB; Sec. 2.1 names the method): the V operator per call and
 the full step against the oracle (oracle.vlasov.v_advect_3v_backsub, and
 oracle.step with cfg["vsplit"] = "backsub") on the same seeded inputs.
 
-* V per call on 8^3, 12^3 and 16^3 blocks and a non-cubic 8 x 12 x 10 block,
-  several field strengths (|Omega| tau up to about 1): rel-L2 <= 3e-6 (FP32
+* V per call on 8^3, 12^3 and 16^3 blocks and non-cubic 8 x 12 x 10, 2 x 5 x 3
+  (the shortest pencils) and 20 x 6 x 32 (the longest) blocks, several field
+  strengths (|Omega| tau up to about 1): rel-L2 <= 3e-6 (FP32
   storage and arithmetic) / 1e-13 (FP64), per-cell mass to rounding; 34^3
   blocks in FP32;
 * B = 0 with whole-cell shifts: f moves exactly (FP32, where the shift
@@ -49,7 +50,8 @@ def _gem(nx, ny, nv):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("nv,fscale", [(8, 1.0), (16, 0.3), (12, 2.0), ((8, 12, 10), 1.0)])
+@pytest.mark.parametrize("nv,fscale", [(8, 1.0), (16, 0.3), (12, 2.0), ((8, 12, 10), 1.0), ((2, 5, 3), 1.0),
+                                       ((20, 6, 32), 1.0)])
 def test_v_backsub_3v(dtype, nv, fscale):
     import torch
     from paper_2109_06743_amd import vl
