@@ -59,8 +59,13 @@ def _maxwellian_block(n, uz, T, m, v):
     return pre[..., None, None, None] * ex * ez[..., None, None, :]
 
 
+def _vgrid_name(nv):
+    return f"{nv}^3" if np.isscalar(nv) else "x".join(str(k) for k in nv)
+
+
 def _species(q, m, vmax, nv):
-    return dict(q=q, m=m, v_lo=[-vmax] * 3, v_hi=[vmax] * 3, nv=[nv] * 3)
+    """nv: cells per velocity axis, one number (a cube) or three."""
+    return dict(q=q, m=m, v_lo=[-vmax] * 3, v_hi=[vmax] * 3, nv=[nv] * 3 if np.isscalar(nv) else list(nv))
 
 
 class Yee0:
@@ -80,7 +85,7 @@ def _gem_setup(nx, ny, nv, mass_ratio, c, lam, nb, Ti_Te, psi0, ve_max, vi_max, 
     sp = [_species(-1.0, me, ve_max, nv), _species(1.0, 1.0, vi_max, nv)]
     cfg = dict(kind="2x3v", nx=nx, ny=ny, x_lo=-Lx / 2, x_hi=Lx / 2, y_lo=-Ly / 2, y_hi=Ly / 2,
                c=c, species=sp, fit=fit, dt=dt, steps=steps,
-               name=f"gem {nx}x{ny}x{nv}^3 mi/me={mass_ratio:g}")
+               name=f"gem {nx}x{ny}x{_vgrid_name(nv)} mi/me={mass_ratio:g}")
     x = _centres(-Lx / 2, Lx / 2, nx)
     y = _centres(-Ly / 2, Ly / 2, ny)
     X, Y = np.meshgrid(x, y)          # [ny, nx]
@@ -105,7 +110,8 @@ def _gem_setup(nx, ny, nv, mass_ratio, c, lam, nb, Ti_Te, psi0, ve_max, vi_max, 
 
 def gem(nx=256, ny=128, nv=16, mass_ratio=25.0, c=20.0, lam=0.5, nb=0.2, Ti_Te=5.0, psi0=0.1,
         ve_max=12.5, vi_max=5.0, dt=0.003, steps=200, fit=True, dtype=np.float32):
-    """GEM reconnection set-up (Sec. 3.3) on an nx x ny x nv^3 grid."""
+    """GEM reconnection set-up (Sec. 3.3) on an nx x ny x nv^3 grid (nv one
+    number, or three for a non-cubic velocity grid)."""
     cfg, n, prof, F = _gem_setup(nx, ny, nv, mass_ratio, c, lam, nb, Ti_Te, psi0, ve_max, vi_max, dt, steps, fit)
     f = []
     for s, (uz, T) in zip(cfg["species"], prof):

@@ -228,6 +228,25 @@ def test_moments_3v(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("nv", [(2, 5, 3), (20, 6, 16), (32, 16, 14)])
+def test_moments_3v_general_blocks(dtype, nv):
+    """Blocks without a kernel of their own: the general moments kernel (one
+    workgroup per cell, pencils along v_z) against the oracle's sums."""
+    import torch
+    nx, ny = 6, 4
+    cfg, f0, _ = W.gem(nx=nx, ny=ny, nv=nv, dtype=np.float64)
+    ctx = _ctx(cfg, dtype)
+    for s, sp in enumerate(cfg["species"]):
+        f = storage_round(f0[s] * (1 + 0.2 * W.random_block(f0[s].shape, seed=70 + s, kind="rough")), dtype)
+        mom = torch.empty(nx * ny * 20, dtype=torch.float64, device="cuda")
+        ctx.moments(s, dev(f, dtype), mom)
+        ctx.sync()
+        v, dv = _grid3(sp)
+        ref = OM.raw_moments_3v(f, v, dv, sp["m"])
+        assert _mom_groups_err(host(mom, ref.shape), ref, 3, vscale=sp["v_hi"][0]) < 1e-13
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_moments_1v(dtype):
     import torch
     cfg, f0 = W.twostream(nx=40, nv=96)
@@ -263,12 +282,13 @@ def _fluid_from(mom, m, du, tscale, kind):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("nv", [8, 16, 34])
+@pytest.mark.parametrize("nv", [8, 16, 34, (20, 6, 16), (32, 16, 8), (32, 16, 14)])
 def test_moment_fit_3v(dtype, nv):
     """Fit per cell against the oracle on rough data (clipping) with one
     skipped cell; 34^3 runs the streamed kernel (the cell is not held; cells
     whose density rescale is not one re-read and rescale their output, which
-    the per-cell density check below covers)."""
+    the per-cell density check below covers); the non-cubic blocks run the
+    general kernel with 8, 16 and 28 values per thread."""
     import torch
     nx, ny = 7, 3
     cfg, f0, _ = W.gem(nx=nx, ny=ny, nv=nv, dtype=np.float64)
