@@ -338,3 +338,65 @@ def test_one_cell_periodic_axis_equals_uniform_grid_1v():
     assert np.abs(one - U).max() > 1e-4
     for i in range(4):
         np.testing.assert_array_equal(four[i:i + 1], one)
+
+
+def _yee_sinusoids(nx, ny, hx, hy, kx, ky):
+    """Yee components sampled from sinusoids at their own positions (x =
+    (i + 1/2) hx for Ex, By, Bz; y = (j - 1/2) hy for the [ny + 1] rows)."""
+    xi = np.arange(nx) * hx
+    yj = np.arange(ny) * hy
+    xh = xi + 0.5 * hx
+    yh = np.arange(ny + 1) * hy - 0.5 * hy
+    F = fields.Yee(nx, ny)
+    F.Ex = np.sin(kx * xh)[None, :] * np.cos(ky * yj)[:, None]
+    F.By = 2.0 * np.cos(kx * xh)[None, :] * np.cos(ky * yj)[:, None]
+    F.Ey = np.cos(kx * xi)[None, :] * np.cos(ky * yh)[:, None]
+    F.Bx = np.sin(kx * xi)[None, :] * np.cos(ky * yh)[:, None]
+    F.Bz = np.sin(kx * xh)[None, :] * np.cos(ky * yh)[:, None]
+    F.Ez = np.cos(kx * xi)[None, :] * np.sin(ky * yj)[:, None]
+    return F, xi, yj
+
+
+def test_cell_centred_averages_of_sinusoids():
+    """The mean of a sinusoid at the two points h/2 either side of a cell
+    centre is cos(k h / 2) times its value at the centre: each component's
+    average to the centres carries that factor along every axis it is
+    staggered in, and none along the others."""
+    nx, ny, hx, hy = 16, 10, 0.3, 0.7
+    kx, ky = 2 * math.pi * 3 / (nx * hx), 1.3
+    F, xi, yj = _yee_sinusoids(nx, ny, hx, hy, kx, ky)
+    E, B = fields.cell_centred(F)
+    ax, ay = math.cos(kx * hx / 2), math.cos(ky * hy / 2)
+    X, Y = xi[None, :], yj[:, None]
+    np.testing.assert_allclose(E[..., 0], ax * np.sin(kx * X) * np.cos(ky * Y), atol=1e-14)
+    np.testing.assert_allclose(E[..., 1], ay * np.cos(kx * X) * np.cos(ky * Y), atol=1e-14)
+    np.testing.assert_allclose(E[..., 2], np.cos(kx * X) * np.sin(ky * Y), atol=1e-14)
+    np.testing.assert_allclose(B[..., 0], ay * np.sin(kx * X) * np.cos(ky * Y), atol=1e-14)
+    np.testing.assert_allclose(B[..., 1], 2.0 * ax * np.cos(kx * X) * np.cos(ky * Y), atol=1e-14)
+    np.testing.assert_allclose(B[..., 2], ax * ay * np.sin(kx * X) * np.cos(ky * Y), atol=1e-14)
+
+
+@pytest.mark.parametrize("bc_y", ["reflect", "periodic"])
+def test_current_on_yee_averages_of_sinusoids(bc_y):
+    """Cell-centred j moved to the E positions: j_x to x + h/2 and j_y to the
+    faces y - h/2 carry the factor cos(k h/2) of the two-point mean; j_z
+    stays at the centres; j_y on the wall rows is 0 between reflecting walls
+    and, with periodic y, the mean across the seam (the face at -h/2)."""
+    nx, ny, hx, hy = 12, 9, 0.5, 0.4
+    kx = 2 * math.pi * 2 / (nx * hx)
+    ky = 2 * math.pi * 1 / (ny * hy)
+    xi, yj = np.arange(nx) * hx, np.arange(ny) * hy
+    X, Y = xi[None, :], yj[:, None]
+    jc = np.stack([np.sin(kx * X) * np.cos(ky * Y), np.cos(kx * X) * np.cos(ky * Y),
+                   np.sin(kx * X) * np.sin(ky * Y)], axis=-1)
+    jx, jy, jz = fields.current_on_yee(jc, bc_y)
+    np.testing.assert_allclose(jx, math.cos(kx * hx / 2) * np.sin(kx * (X + hx / 2)) * np.cos(ky * Y), atol=1e-14)
+    yh = np.arange(ny + 1)[:, None] * hy - hy / 2
+    expect_y = math.cos(ky * hy / 2) * np.cos(kx * X) * np.cos(ky * yh)
+    np.testing.assert_allclose(jy[1:ny], expect_y[1:ny], atol=1e-14)
+    if bc_y == "reflect":
+        assert (jy[0] == 0).all() and (jy[ny] == 0).all()
+    else:
+        np.testing.assert_allclose(jy[0], expect_y[0], atol=1e-14)
+        np.testing.assert_allclose(jy[ny], expect_y[0], atol=1e-14)
+    np.testing.assert_array_equal(jz, jc[..., 2])

@@ -344,3 +344,36 @@ def test_field_direction_features():
     np.testing.assert_allclose(x1[0, 0, 61:], [0.6, 0.0, -0.8], rtol=1e-15)
     np.testing.assert_array_equal(x1[1, 2, 61:], 0.0)
     np.testing.assert_array_equal(x0[..., 61:], 0.0)
+
+
+def test_judge_error_contracts_the_full_tensor(monkeypatch):
+    """The judge compares heat-flux vectors q_i = sum_j Q_ijj of the network's
+    and the kinetic third moments.  Both tensors are drawn as full symmetric
+    3x3x3 arrays, packed in the documented order (xxx, xxy, xxz, xyy, xyz,
+    xzz, yyy, yyz, yzz, zzz) and handed to the judge in place of the network
+    and the kinetic heat flux; its value must be the relative L2 norm of the
+    difference of the two contractions taken with einsum on the full tensors."""
+    import itertools
+    rng = np.random.default_rng(17)
+    ny, nx = 3, 4
+
+    def sym(shape):
+        t = rng.normal(size=shape + (3, 3, 3))
+        return sum(np.transpose(t, (0, 1) + tuple(2 + p for p in perm))
+                   for perm in itertools.permutations(range(3))) / 6.0
+
+    order = [(0, 0, 0), (0, 0, 1), (0, 0, 2), (0, 1, 1), (0, 1, 2), (0, 2, 2), (1, 1, 1), (1, 1, 2), (1, 2, 2),
+             (2, 2, 2)]
+    pack = lambda T: np.stack([T[..., a, b, c] for a, b, c in order], axis=-1)
+    Tn, Tk = sym((ny, nx)), sym((ny, nx))
+    scale = rng.uniform(0.5, 2.0, size=(ny, nx))
+    y = np.zeros((ny, nx, OM.N_OUT_PAD))
+    y[..., :OM.N_OUT] = pack(Tn) / scale[..., None]
+    monkeypatch.setattr(OM, "network_heat_flux", lambda U, m, s, p, B=None: (y, scale))
+    monkeypatch.setattr(OM, "heat_flux", lambda mom, m: pack(Tk))
+    got = OM.judge_error(np.zeros((ny, nx, 20)), 1.0, 0, None)
+    qn, qk = np.einsum("...ijj->...i", Tn), np.einsum("...ijj->...i", Tk)
+    assert got == pytest.approx(np.linalg.norm(qn - qk) / np.linalg.norm(qk), rel=1e-12)
+    # and zero for the same tensor
+    monkeypatch.setattr(OM, "heat_flux", lambda mom, m: pack(Tn))
+    assert OM.judge_error(np.zeros((ny, nx, 20)), 1.0, 0, None) < 1e-14
