@@ -212,7 +212,12 @@ vl_status vl_fluid_step(vl_ctx* ctx, int32_t s, double* U, const double* mom_t, 
  * fitting (standard PFC step, mom_post = mom_pre).
  * f_max_valid: host flag; 0 tells the step to compute max f[s] itself, the
  * step sets it to 1 (the maximum of f^{t+1} is kept in the context for the
- * next step).  Set it to 0 whenever f changes outside vl_step. */
+ * next step).  Set it to 0 whenever f changes outside vl_step.
+ * Graph capture (the kinetic closure): every launch goes to `stream`, with no
+ * memset and no host synchronisation; the context allocates its scratch on
+ * first use, so after one eager vl_step on a state with f_max_valid = 1 a
+ * vl_step captured on `stream` replays as further steps of that state (the
+ * buffers are the ones named at capture). */
 typedef struct {
     void* f[VL_MAX_SPECIES];
     void* f_tmp[VL_MAX_SPECIES];
