@@ -77,13 +77,6 @@ struct FluidArgs {
     int per;              // 1: periodic y, 0: reflecting walls
 };
 
-__device__ __forceinline__ double speed3(const double* U, int d, double m) {
-    const double n = U[0];
-    const double u = U[1 + d] / n;
-    const double p = U[4 + p_index(d, d)] - m * n * u * u;
-    return fabs(u) + sqrt(fmax(3.0 * p / (m * n), 0.0));
-}
-
 // Both face directions in one launch.  An x tile is kXTile consecutive faces
 // i+1/2 of one cell row; a y tile is kYRows consecutive face rows jh-1/2 of
 // kYCols adjacent columns.  A block stages the cell values (U and Qcal,

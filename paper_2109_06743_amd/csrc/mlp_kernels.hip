@@ -35,7 +35,6 @@ __device__ __forceinline__ unsigned short bf16_of(float f) {
     u += 0x7FFFu + ((u >> 16) & 1u);     // round to nearest, ties to even
     return (unsigned short)(u >> 16);
 }
-__device__ __forceinline__ float f32_of(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 __device__ __forceinline__ bf16x4 pack4(const f32x4& v) {
     bf16x4 r;

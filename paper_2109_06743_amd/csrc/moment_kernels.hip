@@ -320,15 +320,6 @@ __device__ __forceinline__ void pencil_moments(const double (&S)[4], double vy, 
     a[17] = vy2 * vz * S[0]; a[18] = vy * vz2 * S[0]; a[19] = vz2 * vz * S[0];
 }
 
-__device__ __forceinline__ void store20(double* dst, const double (&a)[20], double scale_lo, double scale_hi) {
-    if (threadIdx.x < 20) {
-        double v = 0;
-#pragma unroll
-        for (int k = 0; k < 20; ++k) v = (threadIdx.x == k) ? a[k] * (k < 4 ? scale_lo : scale_hi) : v;
-        dst[threadIdx.x] = v;
-    }
-}
-
 // One wave per cell (four cells per 256-thread block): lane l owns the v_x
 // pencils at transverse positions t = l + 64 j (t = iy * N + iz), so the 20
 // sums are reduced inside one wave, with no block barrier.
