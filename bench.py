@@ -740,6 +740,47 @@ def v_operator_report(steps=5):
     return out
 
 
+def graph_replay_report(nx=32, ny=16, nv=8, steps=200):
+    """A small GEM grid, where a step is bound by its ~60 kernel launches
+    rather than by HBM: eager vl_step calls against replays of one captured
+    step (a HIP graph through torch's graph API), two contexts from the same
+    state, both trajectories compared bit for bit at the end."""
+    import torch
+    from paper_2109_06743_amd import vl
+    from paper_2109_06743_amd import workloads as W
+    cfg, f, F = W.gem(nx=nx, ny=ny, nv=nv, dt=0.003, fit=True, dtype=np.float32)
+    pair = []
+    for _ in range(2):
+        ctx = vl.Context(cfg, "f32")
+        st = vl.StepState(ctx, f, vl.yee_pack(F))
+        ctx.step(st, cfg["dt"])                     # allocates the context's scratch
+        pair.append((ctx, st))
+    (ca, sa), (cb, sb) = pair
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=side):
+        cb.step(sb, cfg["dt"])                      # recorded, not run
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        ca.step(sa, cfg["dt"])
+    ev[1].record(stream)
+    ev[2].record(stream)
+    for _ in range(steps):
+        g.replay()
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    eager, graph = ev[0].elapsed_time(ev[1]) / steps, ev[2].elapsed_time(ev[3]) / steps
+    same = all(torch.equal(x, y) for x, y in zip(sa.f + sa.U + [sa.fields], sb.f + sb.U + [sb.fields]))
+    del g, pair, ca, sa, cb, sb
+    torch.cuda.empty_cache()
+    return {"workload": f"GEM 2X3V {nx}x{ny} x {nv}^3 x 2 species, moment fitting", "steps": steps,
+            "eager_ms_per_step": round(eager, 4), "graph_ms_per_step": round(graph, 4),
+            "speedup": round(eager / graph, 3), "bitwise_equal": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -756,6 +797,7 @@ def main():
     ap.add_argument("--closure-tol", type=float, nargs="+", default=[0.25, 0.5, 1.0],
                     help="judge tolerances of the learned-closure runs (one run each)")
     ap.add_argument("--no-fluid-closure", action="store_true", help="skip the fluid-only closure runs")
+    ap.add_argument("--no-graph", action="store_true", help="skip the eager-against-graph-replay comparison")
     ap.add_argument("--fluid-grid", type=int, nargs=2, default=[2048, 1024], metavar=("NX", "NY"))
     ap.add_argument("--only-fluid-closure", action="store_true",
                     help="only the fluid-only closure runs (one JSON object), e.g. for profiling")
@@ -818,6 +860,9 @@ def main():
     if args.secondary != "none" and args.secondary != args.workload:
         sec, _ = measure(args.secondary, args, fp64=not args.no_fp64, backsub=not args.no_backsub)
         out["secondary"] = sec
+    if not args.no_graph:
+        out["graph_replay"] = graph_replay_report()
+        log(f"graph replay: {out['graph_replay']}")
     mlp_geom = "gem"
     params = None
     if not args.no_mlp:
