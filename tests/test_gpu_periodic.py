@@ -100,3 +100,39 @@ def test_fluid_closure_periodic():
         ctx.sync()
         for s in range(2):
             assert rel_l2(host(fs.U[s], ref["U"][s].shape), ref["U"][s]) < 1e-12 * (k + 1), (k, s)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_step_periodic_34(dtype):
+    """The Orszag-Tang configuration itself at a small grid: periodic y with
+    34^3 velocity blocks (FP32: the block fills one CU's LDS; FP64: half its
+    v_x planes at a time), two full steps against the oracle."""
+    from gpu_util import ensure_lib
+    from paper_2109_06743_amd import vl
+    ensure_lib()
+    cfg, f, F0 = W.orszag_tang(n=4, nv=34, dtype=np.float64)
+    nx, ny = cfg["nx"], cfg["ny"]
+    F = _yee(F0, nx, ny)
+    f = [storage_round(x, dtype) for x in f]
+    moms, Us = [], []
+    for k, sp in enumerate(cfg["species"]):
+        v, dv = OS._grids(cfg, sp)
+        mm = OM.raw_moments_3v(f[k], v, dv, sp["m"])
+        moms.append(mm)
+        Us.append(mm[..., :10].copy())
+    ctx = vl.Context(cfg, dtype)
+    st = vl.StepState(ctx, f, vl.yee_pack(F), U_list=Us, mom_post_list=moms)
+    ref = dict(f=f, U=[u.copy() for u in Us], mom_post=moms, F=F)
+    for k in range(2):
+        print(f"{dtype} 34^3 periodic step {k}", flush=True)
+        ctx.step(st, cfg["dt"])
+        ref = OS.step_2x3v(ref, cfg, cfg["dt"])
+        ctx.sync()
+        for s in range(2):
+            got = host(st.f[s], ref["f"][s].shape)
+            assert rel_l2(got, ref["f"][s]) < TOL_STEP[dtype] * (k + 1), (k, s)
+            assert rel_l2(host(st.U[s], ref["U"][s].shape), ref["U"][s]) < (1e-5 if dtype == "f32" else 1e-12)
+        yee = vl.yee_unpack(host(st.fields), nx, ny)
+        for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+            np.testing.assert_allclose(yee[c], getattr(ref["F"], c), rtol=0,
+                                       atol=(1e-6 if dtype == "f32" else 1e-12), err_msg=c)
