@@ -400,3 +400,21 @@ def test_current_on_yee_averages_of_sinusoids(bc_y):
         np.testing.assert_allclose(jy[0], expect_y[0], atol=1e-14)
         np.testing.assert_allclose(jy[ny], expect_y[0], atol=1e-14)
     np.testing.assert_array_equal(jz, jc[..., 2])
+
+
+def test_field_energy_closed_forms():
+    """Field energy sum (B^2/2 + E^2/(2 c^2)) dx dy over the Yee points, the
+    wall rows of the [ny + 1] arrays at half weight: a uniform field in any
+    one component gives the continuum value (B0^2/2 or E0^2/(2 c^2)) times the
+    box area, and a sinusoid along x, whose square averages to exactly 1/2
+    over whole periods of the periodic grid, half that."""
+    nx, ny, dx, dy, c = 12, 7, 0.4, 0.3, 3.0
+    area = nx * dx * ny * dy
+    for comp in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        F = fields.Yee(nx, ny)
+        a = getattr(F, comp)
+        a[...] = 1.5
+        unit = 1.0 if comp[0] == "B" else 1.0 / c ** 2
+        assert fields.field_energy(F, c, dx, dy) == pytest.approx(0.5 * 1.5 ** 2 * unit * area, rel=1e-14), comp
+        a[...] = 1.5 * np.sin(2 * math.pi * 3 * np.arange(nx) / nx)[None, :]
+        assert fields.field_energy(F, c, dx, dy) == pytest.approx(0.25 * 1.5 ** 2 * unit * area, rel=1e-13), comp
