@@ -185,3 +185,22 @@ def test_gem_small_conservation_and_energy():
             assert (f >= 0).all()
     assert abs(drift_pfc) > 5e-3            # standard PFC heats at 16^3
     assert abs(drift_fit) < 2e-4            # moment fitting holds energy
+
+
+def test_energy_1x1v_closed_forms():
+    """Kinetic energy of f = (1 + e cos kx) M(v), M a Maxwellian of
+    temperature T sampled at the velocity cell centres, is (1/2) T L (the cos
+    term integrates to zero over whole periods, the midpoint rule on a
+    Gaussian is exact to far below 1e-12 here); with q = -1 the spectral
+    Gauss law gives E = -e sin(kx)/k exactly for one mode, so the field energy
+    is (1/2)(e/k)^2 L/2."""
+    L, nx, nv, T, e = 4 * math.pi, 32, 256, 1.3, 0.07
+    k = 2 * math.pi / L
+    cfg = dict(kind="1x1v", nx=nx, x_lo=0.0, x_hi=L, nv=nv, v_lo=-10.0, v_hi=10.0, q=-1.0, m=1.0)
+    v = -10.0 + (np.arange(nv) + 0.5) * 20.0 / nv
+    x = (np.arange(nx) + 0.5) * L / nx
+    M = np.exp(-v * v / (2 * T)) / math.sqrt(2 * math.pi * T)
+    f = (1 + e * np.cos(k * x))[:, None] * M[None, :]
+    kin, fld = step.energy_1x1v(f, cfg)
+    assert kin == pytest.approx(0.5 * T * L, rel=1e-12)
+    assert fld == pytest.approx(0.5 * (e / k) ** 2 * L / 2, rel=1e-10)
