@@ -797,7 +797,9 @@ def main():
     ap.add_argument("--closure-tol", type=float, nargs="+", default=[0.25, 0.5, 1.0],
                     help="judge tolerances of the learned-closure runs (one run each)")
     ap.add_argument("--no-fluid-closure", action="store_true", help="skip the fluid-only closure runs")
-    ap.add_argument("--no-graph", action="store_true", help="skip the eager-against-graph-replay comparison")
+    ap.add_argument("--graph", action="store_true",
+                    help="add the eager-against-graph-replay comparison (not under rocprofv3 --pmc: graph "
+                         "replays there do not return)")
     ap.add_argument("--fluid-grid", type=int, nargs=2, default=[2048, 1024], metavar=("NX", "NY"))
     ap.add_argument("--only-fluid-closure", action="store_true",
                     help="only the fluid-only closure runs (one JSON object), e.g. for profiling")
@@ -860,7 +862,7 @@ def main():
     if args.secondary != "none" and args.secondary != args.workload:
         sec, _ = measure(args.secondary, args, fp64=not args.no_fp64, backsub=not args.no_backsub)
         out["secondary"] = sec
-    if not args.no_graph:
+    if args.graph:
         out["graph_replay"] = graph_replay_report()
         log(f"graph replay: {out['graph_replay']}")
     mlp_geom = "gem"

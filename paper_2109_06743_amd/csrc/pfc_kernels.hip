@@ -1306,11 +1306,16 @@ hipError_t launch_pfc_x(const T* fin, T* fout, int rows, int nx, long long Nv, i
     return finish_max<T>(max_out, part, blocks, st);
 }
 
-// x cells per thread (FP32: 8; FP64 registers allow 4)
-template <class T> constexpr int xy_cols() { return sizeof(T) == 4 ? 8 : 4; }
+// x cells per thread: 8 in both storage types (FP64: 256 registers, one wave
+// per SIMD, no spill; against 4 columns 3292 -> 3061 us per 1024x512x12^3
+// launch and 456 -> 395 us per 256x128x16^3 launch; 12 columns: 3134 us),
+// and 16 for FP32 velocity blocks of 64 KB or more (below)
+template <class T> constexpr int xy_cols() { return 8; }
+template <class T> constexpr int xy_cols_big() { return sizeof(T) == 4 ? 16 : 8; }
 
-// Rows per segment of the fused X operator.  Waves in flight per CU: 12 in
-// FP32, 8 in FP64 (register-limited to 3 and 2 per SIMD).  A wave walks
+// Rows per segment of the fused X operator.  Waves in flight per CU the
+// model assumes: 12 in FP32 (register-limited to 3 per SIMD), 8 in FP64 (the
+// value the FP64 strip widths were measured with).  A wave walks
 // S + 2 Kmax + 4 rows for S outputs.  Beyond the one-round case in
 // xy_segment, the model cost rounds(S) * (S + 4 + 2 Kmax), with rounds the
 // number of times the waves of the launch refill the GPU, picks the segment
@@ -1359,7 +1364,7 @@ static long long xy_waves_per_seg(int nx, long long Nv, int cols) {
 long long pfc_xy_blocks(int nx, int ny, int nvx, int nvy, int nvz) {
     const long long Nv = (long long)nvx * nvy * nvz;
     const long long nseg = ny < kXyMaxSeg ? ny : kXyMaxSeg;
-    const long long w = xy_waves_per_seg(nx, Nv, 4) * nseg;    // the narrower FP64 strips
+    const long long w = xy_waves_per_seg(nx, Nv, 4) * nseg;    // 4 columns: a bound for every strip width
     return (w + 3) / 4;
 }
 
@@ -1416,19 +1421,20 @@ static hipError_t launch_pfc_xy_cols(const T* fin, T* fout, int nx, int ny, int 
     return finish_max<T>(max_out, part, blocks, st);
 }
 
-// Columns per lane: xy_cols for most blocks; twice that for velocity blocks
-// of 64 KB or more (34^3), where the wider strip's fewer halo loads per
+// Columns per lane: xy_cols for most blocks; for FP32 velocity blocks of 64 KB
+// or more (34^3) twice that, where the wider strip's fewer halo loads per
 // output pay for the registers (one wave per SIMD; the launcher keeps one
 // workgroup per CU there anyway): 11.0 -> 10.2 ms per 512x256x34^3 FP32
-// launch, 5.28 -> 4.68 ms per 256x128x34^3 FP64 launch.  At 12^3 and 16^3
-// the wider strip is 3-18 % slower.
+// launch (FP64 34^3: 8 against 4 columns, 5.28 -> 4.68 ms per 256x128x34^3
+// launch).  At 12^3 and 16^3 the wider FP32 strip is 3-18 % slower, and 4,
+// 6, 10 or 12 columns are slower than 8 at 12^3.
 template <class T>
 hipError_t launch_pfc_xy(const T* fin, T* fout, int nx, int ny, int nvx, int nvy, int nvz, double vx_lo, double dvx,
                          double tau_dx, double vy_lo, double dvy, double tau_dy, int per, const void* finf,
                          void* max_out, void* part, hipStream_t st) {
     const size_t cellb = (size_t)nvx * nvy * nvz * sizeof(T);
     if (cellb >= 65536)
-        return launch_pfc_xy_cols<T, 2 * xy_cols<T>()>(fin, fout, nx, ny, nvx, nvy, nvz, vx_lo, dvx, tau_dx, vy_lo, dvy, tau_dy,
+        return launch_pfc_xy_cols<T, xy_cols_big<T>()>(fin, fout, nx, ny, nvx, nvy, nvz, vx_lo, dvx, tau_dx, vy_lo, dvy, tau_dy,
                                              per, finf, max_out, part, st);
     return launch_pfc_xy_cols<T, xy_cols<T>()>(fin, fout, nx, ny, nvx, nvy, nvz, vx_lo, dvx, tau_dx, vy_lo, dvy,
                                                tau_dy, per, finf, max_out, part, st);
